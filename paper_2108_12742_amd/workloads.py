@@ -1,0 +1,174 @@
+"""Seeded synthetic workloads (initial data) for the ENO-AO solvers.
+
+This module is the only code shared by the HIP path and the CPU oracle: it
+draws initial states and nothing else -- none of the method's arithmetic
+(splitting, reconstruction, indicators, fluxes, time stepping) lives here.
+States are float64 numpy arrays of shape (ncomp, ny, nx) in conserved
+variables over the node grid x_i = x_lo + i*dx, dx = (x_hi - x_lo)/nx
+(ncomp = 1 advection, 3 for 1D Euler, 4 for 2D Euler); the ideal-gas
+relation E = p/(gamma-1) + rho |v|^2 / 2 (the paper's equation of state)
+converts the drawn primitive states.
+
+Workload recipes (numpy PCG64 via default_rng(seed)):
+  advection   u0 = sin(pi x) + 0.2 sin(3 pi x + phi), phi ~ U[0, 2 pi), on
+              [-1, 1] periodic (the smooth periodic advection of Section 4.1,
+              with a seeded second harmonic).
+  riemann_1d  [0, 1], transmissive; rho, p ~ LogUniform[0.1, 10],
+              u ~ U[-2, 2] on each side of x0 ~ U[0.3, 0.7]; the right density
+              carries rho_R (1 + 0.2 sin(2 pi 5 x + phi)); states whose exact
+              Riemann problem would open a vacuum are redrawn.
+  quadrants   [-1, 1]^2 periodic, four constant quadrants split at (0, 0),
+              each drawn as above (both velocity components ~ U[-2, 2]); every
+              pair of neighbouring quadrants (also across the periodic wrap) is
+              checked for vacuum and redrawn.
+  batch_1d    many riemann_1d instances with N = round(exp(U(ln 128, ln 16384))).
+  arrivals    Poisson arrival times and square sizes N ~ U{128..1024}.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+@dataclass
+class Instance:
+    """One initial-value problem: geometry + initial conserved state."""
+    equation: str            # "advection" | "euler1d" | "euler2d"
+    u0: np.ndarray           # (ncomp, ny, nx) float64
+    x_lo: float
+    x_hi: float
+    y_lo: float = -1.0
+    y_hi: float = 1.0
+    bc_x: str = "periodic"   # "periodic" | "transmissive"
+    bc_y: str = "periodic"
+    gamma: float = GAMMA
+    adv_speed: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nx(self):
+        return self.u0.shape[2]
+
+    @property
+    def ny(self):
+        return self.u0.shape[1]
+
+
+def nodes(lo: float, hi: float, n: int) -> np.ndarray:
+    dx = (hi - lo) / n
+    return lo + dx * np.arange(n, dtype=np.float64)
+
+
+def conserved_1d(rho, u, p, gamma=GAMMA):
+    rho, u, p = np.broadcast_arrays(np.asarray(rho, np.float64), np.asarray(u, np.float64),
+                                    np.asarray(p, np.float64))
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def conserved_2d(rho, u, v, p, gamma=GAMMA):
+    rho, u, v, p = np.broadcast_arrays(*(np.asarray(a, np.float64) for a in (rho, u, v, p)))
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def _loguniform(rng, lo, hi):
+    return math.exp(rng.uniform(math.log(lo), math.log(hi)))
+
+
+def _no_vacuum(rhoL, uL, pL, rhoR, uR, pR, gamma=GAMMA, margin=0.5):
+    """Pressure-positivity condition of the exact Riemann problem (with margin)."""
+    cL = math.sqrt(gamma * pL / rhoL)
+    cR = math.sqrt(gamma * pR / rhoR)
+    return 2.0 * (cL + cR) / (gamma - 1.0) - (uR - uL) > margin * (cL + cR)
+
+
+def advection(seed: int, n: int = 200, amp2: float = 0.2) -> Instance:
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 2.0 * math.pi)
+    x = nodes(-1.0, 1.0, n)
+    u0 = np.sin(np.pi * x) + amp2 * np.sin(3.0 * np.pi * x + phi)
+    return Instance("advection", u0.reshape(1, 1, n).copy(), -1.0, 1.0, meta={"phi": phi, "seed": seed})
+
+
+def _draw_state(rng):
+    return (_loguniform(rng, 0.1, 10.0), rng.uniform(-2.0, 2.0), _loguniform(rng, 0.1, 10.0))
+
+
+def riemann_1d(seed: int, n: int = 2000, amp: float = 0.2, wavenumber: float = 5.0) -> Instance:
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(0.3, 0.7)
+    phi = rng.uniform(0.0, 2.0 * math.pi)
+    while True:
+        rL, uL, pL = _draw_state(rng)
+        rR, uR, pR = _draw_state(rng)
+        # the perturbed right density ranges over rho_R (1 +/- amp)
+        if _no_vacuum(rL, uL, pL, rR * (1.0 + amp), uR, pR) and _no_vacuum(rL, uL, pL, rR * (1.0 - amp), uR, pR):
+            break
+    x = nodes(0.0, 1.0, n)
+    left = x < x0
+    rho = np.where(left, rL, rR * (1.0 + amp * np.sin(2.0 * math.pi * wavenumber * x + phi)))
+    u = np.where(left, uL, uR)
+    p = np.where(left, pL, pR)
+    u0 = conserved_1d(rho, u, p).reshape(3, 1, n)
+    return Instance("euler1d", np.ascontiguousarray(u0), 0.0, 1.0, bc_x="transmissive",
+                    meta={"seed": seed, "x0": x0, "left": (rL, uL, pL), "right": (rR, uR, pR), "phi": phi})
+
+
+def lax_tube(n: int = 200) -> Instance:
+    """Lax shock tube of Section 4.2 on [0, 2]: (0.445, 0.698, 3.528) | (0.5, 0, 0.571)."""
+    x = nodes(0.0, 2.0, n)
+    left = x < 1.0
+    rho = np.where(left, 0.445, 0.5)
+    u = np.where(left, 0.698, 0.0)
+    p = np.where(left, 3.528, 0.571)
+    return Instance("euler1d", np.ascontiguousarray(conserved_1d(rho, u, p).reshape(3, 1, n)),
+                    0.0, 2.0, bc_x="transmissive", meta={"x0": 1.0})
+
+
+def quadrants(seed: int, n: int = 2048, ny: int | None = None) -> Instance:
+    ny = n if ny is None else ny
+    rng = np.random.default_rng(seed)
+    while True:
+        # quadrant order: (x<0,y<0), (x<0,y>=0), (x>=0,y>=0), (x>=0,y<0)
+        q = [(_loguniform(rng, 0.1, 10.0), rng.uniform(-2, 2), rng.uniform(-2, 2), _loguniform(rng, 0.1, 10.0))
+             for _ in range(4)]
+        ok = True
+        # x-neighbours (normal velocity u), both orientations for the periodic wrap
+        for a, b in ((0, 3), (1, 2)):
+            for l, r in ((a, b), (b, a)):
+                ok &= _no_vacuum(q[l][0], q[l][1], q[l][3], q[r][0], q[r][1], q[r][3])
+        # y-neighbours (normal velocity v)
+        for a, b in ((0, 1), (3, 2)):
+            for l, r in ((a, b), (b, a)):
+                ok &= _no_vacuum(q[l][0], q[l][2], q[l][3], q[r][0], q[r][2], q[r][3])
+        if ok:
+            break
+    x = nodes(-1.0, 1.0, n)
+    y = nodes(-1.0, 1.0, ny)
+    X, Y = np.meshgrid(x, y)  # (ny, nx)
+    idx = np.where(X < 0, np.where(Y < 0, 0, 1), np.where(Y >= 0, 2, 3))
+    prim = np.array(q)  # (4, 4): rho, u, v, p
+    rho, u, v, p = (prim[idx, k] for k in range(4))
+    u0 = conserved_2d(rho, u, v, p)
+    return Instance("euler2d", np.ascontiguousarray(u0), -1.0, 1.0, -1.0, 1.0,
+                    meta={"seed": seed, "quadrants": q})
+
+
+def batch_1d(seed: int, count: int = 512, n_lo: int = 128, n_hi: int = 16384) -> list[Instance]:
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=count))).astype(int)
+    seeds = rng.integers(0, 2**31 - 1, size=count)
+    return [riemann_1d(int(s), int(n)) for s, n in zip(seeds, sizes)]
+
+
+def arrivals(seed: int, count: int, rate: float, n_lo: int = 128, n_hi: int = 1024):
+    """(arrival times [s], sizes N, data seeds) of a Poisson request stream."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    sizes = rng.integers(n_lo, n_hi + 1, size=count)
+    seeds = rng.integers(0, 2**31 - 1, size=count)
+    return t, sizes, seeds

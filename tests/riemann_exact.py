@@ -1,0 +1,96 @@
+"""Exact solution of the 1D Riemann problem for an ideal gas (test helper).
+
+Restated from the standard textbook construction (Toro, "Riemann Solvers and
+Numerical Methods for Fluid Dynamics", ch. 4): the star pressure solves
+f_L(p) + f_R(p) + (u_R - u_L) = 0 with the shock / rarefaction branches of f_K,
+found by Newton iteration; the solution is then sampled along x/t.
+"""
+import math
+
+import numpy as np
+
+
+def _fk(p, rho, pk, ck, g):
+    if p > pk:  # shock
+        A = 2.0 / ((g + 1.0) * rho)
+        B = (g - 1.0) / (g + 1.0) * pk
+        s = math.sqrt(A / (p + B))
+        return (p - pk) * s, s * (1.0 - 0.5 * (p - pk) / (B + p))
+    # rarefaction
+    e = (g - 1.0) / (2.0 * g)
+    return 2.0 * ck / (g - 1.0) * ((p / pk) ** e - 1.0), (1.0 / (rho * ck)) * (p / pk) ** (-(g + 1.0) / (2.0 * g))
+
+
+def star_state(left, right, g=1.4):
+    rl, ul, pl = left
+    rr, ur, pr = right
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    if 2.0 * (cl + cr) / (g - 1.0) <= ur - ul:
+        raise ValueError("vacuum")
+    p = max(1e-8, 0.5 * (pl + pr) - 0.125 * (ur - ul) * (rl + rr) * (cl + cr))
+    for _ in range(100):
+        fl, dl = _fk(p, rl, pl, cl, g)
+        fr, dr = _fk(p, rr, pr, cr, g)
+        dp = (fl + fr + ur - ul) / (dl + dr)
+        pn = max(1e-10, p - dp)
+        if abs(pn - p) <= 1e-14 * (pn + p):
+            p = pn
+            break
+        p = pn
+    fl, _ = _fk(p, rl, pl, cl, g)
+    fr, _ = _fk(p, rr, pr, cr, g)
+    return p, 0.5 * (ul + ur) + 0.5 * (fr - fl)
+
+
+def sample(left, right, x, x0, t, g=1.4):
+    """(rho, u, p) at positions x, time t, initial discontinuity at x0."""
+    rl, ul, pl = left
+    rr, ur, pr = right
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    ps, us = star_state(left, right, g)
+    out = np.zeros((3, len(x)))
+    for i, xi in enumerate(np.asarray(x, float)):
+        s = (xi - x0) / t
+        if s <= us:  # left of contact
+            if ps > pl:  # left shock
+                sl = ul - cl * math.sqrt((g + 1) / (2 * g) * ps / pl + (g - 1) / (2 * g))
+                if s <= sl:
+                    out[:, i] = (rl, ul, pl)
+                else:
+                    r = rl * (ps / pl + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * ps / pl + 1)
+                    out[:, i] = (r, us, ps)
+            else:  # left rarefaction
+                shl = ul - cl
+                csl = cl * (ps / pl) ** ((g - 1) / (2 * g))
+                stl = us - csl
+                if s <= shl:
+                    out[:, i] = (rl, ul, pl)
+                elif s >= stl:
+                    out[:, i] = (rl * (ps / pl) ** (1 / g), us, ps)
+                else:
+                    u = 2 / (g + 1) * (cl + (g - 1) / 2 * ul + s)
+                    c = 2 / (g + 1) * (cl + (g - 1) / 2 * (ul - s))
+                    r = rl * (c / cl) ** (2 / (g - 1))
+                    out[:, i] = (r, u, pl * (c / cl) ** (2 * g / (g - 1)))
+        else:  # right of contact
+            if ps > pr:  # right shock
+                sr = ur + cr * math.sqrt((g + 1) / (2 * g) * ps / pr + (g - 1) / (2 * g))
+                if s >= sr:
+                    out[:, i] = (rr, ur, pr)
+                else:
+                    r = rr * (ps / pr + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * ps / pr + 1)
+                    out[:, i] = (r, us, ps)
+            else:  # right rarefaction
+                shr = ur + cr
+                csr = cr * (ps / pr) ** ((g - 1) / (2 * g))
+                str_ = us + csr
+                if s >= shr:
+                    out[:, i] = (rr, ur, pr)
+                elif s <= str_:
+                    out[:, i] = (rr * (ps / pr) ** (1 / g), us, ps)
+                else:
+                    u = 2 / (g + 1) * (-cr + (g - 1) / 2 * ur + s)
+                    c = 2 / (g + 1) * (cr - (g - 1) / 2 * (ur - s))
+                    r = rr * (c / cr) ** (2 / (g - 1))
+                    out[:, i] = (r, u, pr * (c / cr) ** (2 * g / (g - 1)))
+    return out
