@@ -28,7 +28,7 @@ int ref_euler_flux(int dim, double gamma, const double *U, double *F)
     if (!(rho > 0.0)) return REF_ENONPHYSICAL;
     if (dim == 1) {
         const double u = U[1] / rho;
-        const double p = (gamma - 1.0) * (U[2] - 0.5 * rho * u * u);
+        const double p = (gamma - 1.0) * (U[2] - 0.5 * rho * (u * u));
         if (!(p > 0.0)) return REF_ENONPHYSICAL;
         F[0] = U[1];
         F[1] = U[1] * u + p;
@@ -58,7 +58,7 @@ static int primitives(int dim, double gamma, const double *U, double *u, double 
     if (dim == 1) {
         *u = U[1] / rho;
         *v = 0.0;
-        p = (gamma - 1.0) * (U[2] - 0.5 * rho * (*u) * (*u));
+        p = (gamma - 1.0) * (U[2] - 0.5 * rho * ((*u) * (*u)));
         *H = (U[2] + p) / rho;
     } else {
         *u = U[1] / rho;

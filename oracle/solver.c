@@ -78,7 +78,7 @@ static int node_speed(int eq, double gamma, const double *U, double *un, double 
     if (eq == REF_EULER1D) {
         *un = U[1] / rho;
         *ut = 0.0;
-        p = (gamma - 1.0) * (U[2] - 0.5 * rho * (*un) * (*un));
+        p = (gamma - 1.0) * (U[2] - 0.5 * rho * ((*un) * (*un)));
     } else {
         *un = U[1] / rho;
         *ut = U[2] / rho;

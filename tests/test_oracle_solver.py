@@ -203,6 +203,25 @@ def test_2d_reduces_to_1d():
     assert np.abs(L2[2]).max() == 0.0
 
 
+def test_2d_reduces_to_1d_along_y_rectangular():
+    """P16 along y on a non-square grid (dx != dy): x-invariant data with u = 0 gives a
+    vanishing x-part and a y-part equal to the 1D operator on the column (momentum rho v)."""
+    ny, nx = 36, 7
+    inst = W.riemann_1d(9, ny)
+    r, m, E = inst.u0[:, 0, :]
+    u2 = np.stack([np.tile(r[:, None], (1, nx)), np.zeros((ny, nx)), np.tile(m[:, None], (1, nx)),
+                   np.tile(E[:, None], (1, nx))])
+    p2 = O.Problem(O.EULER2D, nx=nx, ny=ny, x_lo=-3.0, x_hi=2.0, y_lo=0.0, y_hi=1.0,
+                   bc_x=O.PERIODIC, bc_y=O.TRANSMISSIVE)
+    L2 = O.rhs(p2, u2)
+    L1 = O.rhs(_euler1d_problem(ny, bc=O.TRANSMISSIVE), inst.u0)
+    for col in range(nx):
+        np.testing.assert_array_equal(L2[0, :, col], L1[0, 0])
+        np.testing.assert_array_equal(L2[2, :, col], L1[1, 0])
+        np.testing.assert_array_equal(L2[3, :, col], L1[2, 0])
+    assert np.abs(L2[1]).max() == 0.0
+
+
 def test_2d_transpose_symmetry():
     """P16: exchanging x and y (and the two momentum components) commutes with L."""
     inst = W.quadrants(6, 20)
