@@ -1,0 +1,125 @@
+#!/usr/bin/env python3
+"""Throughput of the ENO-AO hot path on one MI355X.
+
+Default workload: 2D Euler, 2048 x 2048 nodes, periodic, four seeded quadrant
+states (rho, p ~ LogUniform[0.1, 10], u, v ~ U[-2, 2]), fifth-order ENO-AO with
+Roe characteristic decomposition, SSP-RK3 with the device-side CFL step
+(CFL 0.3); K timed steps after W warm-up steps, inputs resident in HBM.
+
+Prints one JSON line: cell-updates/s of the whole job, the roofline of the
+dominant kernel (HIP events on the stream the kernels run on), and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "cell-updates/s + % HBM/FP64 roofline; batched vs plain; p50/p99 latency"
+KERNEL_NAMES = {  # profile kind -> kernel symbol as rocprofv3 prints it (order 5, no selection record)
+    "sweep_x_s1": "enoao::sweep_x<2, 5, 1, false>", "sweep_x_s2": "enoao::sweep_x<2, 5, 2, false>",
+    "sweep_x_s3": "enoao::sweep_x<2, 5, 3, false>", "sweep_y_s1": "enoao::sweep_y<5, 1, false>",
+    "sweep_y_s2": "enoao::sweep_y<5, 2, false>", "sweep_y_s3": "enoao::sweep_y<5, 3, false>",
+}
+
+
+def cpu_baseline(n_sample=512, steps=2):
+    """The oracle (single-threaded C, FP64) on a bounded sample of the workload:
+    `steps` SSP-RK3 steps of the same seeded quadrant problem at n_sample^2 nodes."""
+    from oracle import oracle as O
+    from paper_2108_12742_amd import workloads as W
+    inst = W.quadrants(0, n_sample)
+    p = O.Problem(O.EULER2D, nx=n_sample, ny=n_sample, order=5)
+    u = inst.u0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dt = O.cfl_dt(p, u, 0.3)
+        u = O.step(p, u, dt)
+    el = time.perf_counter() - t0
+    return {"value": n_sample * n_sample * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of the 2D Euler quadrant workload (seed 0) at {n_sample}x{n_sample}, "
+                      f"{el:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=2048, help="nodes per direction")
+    ap.add_argument("--order", type=int, default=5, choices=(5, 7))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
+              "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import roofline as R
+    from paper_2108_12742_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    n, K, Wu = args.n, args.steps, args.warmup
+    inst = W.quadrants(0, n)
+    ep = E.problem_from_instance(inst, order=args.order)
+    plan = E.enoao_plan_create(ep)
+    u0 = torch.from_numpy(inst.u0).cuda()
+    u = u0.clone()
+    if Wu > 0:
+        E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=Wu)
+    u.copy_(u0)
+    torch.cuda.synchronize()
+
+    E.enoao_profile(plan, True)
+    t0 = time.perf_counter()
+    _, steps = E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=K)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = E.enoao_profile_read(plan)
+    E.enoao_profile(plan, False)
+    assert steps == K, (steps, K)
+    E.enoao_plan_check(plan)
+
+    cells = n * n
+    value = cells * K / el
+    kernels = {}
+    best = None
+    for kind, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        entry = {"mean_ms": round(ms, 4), "launches": cnt}
+        if kind.startswith("sweep"):
+            kern = kind[6]
+            stage = int(kind[-1])
+            fl = cells * R.sweep_flops("euler2d", args.order, kern, stage)
+            by = cells * R.sweep_bytes("euler2d", kern, stage)
+            entry["roofline"] = R.roofline_entry(fl, by, ms * 1e-3)
+            entry["symbol"] = KERNEL_NAMES.get(kind) if args.order == 5 else None
+            if best is None or ms * cnt > best[1]:
+                best = (kind, ms * cnt)
+        kernels[kind] = entry
+    roof = dict(kernels[best[0]]["roofline"])
+    roof["kernel"] = kernels[best[0]].get("symbol") or best[0]
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": Wu,
+        "ms_per_step": el * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"euler2d-quadrants-{n}x{n}-ao{args.order}", "nx": n, "ny": n, "order": args.order,
+                   "bc": "periodic", "cfl": 0.3, "seed": 0, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(),
+        "kernels": kernels,
+        "flops_per_cell_update": R.cell_update_flops("euler2d", args.order),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * enoao.h -- C ABI of the MI355X (gfx950) implementation of the ENO-AO
+ * finite-difference method of H. Shen, "A class of ENO schemes with adaptive
+ * order for solving hyperbolic conservation laws" (arXiv 2108.12742).
+ *
+ * Everything below runs on the GPU: the library launches hand-written HIP
+ * kernels on the caller's stream and never computes a step of the method on
+ * the host.
+ *
+ * ----------------------------------------------------------------------------
+ * Problem (Section 2, Eq. 1DHCL_Eq and 1DWENOFD; Section 4 for the Euler
+ * systems): u_t + f(u)_x [+ g(u)_y] = 0 on a uniform node grid
+ *   x_i = x_lo + i*dx, i = 0..nx-1, dx = (x_hi - x_lo)/nx   (same in y),
+ * semi-discretised as du_i/dt = -(fhat_{i+1/2} - fhat_{i-1/2})/dx [- same in y]
+ * and advanced with the third-order TVD Runge-Kutta method.
+ *   ENOAO_ADVECTION  f = a u (1 component)
+ *   ENOAO_EULER1D    U = [rho, rho u, rho e]           (3 components)
+ *   ENOAO_EULER2D    U = [rho, rho u, rho v, rho e]    (4 components)
+ * with the ideal-gas law p = (gamma-1)(rho e - rho |v|^2/2).
+ *
+ * The numerical flux at every face (Section 3): global Lax-Friedrichs splitting
+ * f^(+/-) = (f +/- alpha u)/2 with alpha = max|f'(u)| over the grid (for the
+ * Euler systems per characteristic field, after projection on the left
+ * eigenvectors of the face's Roe state); the candidate stencils from first
+ * order to the designed order (5 or 7); the minimum-discrepancy smoothness
+ * indicators IS = min(delta_L, delta_R) of Eq. New_Smoothness_Indicator; and
+ * the reconstruction principle: among indicators <= delta the highest-priority
+ * stencil, otherwise the smallest indicator (ties to the higher priority).
+ *
+ * ----------------------------------------------------------------------------
+ * Data layout and ownership
+ *   A state is a caller-owned DEVICE pointer to FP64 values, contiguous SoA
+ *   [ncomp][ny][nx] (ny = 1 in 1D), grid nodes only (no ghost cells: periodic
+ *   or transmissive boundaries are applied inside the kernels).  The library
+ *   never frees or reallocates caller memory.  A plan owns its workspace
+ *   (stage buffers, per-field maxima, time-loop control, optional selection
+ *   record) and any HIP graphs it captured; enoao_plan_destroy releases them.
+ *
+ * Streams
+ *   Every call takes a hipStream_t passed as void* (NULL = the legacy default
+ *   stream).  Calls enqueue work and return without synchronising, except
+ *   enoao_solve, enoao_plan_check and enoao_get_selection, which wait on the
+ *   stream they are given.  Calls on one plan must not overlap in time.
+ *
+ * Errors
+ *   Every function returns an enoao_status; nothing throws across the ABI.
+ *   ENOAO_EINVAL: bad argument (NULL pointer, size, unsupported combination).
+ *   ENOAO_ENOMEM: device allocation failed.  ENOAO_EDEVICE: a HIP call failed.
+ *   ENOAO_ENONPHYSICAL: a state with rho <= 0, p <= 0 or a NaN was met by the
+ *   device-side checks; asynchronous calls report it at the next synchronising
+ *   call on the plan (enoao_solve or enoao_plan_check).
+ */
+#ifndef ENOAO_H
+#define ENOAO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum enoao_status {
+    ENOAO_OK = 0,
+    ENOAO_EINVAL = 1,
+    ENOAO_ENOMEM = 2,
+    ENOAO_EDEVICE = 3,
+    ENOAO_EUNSUPPORTED = 4,
+    ENOAO_ENONPHYSICAL = 5
+} enoao_status;
+
+enum { ENOAO_ADVECTION = 0, ENOAO_EULER1D = 1, ENOAO_EULER2D = 2 };
+enum { ENOAO_BC_PERIODIC = 0, ENOAO_BC_TRANSMISSIVE = 1 };
+/* flags */
+enum { ENOAO_F_RECORD_SELECTION = 1u };
+
+/* Caller-filled description of one problem; copied by the create calls. */
+typedef struct enoao_problem {
+    uint32_t struct_size; /* sizeof(enoao_problem): ABI version check                  */
+    int32_t equation;     /* ENOAO_ADVECTION | ENOAO_EULER1D | ENOAO_EULER2D            */
+    int32_t order;        /* designed order: 5 or 7 (Section 3.2 candidate lists)       */
+    int32_t nx;           /* nodes along x, >= 1                                        */
+    int32_t ny;           /* nodes along y, 1 for the 1D equations                      */
+    int32_t reserved0;    /* must be 0                                                  */
+    double x_lo, x_hi;    /* dx = (x_hi - x_lo)/nx                                      */
+    double y_lo, y_hi;    /* dy = (y_hi - y_lo)/ny (2D only)                            */
+    int32_t bc_x, bc_y;   /* ENOAO_BC_PERIODIC | ENOAO_BC_TRANSMISSIVE (zero gradient)  */
+    double gamma;         /* ratio of specific heats (Euler), > 1                       */
+    double adv_speed;     /* a of the advection equation, != 0                          */
+    double delta;         /* selection threshold, >= 0 (the paper uses 1e-5)            */
+    uint32_t flags;       /* ENOAO_F_RECORD_SELECTION: keep the stencil choices of the  */
+                          /* last evaluation of L for enoao_get_selection               */
+    uint32_t reserved1;   /* must be 0                                                  */
+} enoao_problem;
+
+typedef struct enoao_plan enoao_plan;
+typedef struct enoao_batch enoao_batch;
+
+/* Validates *prob, allocates the plan's device workspace on the current HIP
+ * device and returns the plan in *out.  stream: used for initialisation. */
+enoao_status enoao_plan_create(const enoao_problem *prob, void *stream, enoao_plan **out);
+enoao_status enoao_plan_destroy(enoao_plan *plan);
+
+/* Device bytes a plan for *prob allocates (0 on an invalid problem). */
+size_t enoao_workspace_bytes(const enoao_problem *prob);
+
+/* L = L(u), Eq. 1DWENOFD (plus the y-part in 2D), with alpha taken from u.
+ * u, L: device arrays of ncomp*ny*nx doubles; u is read only; they must not
+ * overlap. */
+enoao_status enoao_rhs(enoao_plan *plan, const double *u, double *L, void *stream);
+
+/* One third-order TVD Runge-Kutta step of size dt > 0, in place on u. */
+enoao_status enoao_step(enoao_plan *plan, double *u, double dt, void *stream);
+
+/* Advance u in place from t = 0 towards t_final, at most max_steps steps.
+ * dt_fixed > 0: constant step dt_fixed; otherwise the CFL step
+ * (advection cfl*dx/|a|; 1D Euler cfl*dx/max(|u|+c); 2D Euler
+ * cfl/max((|u|+c)/dx + (|v|+c)/dy)), computed on the device from the state at
+ * the start of each step.  The step that would reach t_final
+ * (dt >= (t_final - t)(1 - 1e-10)) is shortened to land on it exactly.
+ * Synchronises stream; *t_out / *steps_out (may be NULL) receive the final
+ * time and the number of steps taken. */
+enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl, double dt_fixed,
+                         int64_t max_steps, double *t_out, int64_t *steps_out, void *stream);
+
+/* Synchronises stream and returns ENOAO_ENONPHYSICAL if any device-side check
+ * of the plan failed since the last synchronising call (then clears it). */
+enoao_status enoao_plan_check(enoao_plan *plan, void *stream);
+
+/* Number of selection records of a plan (0 without ENOAO_F_RECORD_SELECTION):
+ *   x block [ncomp][2 sides: plus, minus][ny][nx+1] (face i between nodes i-1 and i),
+ *   y block [ncomp][2][ny+1][nx] (2D only, after the x block);
+ * each record is the chosen candidate 0..K-1 (K = 6 for order 5, 9 for order 7)
+ * numbered S_j^j, S_j^{j+1}, S_{j-1}^{j+1}, S_{j-2}^{j+1}, S_{j-1}^{j+2},
+ * S_{j-2}^{j+2}[, S_{j-3}^{j+2}, S_{j-2}^{j+3}, S_{j-3}^{j+3}], i.e. in
+ * increasing priority; entries are in characteristic fields for Euler. */
+size_t enoao_selection_size(const enoao_plan *plan);
+
+/* Copies the selection records of the last evaluation of L (enoao_rhs, or the
+ * third stage of the last step) to host memory host_out[n]; n must equal
+ * enoao_selection_size.  Synchronises stream. */
+enoao_status enoao_get_selection(enoao_plan *plan, uint8_t *host_out, size_t n, void *stream);
+
+/* ---- batches: many independent problems advanced together ----------------
+ * One batch holds n problems of one equation and order (any sizes, geometry,
+ * boundary conditions), each with its own CFL time step, time and step
+ * count.  Every Runge-Kutta stage of every member is one persistent kernel
+ * launch over the flattened list of line tiles of all members; a step is
+ * captured once into a HIP graph and replayed. */
+enoao_status enoao_batch_create(const enoao_problem *probs, int32_t n, void *stream, enoao_batch **out);
+enoao_status enoao_batch_destroy(enoao_batch *batch);
+
+/* Advance every member i (state u[i], a device pointer, in place) by nsteps
+ * CFL steps of its own size (cfl > 0), stopping a member early once it
+ * reaches t_final[i] (t_final may be NULL: no end time).  Member times and
+ * step counts persist across calls until enoao_batch_reset.  Synchronises
+ * stream only when status is requested via enoao_batch_query. */
+enoao_status enoao_batch_step(enoao_batch *batch, double *const *u, int32_t nsteps, double cfl,
+                              const double *t_final, void *stream);
+enoao_status enoao_batch_reset(enoao_batch *batch, void *stream);
+
+/* Synchronises stream; copies each member's time and step count (either
+ * pointer may be NULL) and returns ENOAO_ENONPHYSICAL if a member failed a
+ * device-side check (member_status[i] != 0 marks it; may be NULL). */
+enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, int32_t *member_status,
+                               void *stream);
+
+/* ---- per-kernel timing -------------------------------------------------
+ * enoao_profile(plan, 1): subsequent enoao_step / enoao_solve calls launch
+ * eagerly (no graph replay) and record a hipEvent pair around every kernel on
+ * the stream the kernel runs on.  enoao_profile_read synchronises stream and
+ * returns, per kernel kind, the mean duration in ms and the number of
+ * launches since profiling was enabled.  Kinds (n_kinds <= 8):
+ *   0..2 x-sweep of stage 1..3, 3..5 y-sweep of stage 1..3 (2D only),
+ *   6 time-step control, 7 initial per-field maxima. */
+enoao_status enoao_profile(enoao_plan *plan, int32_t enable);
+enoao_status enoao_profile_read(enoao_plan *plan, double *avg_ms, int64_t *count, int32_t n_kinds, void *stream);
+enoao_status enoao_batch_profile(enoao_batch *batch, int32_t enable);
+enoao_status enoao_batch_profile_read(enoao_batch *batch, double *avg_ms, int64_t *count, int32_t n_kinds,
+                                      void *stream);
+
+/* Tuning knobs of the persistent launches (0 = library default). */
+enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved);
+
+const char *enoao_status_string(enoao_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,699 @@
+// enoao_api.hip -- C ABI (include/enoao.h): plans, batches and the device-side
+// time loop.  Host code only orders kernel launches; every arithmetic step of
+// the method runs in the kernels of enoao_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/enoao.h"
+#include "enoao_common.hpp"
+#include "enoao_kernels.hpp"
+
+using namespace enoao;
+
+namespace {
+
+int g_wg_per_cu = 0;  // 0: occupancy of each kernel
+
+// kernel kinds of the per-kernel timing (enoao_profile_read order)
+enum { PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_KINDS };
+
+int ncomp_of(int eq) { return eq == ADVECTION ? 1 : eq == EULER1D ? 3 : eq == EULER2D ? 4 : 0; }
+
+enoao_status check_problem(const enoao_problem *p)
+{
+    if (!p || p->struct_size != sizeof(enoao_problem)) return ENOAO_EINVAL;
+    if (!ncomp_of(p->equation)) return ENOAO_EINVAL;
+    if (p->order != 5 && p->order != 7) return ENOAO_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->reserved0 != 0 || p->reserved1 != 0) return ENOAO_EINVAL;
+    if (p->equation != EULER2D && p->ny != 1) return ENOAO_EINVAL;
+    if (!(p->x_hi > p->x_lo)) return ENOAO_EINVAL;
+    if (p->equation == EULER2D && !(p->y_hi > p->y_lo)) return ENOAO_EINVAL;
+    if (p->bc_x != BC_PERIODIC && p->bc_x != BC_TRANSMISSIVE) return ENOAO_EINVAL;
+    if (p->equation == EULER2D && p->bc_y != BC_PERIODIC && p->bc_y != BC_TRANSMISSIVE) return ENOAO_EINVAL;
+    if (p->equation != ADVECTION && !(p->gamma > 1.0)) return ENOAO_EINVAL;
+    if (p->equation == ADVECTION && !(std::isfinite(p->adv_speed) && p->adv_speed != 0.0)) return ENOAO_EINVAL;
+    if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return ENOAO_EINVAL;
+    if ((long long)p->nx * p->ny > (1ll << 31)) return ENOAO_EINVAL;
+    return ENOAO_OK;
+}
+
+size_t selection_count(const enoao_problem *p)
+{
+    const size_t nc = ncomp_of(p->equation);
+    size_t n = nc * 2 * (size_t)p->ny * (p->nx + 1);
+    if (p->equation == EULER2D) n += nc * 2 * (size_t)(p->ny + 1) * p->nx;
+    return n;
+}
+
+// device bytes of one member: w1, w2 (+ Lx for 2D) and the selection record
+size_t member_bytes(const enoao_problem *p)
+{
+    const size_t n = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
+    size_t b = 2 * n * sizeof(double);
+    if (p->equation == EULER2D) b += n * sizeof(double);
+    if (p->flags & ENOAO_F_RECORD_SELECTION) b += (selection_count(p) + 255) / 256 * 256;
+    return b;
+}
+
+size_t member_fixed_bytes() { return sizeof(Inst) + sizeof(Ctrl) + AMAX_SLOTS * AMAX_VALS * 8 + 256; }
+
+#define HIP_TRY(x)                                    \
+    do {                                              \
+        if ((x) != hipSuccess) return ENOAO_EDEVICE;  \
+    } while (0)
+
+}  // namespace
+
+// A runtime = a batch of members sharing equation and order (a plan is one member).
+struct Runtime {
+    int eq = 0, order = 5, nc = 1, n = 0;
+    double gamma = 1.4, delta = 1e-5;
+    bool rec = false;
+    int device = 0, cus = 256;
+    std::vector<enoao_problem> probs;
+    std::vector<Inst> h_inst;
+    BatchHdr h_hdr{};
+    // device memory
+    void *d_block = nullptr;   // one allocation for everything
+    BatchHdr *d_hdr = nullptr;
+    Inst *d_inst = nullptr;
+    Ctrl *d_ctrl = nullptr;
+    unsigned long long *d_amax = nullptr;
+    Ctrl *h_ctrl = nullptr;    // pinned mirror
+    // captured step graph (K steps of control + stages)
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    hipStream_t cap = nullptr;
+    int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
+    // optional per-kernel timing: hipEvents recorded around every launch, on the
+    // stream the kernel is launched on (eager launches, no graph)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pairs;  // (kind, first event index)
+    double prof_ms[PROF_KINDS] = {};
+    long long prof_n[PROF_KINDS] = {};
+
+    hipError_t prof_begin(int kind, hipStream_t s, int &slot)
+    {
+        slot = -1;
+        if (!profiling) return hipSuccess;
+        const size_t need = ev_pairs.size() * 2 + 2;
+        while (ev_pool.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+            ev_pool.push_back(e);
+        }
+        slot = (int)ev_pairs.size() * 2;
+        ev_pairs.push_back({kind, slot});
+        return hipEventRecord(ev_pool[slot], s);
+    }
+    hipError_t prof_end(int slot, hipStream_t s)
+    {
+        if (slot < 0) return hipSuccess;
+        return hipEventRecord(ev_pool[slot + 1], s);
+    }
+    // after a synchronisation: fold the recorded pairs into the per-kind totals
+    void prof_collect()
+    {
+        for (auto &pr : ev_pairs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev_pool[pr.second], ev_pool[pr.second + 1]) == hipSuccess) {
+                prof_ms[pr.first] += ms;
+                prof_n[pr.first] += 1;
+            }
+        }
+        ev_pairs.clear();
+    }
+
+    KParams params(int r_in, int r_out, int r_zero) const
+    {
+        KParams p{};
+        p.hdr = d_hdr;
+        p.inst = d_inst;
+        p.gamma = gamma;
+        p.gm1 = gamma - 1.0;
+        p.delta = delta;
+        p.r_in = r_in;
+        p.r_out = r_out;
+        p.r_zero = r_zero;
+        return p;
+    }
+
+    int grid_for(long long tiles, int occ) const
+    {
+        const int per_cu = g_wg_per_cu > 0 ? g_wg_per_cu : occ;
+        const long long g = std::min<long long>(tiles, (long long)cus * per_cu);
+        return (int)std::max<long long>(g, 1);
+    }
+
+    enoao_status init(const enoao_problem *ps, int count, hipStream_t stream)
+    {
+        if (count < 1) return ENOAO_EINVAL;
+        for (int i = 0; i < count; ++i) {
+            if (check_problem(&ps[i])) return ENOAO_EINVAL;
+            if (ps[i].equation != ps[0].equation || ps[i].order != ps[0].order) return ENOAO_EINVAL;
+            if (ps[i].gamma != ps[0].gamma || ps[i].delta != ps[0].delta) return ENOAO_EINVAL;
+        }
+        eq = ps[0].equation;
+        order = ps[0].order;
+        nc = ncomp_of(eq);
+        n = count;
+        gamma = ps[0].gamma;
+        delta = ps[0].delta;
+        rec = (ps[0].flags & ENOAO_F_RECORD_SELECTION) != 0;
+        probs.assign(ps, ps + count);
+        HIP_TRY(hipGetDevice(&device));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+
+        // layout of the single device allocation
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) / 256 * 256;
+            return o;
+        };
+        const size_t o_hdr = take(sizeof(BatchHdr));
+        const size_t o_inst = take(sizeof(Inst) * count);
+        const size_t o_ctrl = take(sizeof(Ctrl) * count);
+        const size_t o_amax = take(8ull * AMAX_SLOTS * AMAX_VALS * count);
+        std::vector<size_t> o_mem(count);
+        for (int i = 0; i < count; ++i) o_mem[i] = take(member_bytes(&ps[i]));
+        if (hipMalloc(&d_block, off) != hipSuccess) {
+            d_block = nullptr;
+            return ENOAO_ENOMEM;
+        }
+        char *base = (char *)d_block;
+        d_hdr = (BatchHdr *)(base + o_hdr);
+        d_inst = (Inst *)(base + o_inst);
+        d_ctrl = (Ctrl *)(base + o_ctrl);
+        d_amax = (unsigned long long *)(base + o_amax);
+        if (hipHostMalloc((void **)&h_ctrl, sizeof(Ctrl) * count, hipHostMallocDefault) != hipSuccess) {
+            h_ctrl = nullptr;
+            return ENOAO_ENOMEM;
+        }
+
+        h_inst.resize(count);
+        long long xt = 0, yt = 0;
+        for (int i = 0; i < count; ++i) {
+            const enoao_problem &p = ps[i];
+            Inst &I = h_inst[i];
+            std::memset(&I, 0, sizeof(I));
+            const size_t cells = (size_t)nc * p.nx * p.ny;
+            double *m = (double *)(base + o_mem[i]);
+            I.u = nullptr;
+            I.w1 = m;
+            I.w2 = m + cells;
+            I.lx = eq == EULER2D ? m + 2 * cells : nullptr;
+            I.sel = rec ? (uint8_t *)(m + (eq == EULER2D ? 3 : 2) * cells) : nullptr;
+            I.amax = d_amax + (size_t)i * AMAX_SLOTS * AMAX_VALS;
+            I.ctrl = d_ctrl + i;
+            I.nx = p.nx;
+            I.ny = p.ny;
+            I.bcx = p.bc_x;
+            I.bcy = eq == EULER2D ? p.bc_y : BC_PERIODIC;
+            I.dx = (p.x_hi - p.x_lo) / p.nx;
+            I.dy = eq == EULER2D ? (p.y_hi - p.y_lo) / p.ny : 1.0;
+            I.adv = p.adv_speed;
+            I.segs_per_row = (p.nx + XW_CELLS - 1) / XW_CELLS;
+            I.ytiles_per_row = (p.ny + YT_CELLS - 1) / YT_CELLS;
+            I.ycol_groups = (p.nx + YT_COLS - 1) / YT_COLS;
+            I.xtile0 = xt;
+            I.xtiles = ((long long)p.ny * I.segs_per_row + XW_SEGS - 1) / XW_SEGS;
+            I.ytile0 = yt;
+            I.ytiles = eq == EULER2D ? (long long)I.ytiles_per_row * I.ycol_groups : 0;
+            xt += I.xtiles;
+            yt += I.ytiles;
+        }
+        h_hdr.n_inst = count;
+        h_hdr.xtiles_total = xt;
+        h_hdr.ytiles_total = yt;
+        HIP_TRY(hipMemcpyAsync(d_hdr, &h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, stream));
+        std::vector<Ctrl> c0(count);
+        for (auto &c : c0) {
+            std::memset(&c, 0, sizeof(Ctrl));
+            c.t_final = INFINITY;
+            c.max_steps = 0;
+            c.done = 0;
+        }
+        HIP_TRY(hipMemcpyAsync(d_ctrl, c0.data(), sizeof(Ctrl) * count, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+
+        for (int m = 0; m < 4; ++m) {
+            grid_x[m] = grid_for(xt, occupancy_x(eq, order, m, false));
+            if (eq == EULER2D) grid_y[m] = grid_for(yt, occupancy_y(order, m, false));
+        }
+        grid_m = grid_for(xt, occupancy_maxima(eq));
+        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        return ENOAO_OK;
+    }
+
+    void release()
+    {
+        for (auto e : ev_pool) hipEventDestroy(e);
+        ev_pool.clear();
+        if (graph) hipGraphExecDestroy(graph);
+        if (cap) hipStreamDestroy(cap);
+        if (h_ctrl) hipHostFree(h_ctrl);
+        if (d_block) hipFree(d_block);
+        graph = nullptr;
+        cap = nullptr;
+        h_ctrl = nullptr;
+        d_block = nullptr;
+    }
+
+    // ---- building blocks, all enqueued on stream s ----
+    enoao_status set_pointers(int k, const double *u, double *lx, hipStream_t s)
+    {
+        // patch the member's u (and L output) in the device descriptor
+        HIP_TRY(launch_patch_inst(d_inst, k, u, lx, lx != nullptr, s));
+        return ENOAO_OK;
+    }
+
+    enoao_status reset_and_maxima(hipStream_t s)
+    {
+        int slot;
+        HIP_TRY(launch_reset_maxima(params(0, 0, -1), n, s));
+        HIP_TRY(prof_begin(PROF_MAXIMA, s, slot));
+        HIP_TRY(launch_state_maxima(eq, params(-1, 0, -1), grid_m, s));
+        HIP_TRY(prof_end(slot, s));
+        return ENOAO_OK;
+    }
+
+    // one Runge-Kutta stage (1..3); slots: stage s reads s-1, writes s%3, clears (s+1)%3
+    enoao_status stage(int s, bool record, hipStream_t st)
+    {
+        const int r_in = (s - 1) % 3, r_out = s % 3, r_zero = (s + 1) % 3;
+        const int mode = s;  // M_S1..M_S3
+        int slot;
+        HIP_TRY(prof_begin(PROF_X1 + s - 1, st, slot));
+        if (eq == EULER2D)
+            HIP_TRY(launch_sweep_x(eq, order, mode, record, params(r_in, -1, r_zero), grid_x[mode], st));
+        else
+            HIP_TRY(launch_sweep_x(eq, order, mode, record, params(r_in, r_out, r_zero), grid_x[mode], st));
+        HIP_TRY(prof_end(slot, st));
+        if (eq == EULER2D) {
+            HIP_TRY(prof_begin(PROF_Y1 + s - 1, st, slot));
+            HIP_TRY(launch_sweep_y(order, mode, record, params(r_in, r_out, -1), grid_y[mode], st));
+            HIP_TRY(prof_end(slot, st));
+        }
+        return ENOAO_OK;
+    }
+
+    enoao_status rhs(hipStream_t s)
+    {
+        HIP_TRY(launch_sweep_x(eq, order, M_RHS, rec, params(0, -1, -1), grid_x[M_RHS], s));
+        if (eq == EULER2D) HIP_TRY(launch_sweep_y(order, M_RHS, rec, params(0, -1, -1), grid_y[M_RHS], s));
+        return ENOAO_OK;
+    }
+
+    enoao_status steps(int k, bool control, hipStream_t s)
+    {
+        for (int i = 0; i < k; ++i) {
+            if (control) {
+                int slot;
+                HIP_TRY(prof_begin(PROF_CONTROL, s, slot));
+                HIP_TRY(launch_step_control(eq, params(0, -1, -1), n, s));
+                HIP_TRY(prof_end(slot, s));
+            }
+            for (int st = 1; st <= 3; ++st)
+                if (enoao_status e = stage(st, rec && st == 3, s)) return e;
+        }
+        return ENOAO_OK;
+    }
+
+    // graph of k controlled steps, captured once and replayed
+    enoao_status ensure_graph(int k)
+    {
+        if (graph && graph_k == k) return ENOAO_OK;
+        if (graph) {
+            hipGraphExecDestroy(graph);
+            graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        enoao_status e = steps(k, true, cap);
+        const hipError_t ce = hipStreamEndCapture(cap, &g);
+        if (e) {
+            if (g) hipGraphDestroy(g);
+            return e;
+        }
+        if (ce != hipSuccess) return ENOAO_EDEVICE;
+        const hipError_t ie = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            graph = nullptr;
+            return ENOAO_EDEVICE;
+        }
+        graph_k = k;
+        return ENOAO_OK;
+    }
+
+    enoao_status read_ctrl(hipStream_t s)
+    {
+        HIP_TRY(hipMemcpyAsync(h_ctrl, d_ctrl, sizeof(Ctrl) * n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (profiling) prof_collect();
+        return ENOAO_OK;
+    }
+
+    // k controlled steps: one graph replay, or eager launches when profiling
+    enoao_status run_steps(int k, hipStream_t s)
+    {
+        if (profiling) return steps(k, true, s);
+        if (enoao_status e = ensure_graph(k)) return e;
+        HIP_TRY(hipGraphLaunch(graph, s));
+        return ENOAO_OK;
+    }
+};
+
+struct enoao_plan {
+    Runtime rt;
+    double *ws_lx = nullptr;  // 2D: Lx workspace (inside the runtime allocation)
+};
+
+struct enoao_batch {
+    Runtime rt;
+    std::vector<const double *> bound;  // member states currently in the descriptors
+    bool started = false;
+};
+
+// init-control kernel arguments go through a tiny device copy of a host Ctrl array
+static enoao_status upload_ctrl(Runtime &rt, const std::vector<Ctrl> &c, hipStream_t s)
+{
+    std::memcpy(rt.h_ctrl, c.data(), sizeof(Ctrl) * rt.n);
+    HIP_TRY(hipMemcpyAsync(rt.d_ctrl, rt.h_ctrl, sizeof(Ctrl) * rt.n, hipMemcpyHostToDevice, s));
+    // the pinned mirror is reused by later calls: wait until the copy has read it
+    HIP_TRY(hipStreamSynchronize(s));
+    return ENOAO_OK;
+}
+
+extern "C" {
+
+const char *enoao_status_string(enoao_status s)
+{
+    switch (s) {
+    case ENOAO_OK: return "ok";
+    case ENOAO_EINVAL: return "invalid argument";
+    case ENOAO_ENOMEM: return "device out of memory";
+    case ENOAO_EDEVICE: return "HIP runtime error";
+    case ENOAO_EUNSUPPORTED: return "unsupported";
+    case ENOAO_ENONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or NaN)";
+    }
+    return "unknown status";
+}
+
+size_t enoao_workspace_bytes(const enoao_problem *prob)
+{
+    if (check_problem(prob)) return 0;
+    return sizeof(BatchHdr) + member_fixed_bytes() + member_bytes(prob);
+}
+
+enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved)
+{
+    if (workgroups_per_cu < 0 || reserved != 0) return ENOAO_EINVAL;
+    g_wg_per_cu = workgroups_per_cu;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_plan_create(const enoao_problem *prob, void *stream, enoao_plan **out)
+{
+    if (!out) return ENOAO_EINVAL;
+    *out = nullptr;
+    if (check_problem(prob)) return ENOAO_EINVAL;
+    enoao_plan *p = new (std::nothrow) enoao_plan();
+    if (!p) return ENOAO_ENOMEM;
+    enoao_status e = p->rt.init(prob, 1, (hipStream_t)stream);
+    if (e) {
+        p->rt.release();
+        delete p;
+        return e;
+    }
+    p->ws_lx = p->rt.h_inst[0].lx;
+    *out = p;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_plan_destroy(enoao_plan *plan)
+{
+    if (!plan) return ENOAO_EINVAL;
+    hipDeviceSynchronize();
+    plan->rt.release();
+    delete plan;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_rhs(enoao_plan *plan, const double *u, double *L, void *stream)
+{
+    if (!plan || !u || !L || (const double *)L == u) return ENOAO_EINVAL;
+    Runtime &rt = plan->rt;
+    hipStream_t s = (hipStream_t)stream;
+    if (enoao_status e = rt.set_pointers(0, u, L, s)) return e;
+    HIP_TRY(launch_clear_done(rt.params(0, -1, -1), 1, s));
+    if (enoao_status e = rt.reset_and_maxima(s)) return e;
+    if (enoao_status e = rt.rhs(s)) return e;
+    // restore the workspace Lx pointer for later steps
+    if (rt.eq == EULER2D) return rt.set_pointers(0, u, plan->ws_lx, s);
+    return ENOAO_OK;
+}
+
+enoao_status enoao_step(enoao_plan *plan, double *u, double dt, void *stream)
+{
+    if (!plan || !u || !(dt > 0.0) || !std::isfinite(dt)) return ENOAO_EINVAL;
+    Runtime &rt = plan->rt;
+    hipStream_t s = (hipStream_t)stream;
+    if (enoao_status e = rt.set_pointers(0, u, plan->ws_lx, s)) return e;
+    if (enoao_status e = rt.reset_and_maxima(s)) return e;
+    HIP_TRY(launch_set_dt(rt.params(0, -1, -1), 1, dt, s));
+    return rt.steps(1, false, s);
+}
+
+enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl, double dt_fixed,
+                         int64_t max_steps, double *t_out, int64_t *steps_out, void *stream)
+{
+    if (!plan || !u || !(t_final >= 0.0) || !std::isfinite(t_final) || max_steps < 0) return ENOAO_EINVAL;
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return ENOAO_EINVAL;
+    Runtime &rt = plan->rt;
+    hipStream_t s = (hipStream_t)stream;
+    if (enoao_status e = rt.set_pointers(0, u, plan->ws_lx, s)) return e;
+    std::vector<Ctrl> c(1);
+    std::memset(c.data(), 0, sizeof(Ctrl));
+    c[0].t = 0.0;
+    c[0].t_final = t_final;
+    c[0].cfl = cfl;
+    c[0].dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+    c[0].max_steps = max_steps;
+    if (enoao_status e = upload_ctrl(rt, c, s)) return e;
+    if (enoao_status e = rt.reset_and_maxima(s)) return e;
+
+    // steps per graph replay: a guess of the total, bounded
+    int k = 16;
+    if (dt_fixed > 0.0) {
+        const double est = std::ceil(t_final / dt_fixed);
+        k = (int)std::min(256.0, std::max(1.0, est));
+    } else {
+        k = 64;
+    }
+    if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps);
+    k = std::max(k, 1);
+    enoao_status st = ENOAO_OK;
+    for (;;) {
+        if (enoao_status e = rt.run_steps(k, s)) return e;
+        if (enoao_status e = rt.read_ctrl(s)) return e;
+        const Ctrl &h = rt.h_ctrl[0];
+        if (h.status) { st = ENOAO_ENONPHYSICAL; break; }
+        if (h.done) break;
+        if (max_steps == 0) break;
+    }
+    const Ctrl &h = rt.h_ctrl[0];
+    if (t_out) *t_out = h.t;
+    if (steps_out) *steps_out = h.steps;
+    if (st == ENOAO_OK && h.status) st = ENOAO_ENONPHYSICAL;
+    return st;
+}
+
+enoao_status enoao_plan_check(enoao_plan *plan, void *stream)
+{
+    if (!plan) return ENOAO_EINVAL;
+    Runtime &rt = plan->rt;
+    hipStream_t s = (hipStream_t)stream;
+    if (enoao_status e = rt.read_ctrl(s)) return e;
+    if (rt.h_ctrl[0].status) {
+        HIP_TRY(hipMemsetAsync(&rt.d_ctrl[0].status, 0, sizeof(int), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return ENOAO_ENONPHYSICAL;
+    }
+    return ENOAO_OK;
+}
+
+static enoao_status profile_set(Runtime &rt, int32_t enable)
+{
+    if (enable) {
+        rt.profiling = true;
+        for (int i = 0; i < PROF_KINDS; ++i) { rt.prof_ms[i] = 0.0; rt.prof_n[i] = 0; }
+        rt.ev_pairs.clear();
+    } else {
+        rt.profiling = false;
+    }
+    return ENOAO_OK;
+}
+
+static enoao_status profile_read(Runtime &rt, double *avg_ms, int64_t *count, int32_t n_kinds, void *stream)
+{
+    if (n_kinds < 0 || n_kinds > PROF_KINDS) return ENOAO_EINVAL;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    rt.prof_collect();
+    for (int i = 0; i < n_kinds; ++i) {
+        if (avg_ms) avg_ms[i] = rt.prof_n[i] ? rt.prof_ms[i] / rt.prof_n[i] : 0.0;
+        if (count) count[i] = rt.prof_n[i];
+    }
+    return ENOAO_OK;
+}
+
+enoao_status enoao_profile(enoao_plan *plan, int32_t enable)
+{
+    return plan ? profile_set(plan->rt, enable) : ENOAO_EINVAL;
+}
+
+enoao_status enoao_profile_read(enoao_plan *plan, double *avg_ms, int64_t *count, int32_t n_kinds, void *stream)
+{
+    return plan ? profile_read(plan->rt, avg_ms, count, n_kinds, stream) : ENOAO_EINVAL;
+}
+
+enoao_status enoao_batch_profile(enoao_batch *batch, int32_t enable)
+{
+    return batch ? profile_set(batch->rt, enable) : ENOAO_EINVAL;
+}
+
+enoao_status enoao_batch_profile_read(enoao_batch *batch, double *avg_ms, int64_t *count, int32_t n_kinds,
+                                      void *stream)
+{
+    return batch ? profile_read(batch->rt, avg_ms, count, n_kinds, stream) : ENOAO_EINVAL;
+}
+
+size_t enoao_selection_size(const enoao_plan *plan)
+{
+    if (!plan || !plan->rt.rec) return 0;
+    return selection_count(&plan->rt.probs[0]);
+}
+
+enoao_status enoao_get_selection(enoao_plan *plan, uint8_t *host_out, size_t n, void *stream)
+{
+    if (!plan || !host_out || !plan->rt.rec) return ENOAO_EINVAL;
+    if (n != selection_count(&plan->rt.probs[0])) return ENOAO_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(host_out, plan->rt.h_inst[0].sel, n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return ENOAO_OK;
+}
+
+// ---- batches ----
+enoao_status enoao_batch_create(const enoao_problem *probs, int32_t n, void *stream, enoao_batch **out)
+{
+    if (!out || !probs || n < 1) return ENOAO_EINVAL;
+    *out = nullptr;
+    enoao_batch *b = new (std::nothrow) enoao_batch();
+    if (!b) return ENOAO_ENOMEM;
+    enoao_status e = b->rt.init(probs, n, (hipStream_t)stream);
+    if (e) {
+        b->rt.release();
+        delete b;
+        return e;
+    }
+    b->bound.assign(n, nullptr);
+    *out = b;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_batch_destroy(enoao_batch *batch)
+{
+    if (!batch) return ENOAO_EINVAL;
+    hipDeviceSynchronize();
+    batch->rt.release();
+    delete batch;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_batch_reset(enoao_batch *batch, void *stream)
+{
+    if (!batch) return ENOAO_EINVAL;
+    batch->started = false;
+    (void)stream;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_batch_step(enoao_batch *batch, double *const *u, int32_t nsteps, double cfl,
+                              const double *t_final, void *stream)
+{
+    if (!batch || !u || nsteps < 0 || !(cfl > 0.0)) return ENOAO_EINVAL;
+    Runtime &rt = batch->rt;
+    hipStream_t s = (hipStream_t)stream;
+    bool rebind = false;
+    for (int i = 0; i < rt.n; ++i) {
+        if (!u[i]) return ENOAO_EINVAL;
+        if (batch->bound[i] != u[i]) rebind = true;
+    }
+    if (rebind) {
+        for (int i = 0; i < rt.n; ++i) rt.h_inst[i].u = u[i];
+        HIP_TRY(hipMemcpyAsync(rt.d_inst, rt.h_inst.data(), sizeof(Inst) * rt.n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // h_inst is reused by later calls
+        for (int i = 0; i < rt.n; ++i) batch->bound[i] = u[i];
+    }
+    // member control: continue times and step counts, extend the step budget
+    if (!batch->started) {
+        std::vector<Ctrl> c(rt.n);
+        for (int i = 0; i < rt.n; ++i) {
+            std::memset(&c[i], 0, sizeof(Ctrl));
+            c[i].t_final = t_final ? t_final[i] : INFINITY;
+            c[i].cfl = cfl;
+            c[i].max_steps = nsteps;
+        }
+        if (enoao_status e = upload_ctrl(rt, c, s)) return e;
+        if (enoao_status e = rt.reset_and_maxima(s)) return e;
+        batch->started = true;
+    } else {
+        if (enoao_status e = rt.read_ctrl(s)) return e;
+        std::vector<Ctrl> c(rt.h_ctrl, rt.h_ctrl + rt.n);
+        for (int i = 0; i < rt.n; ++i) {
+            c[i].cfl = cfl;
+            if (t_final) c[i].t_final = t_final[i];
+            c[i].max_steps = c[i].steps + nsteps;
+            if (c[i].status == 0) c[i].done = 0;
+        }
+        if (enoao_status e = upload_ctrl(rt, c, s)) return e;
+    }
+    if (nsteps == 0) return ENOAO_OK;
+    const int k = std::min(nsteps, 32);
+    for (int done = 0; done < nsteps; done += k) {
+        if (nsteps - done < k) {
+            if (enoao_status e = rt.steps(nsteps - done, true, s)) return e;
+            break;
+        }
+        if (enoao_status e = rt.run_steps(k, s)) return e;
+    }
+    return ENOAO_OK;
+}
+
+enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, int32_t *member_status,
+                               void *stream)
+{
+    if (!batch) return ENOAO_EINVAL;
+    Runtime &rt = batch->rt;
+    if (enoao_status e = rt.read_ctrl((hipStream_t)stream)) return e;
+    enoao_status st = ENOAO_OK;
+    for (int i = 0; i < rt.n; ++i) {
+        if (t) t[i] = rt.h_ctrl[i].t;
+        if (steps) steps[i] = rt.h_ctrl[i].steps;
+        if (member_status) member_status[i] = rt.h_ctrl[i].status;
+        if (rt.h_ctrl[i].status) st = ENOAO_ENONPHYSICAL;
+    }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// enoao_common.hpp -- structures shared by the host runtime and the HIP kernels.
+//
+// A "batch" is the unit every kernel works on: an array of instance
+// descriptors in device memory plus the flattened lists of line tiles of all
+// instances.  A single plan is a batch of one instance, so the plain, batched
+// and served paths run the same kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace enoao {
+
+enum Equation : int { ADVECTION = 0, EULER1D = 1, EULER2D = 2 };
+enum Bc : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+
+// x-sweep tiles: each wave reconstructs 64 consecutive faces of one grid line
+// and updates the 63 cells between them; a workgroup holds 4 such segments.
+constexpr int XW_FACES = 64;
+constexpr int XW_CELLS = XW_FACES - 1;
+constexpr int XW_SEGS = 4;
+// y-sweep tiles: 16 columns x 16 faces per workgroup, updating 16 x 15 cells.
+constexpr int YT_COLS = 16;
+constexpr int YT_FACES = 16;
+constexpr int YT_CELLS = YT_FACES - 1;
+constexpr int BLOCK = 256;
+
+// per-field maxima kept per instance: three ring slots of 8 values each
+// (non-negative doubles stored as their IEEE bit patterns so that unsigned
+// integer max is the floating-point max):
+//   [0..2] max |u-c|, |u|, |u+c| along x    [3..5] same along y (v)
+//   [6]    max (|u|+c)/dx + (|v|+c)/dy (2D time step)
+constexpr int AMAX_VALS = 8;
+constexpr int AMAX_SLOTS = 3;
+
+// Time-loop control of one instance (device memory).
+struct Ctrl {
+    double dt;          // step size of the step in flight
+    double t;           // time reached (after the step in flight)
+    double t_final;     // end time (+inf: none)
+    double cfl;         // CFL number for the device-computed step (if dt_fixed <= 0)
+    double dt_fixed;    // > 0: constant step
+    long long steps;    // steps taken
+    long long max_steps;
+    int done;           // 1: no further steps; kernels skip the instance
+    int status;         // bit 0: non-physical state met
+    int pad0, pad1;
+};
+
+// One instance of a batch (device memory).
+struct Inst {
+    double *u;                  // u^n: caller state, updated in place by stage 3
+    double *w1, *w2;            // stage-1 and stage-2 states
+    double *lx;                 // 2D: x-part of L; rhs: the L output
+    unsigned long long *amax;   // AMAX_SLOTS x AMAX_VALS
+    Ctrl *ctrl;
+    uint8_t *sel;               // selection record or nullptr
+    int nx, ny;
+    int bcx, bcy;
+    double dx, dy;
+    double adv;                 // advection speed
+    int segs_per_row;           // ceil(nx / XW_CELLS)
+    int ytiles_per_row;         // ceil(ny / YT_CELLS) row segments per column group
+    int ycol_groups;            // ceil(nx / YT_COLS)
+    int pad;
+    long long xtile0, ytile0;   // first x / y tile of this instance in the batch lists
+    long long xtiles, ytiles;   // number of x / y tiles
+};
+
+// Batch header (device memory): kernels read the instance count and the tile
+// totals from here, so a captured graph stays valid when the active set changes.
+struct BatchHdr {
+    int n_inst;
+    int pad;
+    long long xtiles_total, ytiles_total;
+};
+
+}  // namespace enoao

@@ -1,0 +1,277 @@
+// enoao_device.hpp -- per-face arithmetic of the ENO-AO method on gfx950.
+//
+// Everything here runs in registers of one lane: one lane owns one face.
+//   * recon<ORDER>: one side of the reconstruction of Section 3.2 -- the
+//     minimum-discrepancy indicators IS = min(delta_L, delta_R) of
+//     Eq. (New_Smoothness_Indicator) in the closed forms of Tables DeltaL /
+//     DeltaR, the reconstruction principle, and the selected row of the table
+//     of numerical fluxes.
+//   * Roe-state characteristic projection for the Euler systems (Section 4:
+//     Roe average at the face for the characteristic decomposition).
+//
+// Implementation notes (same arithmetic as the paper, laid out for the VALU):
+//   * the undivided differences of all candidates come from one difference
+//     table (20 subtractions for order 5 instead of the literal rows); two
+//     candidates whose delta rows coincide share one entry, so their indicators
+//     are bitwise equal as the rows are;
+//   * the two principles are evaluated branch-free as one arg-min over keys
+//     key_k = (IS_k <= delta ? 0 : IS_k) with ties to the higher priority:
+//     when some IS_k <= delta the minimum key is 0 and the highest-priority
+//     such candidate wins (first principle); otherwise the keys are the
+//     indicators (second principle);
+//   * a window may be scaled by a power of two before reconstruction (the
+//     factor 1/2 of the splitting is applied after it); scaling by 2^k is
+//     exact, so indicators, comparisons and selections are unchanged when delta
+//     is scaled alike.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace enoao {
+
+template <int ORDER> struct ReconTraits;
+template <> struct ReconTraits<5> { static constexpr int H = 3, K = 6; };
+template <> struct ReconTraits<7> { static constexpr int H = 4, K = 9; };
+
+__device__ __forceinline__ double key_of(double is, double delta) { return is <= delta ? 0.0 : is; }
+
+// f[0..6] = f_{j-3} .. f_{j+3}; returns fhat^+_{j+1/2}; sel = chosen candidate
+// (0: S_j^j, 1: S_j^{j+1}, 2: S_{j-1}^{j+1}, 3: S_{j-2}^{j+1}, 4: S_{j-1}^{j+2},
+//  5: S_{j-2}^{j+2}).
+__device__ __forceinline__ double recon5(const double (&f)[7], double delta, int &sel)
+{
+    const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
+    const double a3 = f[4] - f[3], a4 = f[5] - f[4], a5 = f[6] - f[5];
+    const double b0 = a1 - a0, b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3, b4 = a5 - a4;
+    const double c0 = b1 - b0, c1 = b2 - b1, c2 = b3 - b2, c3 = b4 - b3;
+    const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
+    const double e0 = d1 - d0, e1 = d2 - d1;
+    const double ad1 = fabs(d1);
+    double is[6];
+    is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
+    is[1] = fmin(fabs(b2), fabs(b3));                              // S_j^{j+1}
+    is[2] = fmin(fabs(c1), fabs(c2));                              // S_{j-1}^{j+1}
+    is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
+    is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
+    is[5] = fmin(fabs(e0), fabs(e1));                              // S_{j-2}^{j+2}
+    double m = key_of(is[0], delta);
+    int s = 0;
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+        const double key = key_of(is[k], delta);
+        if (key <= m) { m = key; s = k; }
+    }
+    const double q1 = 0.5 * (f[3] + f[4]);
+    const double q2 = (fma(5.0, f[3], 2.0 * f[4]) - f[2]) * (1.0 / 6.0);
+    const double q3 = fma(13.0, f[3], fma(3.0, f[4], fma(-5.0, f[2], f[1]))) * (1.0 / 12.0);
+    const double q4 = fma(7.0, f[3] + f[4], -(f[2] + f[5])) * (1.0 / 12.0);
+    const double q5 = fma(47.0, f[3], fma(27.0, f[4], fma(-13.0, f[2], fma(2.0, f[1], -3.0 * f[5])))) *
+                      (1.0 / 60.0);
+    double q = f[3];
+    q = s == 1 ? q1 : q;
+    q = s == 2 ? q2 : q;
+    q = s == 3 ? q3 : q;
+    q = s == 4 ? q4 : q;
+    q = s == 5 ? q5 : q;
+    sel = s;
+    return q;
+}
+
+// f[0..8] = f_{j-4} .. f_{j+4}; candidates 0..5 as recon5, then
+// 6: S_{j-3}^{j+2}, 7: S_{j-2}^{j+3}, 8: S_{j-3}^{j+3}.
+__device__ __forceinline__ double recon7(const double (&f)[9], double delta, int &sel)
+{
+    double a[8], b[7], c[6], d[5], e[4], g[3], h[2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = f[i + 1] - f[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) b[i] = a[i + 1] - a[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) c[i] = b[i + 1] - b[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) d[i] = c[i + 1] - c[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = d[i + 1] - d[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = e[i + 1] - e[i];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) h[i] = g[i + 1] - g[i];
+    const double ad2 = fabs(d[2]), ag1 = fabs(g[1]);
+    double is[9];
+    is[0] = 0.5 * fmin(fabs(a[3]) + fabs(a[2]), fabs(a[4]) + fabs(a[5])); // S_j^j
+    is[1] = fmin(fabs(b[3]), fabs(b[4]));                                  // S_j^{j+1}
+    is[2] = fmin(fabs(c[2]), fabs(c[3]));                                  // S_{j-1}^{j+1}
+    is[3] = fmin(fabs(d[1]), ad2);                                         // S_{j-2}^{j+1}
+    is[4] = fmin(ad2, fabs(d[3]));                                         // S_{j-1}^{j+2}
+    is[5] = fmin(fabs(e[1]), fabs(e[2]));                                  // S_{j-2}^{j+2}
+    is[6] = fmin(fabs(g[0]), ag1);                                         // S_{j-3}^{j+2}
+    is[7] = fmin(ag1, fabs(g[2]));                                         // S_{j-2}^{j+3}
+    is[8] = fmin(fabs(h[0]), fabs(h[1]));                                  // S_{j-3}^{j+3}
+    double m = key_of(is[0], delta);
+    int s = 0;
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+        const double key = key_of(is[k], delta);
+        if (key <= m) { m = key; s = k; }
+    }
+    const double q1 = 0.5 * (f[4] + f[5]);
+    const double q2 = (fma(5.0, f[4], 2.0 * f[5]) - f[3]) * (1.0 / 6.0);
+    const double q3 = fma(13.0, f[4], fma(3.0, f[5], fma(-5.0, f[3], f[2]))) * (1.0 / 12.0);
+    const double q4 = fma(7.0, f[4] + f[5], -(f[3] + f[6])) * (1.0 / 12.0);
+    const double q5 = fma(47.0, f[4], fma(27.0, f[5], fma(-13.0, f[3], fma(2.0, f[2], -3.0 * f[6])))) *
+                      (1.0 / 60.0);
+    const double q6 = fma(57.0, f[4], fma(22.0, f[5], fma(-23.0, f[3], fma(7.0, f[2], fma(-2.0, f[6], -f[1]))))) *
+                      (1.0 / 60.0);
+    const double q7 = fma(37.0, f[4] + f[5], fma(-8.0, f[3] + f[6], f[2] + f[7])) * (1.0 / 60.0);
+    const double q8 = fma(319.0, f[4], fma(214.0, f[5], fma(-101.0, f[3], fma(25.0, f[2],
+                      fma(-38.0, f[6], fma(4.0, f[7], -3.0 * f[1])))))) * (1.0 / 420.0);
+    double q = f[4];
+    q = s == 1 ? q1 : q;
+    q = s == 2 ? q2 : q;
+    q = s == 3 ? q3 : q;
+    q = s == 4 ? q4 : q;
+    q = s == 5 ? q5 : q;
+    q = s == 6 ? q6 : q;
+    q = s == 7 ? q7 : q;
+    q = s == 8 ? q8 : q;
+    sel = s;
+    return q;
+}
+
+template <int ORDER> struct Recon;
+template <> struct Recon<5> {
+    __device__ __forceinline__ static double run(const double (&f)[7], double delta, int &sel)
+    {
+        return recon5(f, delta, sel);
+    }
+};
+template <> struct Recon<7> {
+    __device__ __forceinline__ static double run(const double (&f)[9], double delta, int &sel)
+    {
+        return recon7(f, delta, sel);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Per-node quantities staged in LDS (computed once per node by the lane that
+// loads it; faces read them from LDS).
+//   advection: u
+//   Euler 1D : rho, m, E | F0..F2 | sqrt(rho), u, H
+//   Euler 2D : rho, m, n, E | F0..F3 | sqrt(rho), u, v, H
+// (for a y-sweep the two momentum components arrive exchanged, so the same
+//  x-direction formulas give the y-flux in exchanged order).
+template <int EQ> struct NodeTraits;
+template <> struct NodeTraits<ADVECTION> { static constexpr int NC = 1, NQ = 1; };
+template <> struct NodeTraits<EULER1D> { static constexpr int NC = 3, NQ = 9; };
+template <> struct NodeTraits<EULER2D> { static constexpr int NC = 4, NQ = 12; };
+
+// Returns false for a non-physical node (rho <= 0, p <= 0 or NaN).
+template <int EQ>
+__device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>::NC], double gm1,
+                                                double (&q)[NodeTraits<EQ>::NQ])
+{
+    if constexpr (EQ == ADVECTION) {
+        q[0] = U[0];
+        return U[0] == U[0];
+    } else if constexpr (EQ == EULER1D) {
+        const double rho = U[0], m = U[1], E = U[2];
+        const double ir = 1.0 / rho;
+        const double u = m * ir;
+        const double p = gm1 * (E - 0.5 * rho * (u * u));
+        q[0] = rho; q[1] = m; q[2] = E;
+        q[3] = m; q[4] = fma(m, u, p); q[5] = (E + p) * u;
+        q[6] = sqrt(rho); q[7] = u; q[8] = (E + p) * ir;
+        return rho > 0.0 && p > 0.0;
+    } else {
+        const double rho = U[0], m = U[1], n = U[2], E = U[3];
+        const double ir = 1.0 / rho;
+        const double u = m * ir, v = n * ir;
+        const double p = gm1 * (E - 0.5 * rho * fma(u, u, v * v));
+        q[0] = rho; q[1] = m; q[2] = n; q[3] = E;
+        q[4] = m; q[5] = fma(m, u, p); q[6] = m * v; q[7] = (E + p) * u;
+        q[8] = sqrt(rho); q[9] = u; q[10] = v; q[11] = (E + p) * ir;
+        return rho > 0.0 && p > 0.0;
+    }
+}
+
+// Roe state of the two nodes adjacent to a face, with the factors of the
+// characteristic projection.
+struct RoeState {
+    double u, v, H, c, ic, b1, b2, q2h;
+};
+
+__device__ __forceinline__ RoeState roe_state(double sL, double uL, double vL, double HL, double sR,
+                                              double uR, double vR, double HR, double gm1)
+{
+    RoeState r;
+    const double iw = 1.0 / (sL + sR);
+    const double wL = sL * iw, wR = sR * iw;
+    r.u = fma(wL, uL, wR * uR);
+    r.v = fma(wL, vL, wR * vR);
+    r.H = fma(wL, HL, wR * HR);
+    r.q2h = 0.5 * fma(r.u, r.u, r.v * r.v);
+    const double c2 = gm1 * (r.H - r.q2h);
+    r.c = sqrt(c2);
+    r.ic = 1.0 / r.c;
+    r.b1 = gm1 * r.ic * r.ic;
+    r.b2 = r.q2h * r.b1;
+    return r;
+}
+
+// Projection of a conserved-variable vector x on the left eigenvectors of the
+// Roe state (right eigenvectors with unit first component):
+//   2D: rows l0 = (b2+u/c, -b1 u-1/c, -b1 v, b1)/2, l1 = (1-b2, b1 u, b1 v, -b1),
+//       l2 = (-v, 0, 1, 0), l3 = (b2-u/c, -b1 u+1/c, -b1 v, b1)/2
+//   1D: the same without the v entries and without l2.
+// Output scaled by (2, 1, 1, 2) in 2D and (2, 1, 2) in 1D: with
+// A = b2 x0 - b1 (u x1 + v x2 - x3) and B = (u x0 - x1)/c,
+// 2 l0.x = A + B, l1.x = x0 - A, l2.x = x2 - v x0, 2 l3.x = A - B.
+template <int NC>
+__device__ __forceinline__ void project(const RoeState &r, const double (&x)[NC], double (&w)[NC])
+{
+    if constexpr (NC == 4) {
+        const double t = fma(r.u, x[1], fma(r.v, x[2], -x[3]));
+        const double A = fma(r.b2, x[0], -r.b1 * t);
+        const double B = fma(r.u, x[0], -x[1]) * r.ic;
+        w[0] = A + B;
+        w[1] = x[0] - A;
+        w[2] = fma(-r.v, x[0], x[2]);
+        w[3] = A - B;
+    } else {
+        const double t = fma(r.u, x[1], -x[2]);
+        const double A = fma(r.b2, x[0], -r.b1 * t);
+        const double B = fma(r.u, x[0], -x[1]) * r.ic;
+        w[0] = A + B;
+        w[1] = x[0] - A;
+        w[2] = A - B;
+    }
+}
+
+// scale of field s after project(): 2 for the acoustic fields, 1 otherwise
+template <int NC> __device__ __forceinline__ constexpr double field_scale(int s)
+{
+    return (s == 0 || s == NC - 1) ? 2.0 : 1.0;
+}
+
+// Back to conserved variables: Fhat = R what, R columns (2D)
+//   (1, u-c, v, H-uc), (1, u, v, q^2/2), (0, 0, 1, v), (1, u+c, v, H+uc)
+// (1D: the same without v and without the third column).
+template <int NC>
+__device__ __forceinline__ void back_project(const RoeState &r, const double (&w)[NC], double (&F)[NC])
+{
+    if constexpr (NC == 4) {
+        const double s03 = w[0] + w[3], d30 = w[3] - w[0];
+        F[0] = s03 + w[1];
+        F[1] = fma(r.u, F[0], r.c * d30);
+        F[2] = fma(r.v, F[0], w[2]);
+        F[3] = fma(r.H, s03, fma(r.u * r.c, d30, fma(r.q2h, w[1], r.v * w[2])));
+    } else {
+        const double s02 = w[0] + w[2], d20 = w[2] - w[0];
+        F[0] = s02 + w[1];
+        F[1] = fma(r.u, F[0], r.c * d20);
+        F[2] = fma(r.H, s02, fma(r.u * r.c, d20, r.q2h * w[1]));
+    }
+}
+
+}  // namespace enoao

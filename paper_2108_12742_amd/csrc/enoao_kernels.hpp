@@ -1,0 +1,42 @@
+// enoao_kernels.hpp -- launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "enoao_common.hpp"
+
+namespace enoao {
+
+// what a sweep kernel does with the flux difference
+enum Mode : int {
+    M_RHS = 0,  // evaluate L of the caller state (1D: write L; 2D: x writes Lx, y adds Ly)
+    M_S1 = 1,   // Runge-Kutta stage 1: input u^n, output w1
+    M_S2 = 2,   // stage 2: input w1, output w2
+    M_S3 = 3    // stage 3: input w2, output u^{n+1} (in place)
+};
+
+struct KParams {
+    const BatchHdr *hdr;
+    const Inst *inst;
+    double gamma, gm1, delta;
+    int r_in;    // maxima slot holding alpha of the stage input
+    int r_out;   // slot receiving the maxima of the stage output (-1: none)
+    int r_zero;  // slot cleared by the first kernel of the stage (-1: none)
+    int pad;
+};
+
+hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s);
+hipError_t launch_sweep_y(int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s);
+hipError_t launch_state_maxima(int eq, const KParams &p, int grid, hipStream_t s);
+hipError_t launch_reset_maxima(const KParams &p, int n_inst, hipStream_t s);
+hipError_t launch_step_control(int eq, const KParams &p, int n_inst, hipStream_t s);
+hipError_t launch_set_dt(const KParams &p, int n_inst, double dt, hipStream_t s);
+hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, bool set_lx, hipStream_t s);
+hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
+
+// resident workgroups per CU of each kernel (for persistent grid sizes)
+int occupancy_x(int eq, int order, int mode, bool rec);
+int occupancy_y(int order, int mode, bool rec);
+int occupancy_maxima(int eq);
+
+}  // namespace enoao

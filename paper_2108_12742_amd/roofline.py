@@ -1,0 +1,100 @@
+"""Algorithmic work per unit of the ENO-AO kernels, for roofline reporting.
+
+Units: a "face" is one face of one sweep direction with all its characteristic
+fields and both split sides; a "cell" is one node updated by one kernel launch.
+Counts are the essential FP64 operations of the method as laid out in the
+kernels (add, sub, mul, div, sqrt, min/max, compare = 1 flop; a fused
+multiply-add = 2; fabs and negation free), counting one candidate flux per side
+(the selected one) and every indicator (branch-free selection).  Bytes are the
+compulsory HBM traffic of a launch: each input array read once, each output
+written once (halo re-reads excluded).
+
+Peaks (MI355X, published): HBM3E 8.0 TB/s; FP64 vector 78.6 TFLOP/s
+(256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz).
+"""
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+# one side of one field: 20 (difference table: 6+5+4+3+2 subtractions for order 5;
+# 8+7+...+2 = 35 for order 7) + indicators (S_j^j: 2 adds, 1 min, 1 mul; one min per
+# other candidate) + keys (1 compare per candidate) + arg-min (K-1 compares) + the
+# selected candidate flux (at most 5 / 7 multiply-adds and 1 scaling)
+RECON_SIDE = {5: 20 + (4 + 5) + 6 + 5 + 9, 7: 35 + (4 + 8) + 9 + 8 + 13}
+
+
+def face_flops(equation: str, order: int) -> int:
+    r = RECON_SIDE[order]
+    h = 3 if order == 5 else 4
+    nodes = 2 * h + 2  # stencil nodes of one face
+    if equation == "advection":
+        # split: per window value 1 mul + 1 fma (2 windows of 2h+1), recon 2 sides,
+        # combine 2, flux difference 2
+        return 2 * (2 * h + 1) * 3 + 2 * r + 2 + 2
+    nc = 3 if equation == "euler1d" else 4
+    node = 15 if nc == 4 else 12            # conserved -> flux, sqrt(rho), u, (v,) H: once per node
+    roe = 23 if nc == 4 else 19             # Roe average, c, 1/c, b1, b2
+    proj_vec = 15 if nc == 4 else 11        # structured left-eigenvector product of one vector
+    projection = 2 * nodes * proj_vec       # U and F at every stencil node
+    split = 2 * (2 * h + 1) * nc * 2        # w+ and w- windows, one fma each
+    recon = 2 * nc * r
+    back = 2 * nc + (16 if nc == 4 else 12)  # (w+ + w-) scaling and R w
+    diff = 2 * nc                            # flux difference per cell
+    return node + roe + projection + split + recon + back + diff
+
+
+def stage_cell_flops(equation: str, stage: int) -> int:
+    """RK combine + maxima epilogue per cell of the last sweep of a stage."""
+    nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
+    combine = 2 * nc if stage == 1 else 5 * nc
+    maxima = {"advection": 1, "euler1d": 16, "euler2d": 28}[equation]
+    add_x = nc if equation == "euler2d" else 0
+    return combine + maxima + add_x
+
+
+def sweep_bytes(equation: str, kernel: str, stage: int) -> int:
+    """Compulsory HBM bytes per cell of one launch.
+
+    kernel 'x' (2D): read stage input, write the x-part of L.
+    kernel 'y' (2D) / 'x' (1D): read stage input (+ u^n for stages 2, 3)
+    (+ the x-part of L in 2D), write the stage output."""
+    nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
+    w = 8 * nc
+    if equation == "euler2d" and kernel == "x":
+        return 2 * w
+    b = 2 * w + (w if stage > 1 else 0)
+    if equation == "euler2d":
+        b += w
+    return b
+
+
+def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
+    """Algorithmic flops per cell of one launch."""
+    f = face_flops(equation, order)
+    if equation == "euler2d" and kernel == "x":
+        return f
+    return f + stage_cell_flops(equation, stage)
+
+
+def cell_update_flops(equation: str, order: int) -> int:
+    dims = 2 if equation == "euler2d" else 1
+    return 3 * dims * face_flops(equation, order) + sum(stage_cell_flops(equation, s) for s in (1, 2, 3))
+
+
+def cell_update_bytes(equation: str) -> int:
+    if equation == "euler2d":
+        return sum(sweep_bytes(equation, "x", s) + sweep_bytes(equation, "y", s) for s in (1, 2, 3))
+    return sum(sweep_bytes(equation, "x", s) for s in (1, 2, 3))
+
+
+def roofline_entry(flops: float, nbytes: float, seconds: float, traffic=None):
+    """The roof this launch is closer to, with achieved / peak."""
+    gflops = flops / seconds / 1e12
+    gbs = nbytes / seconds / 1e9
+    f_alu = gflops / PEAK_FP64_TFLOPS
+    f_hbm = gbs / PEAK_HBM_GBS
+    if f_alu >= f_hbm:
+        return {"bound": "alu", "achieved": round(gflops, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(f_alu, 4), "traffic": traffic}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(f_hbm, 4), "traffic": traffic}

@@ -1,0 +1,254 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs.  Sizes span several tiles and ragged tails (x segments hold 63 cells,
+y tiles 16 x 15 cells), plus the degenerate sizes below one tile."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12742_amd import workloads as W
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def _E():
+    from paper_2108_12742_amd import enoao as E
+    return E
+
+
+def _adv_case(n, order=5, jumps=False, a=1.0):
+    inst = W.advection(n % 7, n)
+    u = inst.u0.copy()
+    if jumps:
+        x = W.nodes(-1.0, 1.0, n)
+        u[0, 0] += np.where((x > -0.45) & (x < 0.1), 0.8, 0.0) - np.where(x > 0.6, 0.3, 0.0)
+    inst.u0 = u
+    inst.adv_speed = a
+    return inst, order
+
+
+def _euler1d_case(n, order=5, bc="transmissive", seed=None):
+    inst = W.riemann_1d(n if seed is None else seed, n)
+    inst.bc_x = bc
+    return inst, order
+
+
+def _euler2d_case(nx, ny, order=5, bc="periodic", seed=None):
+    inst = W.quadrants(nx + 3 * ny if seed is None else seed, nx, ny)
+    inst.bc_x = inst.bc_y = bc
+    return inst, order
+
+
+CASES = (
+    [("adv", _adv_case, (n,), {}) for n in (1, 5, 63, 64, 127, 200)]
+    + [("adv-jumps", _adv_case, (n,), {"jumps": True}) for n in (131, 257)]
+    + [("adv-left", _adv_case, (150,), {"jumps": True, "a": -0.7})]
+    + [("adv7", _adv_case, (190,), {"order": 7, "jumps": True})]
+    + [("e1", _euler1d_case, (n,), {}) for n in (3, 8, 63, 126, 300)]
+    + [("e1-periodic", _euler1d_case, (n,), {"bc": "periodic"}) for n in (64, 255)]
+    + [("e1-o7", _euler1d_case, (211,), {"order": 7})]
+    + [("e2", _euler2d_case, (40, 37), {}), ("e2", _euler2d_case, (16, 15), {}),
+       ("e2-tr", _euler2d_case, (70, 31), {"bc": "transmissive"}), ("e2", _euler2d_case, (5, 9), {}),
+       ("e2-o7", _euler2d_case, (33, 29), {"order": 7})]
+)
+IDS = [f"{c[0]}-{'x'.join(map(str, c[2]))}" for c in CASES]
+
+
+def _setup(case, record=True):
+    _, fn, args, kw = case
+    inst, order = fn(*args, **kw)
+    E = _E()
+    ep = E.problem_from_instance(inst, order=order, record_selection=record)
+    return inst, ep, PT.oracle_problem(ep)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_rhs_matches_oracle(case):
+    torch = PT.torch_cuda()
+    E = _E()
+    inst, ep, op = _setup(case)
+    print(f"rhs case {IDS[CASES.index(case)]}", flush=True)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    L = torch.full_like(u, float("nan"))
+    E.enoao_rhs(plan, u, L)
+    sel = E.enoao_get_selection(plan)
+    torch.cuda.synchronize()
+    Lr, selr, tier = O.rhs(op, inst.u0, with_selection=True)
+    mask = PT.compare_selection(op, sel, selr, tier)
+    PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what="L")
+    assert torch.equal(u.cpu(), torch.from_numpy(inst.u0)), "rhs must not modify u"
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_step_matches_oracle(case):
+    torch = PT.torch_cuda()
+    E = _E()
+    inst, ep, op = _setup(case, record=False)
+    print(f"step case {IDS[CASES.index(case)]}", flush=True)
+    plan = E.enoao_plan_create(ep)
+    dt = 0.5 * O.cfl_dt(op, inst.u0, 0.3)
+    u = PT.to_dev(torch, inst.u0)
+    E.enoao_step(plan, u, dt)
+    torch.cuda.synchronize()
+    ur = O.step(op, inst.u0, dt)
+    PT.assert_close_by_component(u.cpu().numpy(), ur, what="u")
+    E.enoao_plan_check(plan)
+
+
+def test_c0_solve_matches_oracle():
+    """The smooth advection workload end to end: N = 200, CFL 0.5, 400 steps to t = 2."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.advection(0, 200)
+    ep = E.problem_from_instance(inst)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, 2.0, cfl=0.5)
+    ur, tr, nr = O.solve(op, inst.u0, 2.0, cfl=0.5)
+    assert (t, n) == (tr, nr) == (2.0, 400)
+    PT.assert_close_by_component(u.cpu().numpy(), ur, what="u(t=2)")
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_convergence_row_on_gpu(order):
+    """The paper's convergence test at dx = 1/20 and 1/30 with the GPU solver (fixed dt)."""
+    torch = PT.torch_cuda()
+    E = _E()
+    printed = {(5, 20): (2.47e-5, 6.23e-5), (5, 30): (1.30e-6, 3.04e-6),
+               (7, 20): (3.68e-8, 5.89e-8), (7, 30): (2.17e-9, 3.46e-9)}
+    for inv in (20, 30):
+        n = 2 * inv
+        x = W.nodes(-1.0, 1.0, n)
+        u0 = np.sin(np.pi * x).reshape(1, 1, n)
+        ep = E.make_problem("advection", n, order=order)
+        plan = E.enoao_plan_create(ep)
+        u = PT.to_dev(torch, u0)
+        dtf = (1.0 / inv) ** (order / 3.0)
+        t, steps = E.enoao_solve(plan, u, 2.0, dt_fixed=dtf)
+        ur, tr, nr = O.solve(PT.oracle_problem(ep), u0, 2.0, dt_fixed=dtf)
+        assert (t, steps) == (tr, nr)
+        g = u.cpu().numpy()
+        PT.assert_close_by_component(g, ur, rtol=1e-11, what="u(t=2)")
+        e = np.abs(g[0, 0] - u0[0, 0])
+        l1, li = np.append(e, e[0]).mean(), e.max()
+        p1, pi = printed[(order, inv)]
+        tol = 0.1 if (order, inv) == (5, 20) else 0.02
+        assert abs(l1 / p1 - 1) < tol and abs(li / pi - 1) < tol, (l1, li)
+
+
+def test_euler1d_per_step_parity_c1():
+    """1D Euler workload (N = 2000, seeded Riemann data): GPU steps from the oracle's state
+    match the oracle step for step."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.riemann_1d(0, 2000)
+    ep = E.problem_from_instance(inst)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    ur = inst.u0.copy()
+    for k in range(5):
+        dt = O.cfl_dt(op, ur, 0.3)
+        u = PT.to_dev(torch, ur)
+        E.enoao_step(plan, u, dt)
+        ur = O.step(op, ur, dt)
+        PT.assert_close_by_component(u.cpu().numpy(), ur, what=f"u step {k}")
+
+
+def test_euler1d_solve_matches_oracle():
+    """Device-side CFL step control and graph replay against the oracle's time loop."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.riemann_1d(1, 400)
+    ep = E.problem_from_instance(inst)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, 0.004, cfl=0.3)
+    ur, tr, nr = O.solve(op, inst.u0, 0.004, cfl=0.3)
+    assert n == nr and abs(t - tr) <= 1e-15
+    PT.assert_close_by_component(u.cpu().numpy(), ur, rtol=1e-11, what="u")
+    # same call again (graph reused): bitwise identical
+    u2 = PT.to_dev(torch, inst.u0)
+    E.enoao_solve(plan, u2, 0.004, cfl=0.3)
+    assert torch.equal(u, u2)
+
+
+def test_euler2d_solve_matches_oracle():
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.quadrants(11, 48, 40)
+    ep = E.problem_from_instance(inst)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, 1.0, cfl=0.3, max_steps=6)
+    ur, tr, nr = O.solve(op, inst.u0, 1.0, cfl=0.3, max_steps=6)
+    assert n == nr == 6 and abs(t / tr - 1) <= 1e-14
+    PT.assert_close_by_component(u.cpu().numpy(), ur, rtol=1e-11, what="u")
+
+
+def test_launch_shape_invariance():
+    """Results do not depend on the persistent grid size (catches LDS/halo races)."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.quadrants(3, 100, 90)
+    ep = E.problem_from_instance(inst)
+    outs = []
+    try:
+        for wg in (0, 1, 3):
+            E.enoao_set_launch(wg)
+            plan = E.enoao_plan_create(ep)
+            u = PT.to_dev(torch, inst.u0)
+            E.enoao_solve(plan, u, 1.0, cfl=0.3, max_steps=3)
+            outs.append(u.cpu())
+    finally:
+        E.enoao_set_launch(0)
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_nonphysical_state_reported():
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.riemann_1d(2, 128)
+    u0 = inst.u0.copy()
+    u0[2, 0, 40] = 0.5 * u0[1, 0, 40] ** 2 / u0[0, 0, 40] * 0.5  # E below kinetic energy: p < 0
+    plan = E.enoao_plan_create(E.problem_from_instance(inst))
+    u = PT.to_dev(torch, u0)
+    with pytest.raises(E.EnoaoError) as ei:
+        E.enoao_solve(plan, u, 0.01, cfl=0.3)
+    assert ei.value.status == E.ENONPHYSICAL
+
+
+def test_invalid_arguments():
+    PT.torch_cuda()
+    E = _E()
+    bad = E.make_problem("euler1d", 10, order=6)
+    with pytest.raises(E.EnoaoError):
+        E.enoao_plan_create(bad)
+    bad = E.make_problem("euler1d", 10, ny=3)
+    with pytest.raises(E.EnoaoError):
+        E.enoao_plan_create(bad)
+
+
+@pytest.mark.slow
+def test_c2_full_size_rhs():
+    """The 2D Euler workload at its full size (2048^2, periodic, quadrant data): one
+    evaluation of L against the oracle, with the launch configuration of the benchmark."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.quadrants(0, 2048)
+    ep = E.problem_from_instance(inst, record_selection=True)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    L = torch.empty_like(u)
+    E.enoao_rhs(plan, u, L)
+    sel = E.enoao_get_selection(plan)
+    print("oracle rhs at 2048^2 ...", flush=True)
+    Lr, selr, tier = O.rhs(op, inst.u0, with_selection=True)
+    mask = PT.compare_selection(op, sel, selr, tier)
+    PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what="L")
