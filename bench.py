@@ -2,7 +2,8 @@
 """Throughput of the ENO-AO hot path on one MI355X.
 
 Default workload: 2D Euler, 2048 x 2048 nodes, periodic, four seeded quadrant
-states (rho, p ~ LogUniform[0.1, 10], u, v ~ U[-2, 2]), fifth-order ENO-AO with
+states (rho, p ~ LogUniform[0.1, 10], u, v ~ U[-2, 2], generator seed
+workloads.QUADRANT_BENCH_SEED), fifth-order ENO-AO with
 Roe characteristic decomposition, SSP-RK3 with the device-side CFL step
 (CFL 0.3); K timed steps after W warm-up steps, inputs resident in HBM.
 
@@ -24,12 +25,40 @@ KERNEL_NAMES = {  # profile kind -> kernel symbol as rocprofv3 prints it (order 
 }
 
 
+def kernel_sources_hash():
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(here, "paper_2108_12742_amd", "csrc", "*.hip"))
+                   + glob.glob(os.path.join(here, "paper_2108_12742_amd", "csrc", "*.hpp")))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(symbol, workload):
+    """HBM bytes per launch of `symbol` from the committed rocprofv3 byte counters
+    (profiles/traffic.json), or None when the kernels changed since they were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_sources_hash() or t.get("workload") != workload:
+        return None
+    v = t.get("bytes_per_launch", {}).get(symbol)
+    return None if v is None else round(v)
+
+
 def cpu_baseline(n_sample=512, steps=2):
     """The oracle (single-threaded C, FP64) on a bounded sample of the workload:
     `steps` SSP-RK3 steps of the same seeded quadrant problem at n_sample^2 nodes."""
     from oracle import oracle as O
     from paper_2108_12742_amd import workloads as W
-    inst = W.quadrants(0, n_sample)
+    inst = W.quadrants(W.QUADRANT_BENCH_SEED, n_sample)
     p = O.Problem(O.EULER2D, nx=n_sample, ny=n_sample, order=5)
     u = inst.u0
     t0 = time.perf_counter()
@@ -38,7 +67,7 @@ def cpu_baseline(n_sample=512, steps=2):
         u = O.step(p, u, dt)
     el = time.perf_counter() - t0
     return {"value": n_sample * n_sample * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of the 2D Euler quadrant workload (seed 0) at {n_sample}x{n_sample}, "
+            "sample": f"{steps} SSP-RK3 steps of the 2D Euler quadrant workload (seed {W.QUADRANT_BENCH_SEED}) at {n_sample}x{n_sample}, "
                       f"{el:.1f} s on one host core"}
 
 
@@ -50,6 +79,9 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="nodes per direction")
     ap.add_argument("--order", type=int, default=5, choices=(5, 7))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the run, one device-to-device copy of this many MiB (a known-size "
+                         "reference for the HBM byte counters of a profiler pass)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -66,8 +98,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, K, Wu = args.n, args.steps, args.warmup
-    inst = W.quadrants(0, n)
+    inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
     ep = E.problem_from_instance(inst, order=args.order)
     plan = E.enoao_plan_create(ep)
     u0 = torch.from_numpy(inst.u0).cuda()
@@ -107,12 +146,14 @@ def main():
         kernels[kind] = entry
     roof = dict(kernels[best[0]]["roofline"])
     roof["kernel"] = kernels[best[0]].get("symbol") or best[0]
+    workload = f"euler2d-quadrants-{n}x{n}-ao{args.order}"
+    roof["traffic"] = measured_traffic(roof["kernel"], workload)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": Wu,
         "ms_per_step": el * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"euler2d-quadrants-{n}x{n}-ao{args.order}", "nx": n, "ny": n, "order": args.order,
-                   "bc": "periodic", "cfl": 0.3, "seed": 0, "parallelism": "single-gpu"},
+        "config": {"workload": workload, "nx": n, "ny": n, "order": args.order,
+                   "bc": "periodic", "cfl": 0.3, "seed": W.QUADRANT_BENCH_SEED, "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(),
         "kernels": kernels,

@@ -503,13 +503,20 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
     if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps);
     k = std::max(k, 1);
     enoao_status st = ENOAO_OK;
-    for (;;) {
-        if (enoao_status e = rt.run_steps(k, s)) return e;
+    int64_t taken = 0;  // steps known to be taken (host view)
+    while (taken < max_steps) {
+        // never enqueue more steps than the budget left: a partial batch runs eagerly
+        const int64_t left = max_steps - taken;
+        if (left >= k) {
+            if (enoao_status e = rt.run_steps(k, s)) return e;
+        } else {
+            if (enoao_status e = rt.steps((int)left, true, s)) return e;
+        }
         if (enoao_status e = rt.read_ctrl(s)) return e;
         const Ctrl &h = rt.h_ctrl[0];
+        taken = h.steps;
         if (h.status) { st = ENOAO_ENONPHYSICAL; break; }
-        if (h.done) break;
-        if (max_steps == 0) break;
+        if (h.done || !(h.t < t_final)) break;
     }
     const Ctrl &h = rt.h_ctrl[0];
     if (t_out) *t_out = h.t;

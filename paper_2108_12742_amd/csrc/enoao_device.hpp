@@ -14,11 +14,13 @@
 //     table (20 subtractions for order 5 instead of the literal rows); two
 //     candidates whose delta rows coincide share one entry, so their indicators
 //     are bitwise equal as the rows are;
-//   * the two principles are evaluated branch-free as one arg-min over keys
-//     key_k = (IS_k <= delta ? 0 : IS_k) with ties to the higher priority:
-//     when some IS_k <= delta the minimum key is 0 and the highest-priority
-//     such candidate wins (first principle); otherwise the keys are the
-//     indicators (second principle);
+//   * the two principles are evaluated branch-free: candidate k wins over the
+//     candidates below it when IS_k <= delta, or when no lower candidate had
+//     IS <= delta and IS_k <= min(lower IS); the last winner is the choice.
+//     This is the highest-priority candidate with IS <= delta if any, else the
+//     highest-priority one among the smallest indicators;
+//   * only the chosen candidate's flux is evaluated, as a dot product of the
+//     window with that row of the flux table (rows held in LDS);
 //   * a window may be scaled by a power of two before reconstruction (the
 //     factor 1/2 of the splitting is applied after it); scaling by 2^k is
 //     exact, so indicators, comparisons and selections are unchanged when delta
@@ -30,16 +32,99 @@
 
 namespace enoao {
 
+// Wave-uniform early exit: when every lane of the wave has IS <= delta for the
+// highest-priority candidate on both sides of a field, that candidate is every
+// lane's choice (first principle), so the selection logic is skipped.  Each
+// lane's result is bitwise the same as on the full path (same indicators, same
+// row); only the work differs.
+#ifndef ENOAO_EARLY_EXIT
+#define ENOAO_EARLY_EXIT 1
+#endif
+
+// true when the predicate holds on every active lane of the wave (one ballot)
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
+
 template <int ORDER> struct ReconTraits;
 template <> struct ReconTraits<5> { static constexpr int H = 3, K = 6; };
 template <> struct ReconTraits<7> { static constexpr int H = 4, K = 9; };
 
-__device__ __forceinline__ double key_of(double is, double delta) { return is <= delta ? 0.0 : is; }
+// Rows of the table of numerical fluxes (Table "Flux_reconstruction") as
+// weights on the whole window, candidates in increasing priority; row stride
+// TW doubles (16-byte aligned).  The kernels copy the rows to LDS and each lane
+// evaluates only its selected row.
+template <int ORDER> struct FluxRows;
+template <> struct FluxRows<5> {
+    static constexpr int TW = 8;
+    // window f_{j-3} .. f_{j+3}
+    static constexpr double num[6][7] = {
+        {0, 0, 0, 1, 0, 0, 0},        {0, 0, 0, 1, 1, 0, 0},       {0, 0, -1, 5, 2, 0, 0},
+        {0, 1, -5, 13, 3, 0, 0},      {0, 0, -1, 7, 7, -1, 0},     {0, 2, -13, 47, 27, -3, 0}};
+    static constexpr double den[6] = {1, 2, 6, 12, 12, 60};
+};
+template <> struct FluxRows<7> {
+    static constexpr int TW = 10;
+    // window f_{j-4} .. f_{j+4}
+    static constexpr double num[9][9] = {
+        {0, 0, 0, 0, 1, 0, 0, 0, 0},          {0, 0, 0, 0, 1, 1, 0, 0, 0},
+        {0, 0, 0, -1, 5, 2, 0, 0, 0},         {0, 0, 1, -5, 13, 3, 0, 0, 0},
+        {0, 0, 0, -1, 7, 7, -1, 0, 0},        {0, 0, 2, -13, 47, 27, -3, 0, 0},
+        {0, -1, 7, -23, 57, 22, -2, 0, 0},    {0, 0, 1, -8, 37, 37, -8, 1, 0},
+        {0, -3, 25, -101, 319, 214, -38, 4, 0}};
+    static constexpr double den[9] = {1, 2, 6, 12, 12, 60, 60, 60, 420};
+};
 
-// f[0..6] = f_{j-3} .. f_{j+3}; returns fhat^+_{j+1/2}; sel = chosen candidate
-// (0: S_j^j, 1: S_j^{j+1}, 2: S_{j-1}^{j+1}, 3: S_{j-2}^{j+1}, 4: S_{j-1}^{j+2},
-//  5: S_{j-2}^{j+2}).
-__device__ __forceinline__ double recon5(const double (&f)[7], double delta, int &sel)
+// Fill the LDS copy of the flux rows (weights num/den), all threads of a block.
+template <int ORDER> __device__ __forceinline__ void load_flux_rows(double *tab)
+{
+    using R = FluxRows<ORDER>;
+    constexpr int K = ReconTraits<ORDER>::K, W = 2 * ReconTraits<ORDER>::H + 1;
+    for (int i = threadIdx.x; i < K * R::TW; i += blockDim.x) {
+        const int k = i / R::TW, t = i % R::TW;
+        tab[i] = t < W ? R::num[k][t] / R::den[k] : 0.0;
+    }
+}
+
+// Two principles of Section 3.2 on the indicators is[0..K-1] (increasing
+// priority): the highest-priority candidate with IS <= delta if there is one,
+// else the last minimum.  The comparisons produce lane masks; the logic between
+// them stays in scalar registers, the lane's index is one select per candidate.
+template <int K>
+__device__ __forceinline__ int select_candidate(const double (&is)[K], double delta)
+{
+    int s = 0;
+    bool any = is[0] <= delta;
+    double mn = is[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        const bool le = is[k] <= delta;
+        const bool win = le || (!any && is[k] <= mn);
+        s = win ? k : s;
+        any = any || le;
+        mn = fmin(mn, is[k]);
+    }
+    return s;
+}
+
+// selected flux: one row of the table, as a dot product with the window
+template <int W, int TW>
+__device__ __forceinline__ double row_dot(const double (&f)[W], const double *tab, int s)
+{
+    const double *r = tab + s * TW;
+    double q = r[0] * f[0];
+#pragma unroll
+    for (int t = 1; t < W; ++t) q = fma(r[t], f[t], q);
+    return q;
+}
+
+// Indicators of all candidates of one window, in increasing priority.
+// Order 5: f[0..6] = f_{j-3} .. f_{j+3}; candidates 0: S_j^j, 1: S_j^{j+1},
+// 2: S_{j-1}^{j+1}, 3: S_{j-2}^{j+1}, 4: S_{j-1}^{j+2}, 5: S_{j-2}^{j+2}.
+// Order 7: f[0..8] = f_{j-4} .. f_{j+4}; then 6: S_{j-3}^{j+2},
+// 7: S_{j-2}^{j+3}, 8: S_{j-3}^{j+3}.
+// delta_L / delta_R of every candidate are entries of one difference table
+// (level k holds the k-th undivided differences); rows shared by two
+// candidates are one entry.
+__device__ __forceinline__ void indicators5(const double (&f)[7], double (&is)[6])
 {
     const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
     const double a3 = f[4] - f[3], a4 = f[5] - f[4], a5 = f[6] - f[5];
@@ -48,39 +133,15 @@ __device__ __forceinline__ double recon5(const double (&f)[7], double delta, int
     const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
     const double e0 = d1 - d0, e1 = d2 - d1;
     const double ad1 = fabs(d1);
-    double is[6];
     is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
     is[1] = fmin(fabs(b2), fabs(b3));                              // S_j^{j+1}
     is[2] = fmin(fabs(c1), fabs(c2));                              // S_{j-1}^{j+1}
     is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
     is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
     is[5] = fmin(fabs(e0), fabs(e1));                              // S_{j-2}^{j+2}
-    double m = key_of(is[0], delta);
-    int s = 0;
-#pragma unroll
-    for (int k = 1; k < 6; ++k) {
-        const double key = key_of(is[k], delta);
-        if (key <= m) { m = key; s = k; }
-    }
-    const double q1 = 0.5 * (f[3] + f[4]);
-    const double q2 = (fma(5.0, f[3], 2.0 * f[4]) - f[2]) * (1.0 / 6.0);
-    const double q3 = fma(13.0, f[3], fma(3.0, f[4], fma(-5.0, f[2], f[1]))) * (1.0 / 12.0);
-    const double q4 = fma(7.0, f[3] + f[4], -(f[2] + f[5])) * (1.0 / 12.0);
-    const double q5 = fma(47.0, f[3], fma(27.0, f[4], fma(-13.0, f[2], fma(2.0, f[1], -3.0 * f[5])))) *
-                      (1.0 / 60.0);
-    double q = f[3];
-    q = s == 1 ? q1 : q;
-    q = s == 2 ? q2 : q;
-    q = s == 3 ? q3 : q;
-    q = s == 4 ? q4 : q;
-    q = s == 5 ? q5 : q;
-    sel = s;
-    return q;
 }
 
-// f[0..8] = f_{j-4} .. f_{j+4}; candidates 0..5 as recon5, then
-// 6: S_{j-3}^{j+2}, 7: S_{j-2}^{j+3}, 8: S_{j-3}^{j+3}.
-__device__ __forceinline__ double recon7(const double (&f)[9], double delta, int &sel)
+__device__ __forceinline__ void indicators7(const double (&f)[9], double (&is)[9])
 {
     double a[8], b[7], c[6], d[5], e[4], g[3], h[2];
 #pragma unroll
@@ -98,7 +159,6 @@ __device__ __forceinline__ double recon7(const double (&f)[9], double delta, int
 #pragma unroll
     for (int i = 0; i < 2; ++i) h[i] = g[i + 1] - g[i];
     const double ad2 = fabs(d[2]), ag1 = fabs(g[1]);
-    double is[9];
     is[0] = 0.5 * fmin(fabs(a[3]) + fabs(a[2]), fabs(a[4]) + fabs(a[5])); // S_j^j
     is[1] = fmin(fabs(b[3]), fabs(b[4]));                                  // S_j^{j+1}
     is[2] = fmin(fabs(c[2]), fabs(c[3]));                                  // S_{j-1}^{j+1}
@@ -108,48 +168,51 @@ __device__ __forceinline__ double recon7(const double (&f)[9], double delta, int
     is[6] = fmin(fabs(g[0]), ag1);                                         // S_{j-3}^{j+2}
     is[7] = fmin(ag1, fabs(g[2]));                                         // S_{j-2}^{j+3}
     is[8] = fmin(fabs(h[0]), fabs(h[1]));                                  // S_{j-3}^{j+3}
-    double m = key_of(is[0], delta);
-    int s = 0;
-#pragma unroll
-    for (int k = 1; k < 9; ++k) {
-        const double key = key_of(is[k], delta);
-        if (key <= m) { m = key; s = k; }
-    }
-    const double q1 = 0.5 * (f[4] + f[5]);
-    const double q2 = (fma(5.0, f[4], 2.0 * f[5]) - f[3]) * (1.0 / 6.0);
-    const double q3 = fma(13.0, f[4], fma(3.0, f[5], fma(-5.0, f[3], f[2]))) * (1.0 / 12.0);
-    const double q4 = fma(7.0, f[4] + f[5], -(f[3] + f[6])) * (1.0 / 12.0);
-    const double q5 = fma(47.0, f[4], fma(27.0, f[5], fma(-13.0, f[3], fma(2.0, f[2], -3.0 * f[6])))) *
-                      (1.0 / 60.0);
-    const double q6 = fma(57.0, f[4], fma(22.0, f[5], fma(-23.0, f[3], fma(7.0, f[2], fma(-2.0, f[6], -f[1]))))) *
-                      (1.0 / 60.0);
-    const double q7 = fma(37.0, f[4] + f[5], fma(-8.0, f[3] + f[6], f[2] + f[7])) * (1.0 / 60.0);
-    const double q8 = fma(319.0, f[4], fma(214.0, f[5], fma(-101.0, f[3], fma(25.0, f[2],
-                      fma(-38.0, f[6], fma(4.0, f[7], -3.0 * f[1])))))) * (1.0 / 420.0);
-    double q = f[4];
-    q = s == 1 ? q1 : q;
-    q = s == 2 ? q2 : q;
-    q = s == 3 ? q3 : q;
-    q = s == 4 ? q4 : q;
-    q = s == 5 ? q5 : q;
-    q = s == 6 ? q6 : q;
-    q = s == 7 ? q7 : q;
-    q = s == 8 ? q8 : q;
-    sel = s;
-    return q;
 }
 
-template <int ORDER> struct Recon;
-template <> struct Recon<5> {
-    __device__ __forceinline__ static double run(const double (&f)[7], double delta, int &sel)
+template <int ORDER> struct Recon {
+    static constexpr int H = ReconTraits<ORDER>::H, K = ReconTraits<ORDER>::K, W = 2 * H + 1;
+    __device__ __forceinline__ static void indicators(const double (&f)[W], double (&is)[K])
     {
-        return recon5(f, delta, sel);
+        if constexpr (ORDER == 5) indicators5(f, is);
+        else indicators7(f, is);
     }
-};
-template <> struct Recon<7> {
-    __device__ __forceinline__ static double run(const double (&f)[9], double delta, int &sel)
+    // One side of one field: the chosen candidate's value at x_{j+1/2}.  The
+    // wave skips the other indicators and the selection when every lane's top
+    // candidate has IS <= delta.
+    __device__ __forceinline__ static double run(const double (&f)[W], double delta, const double *tab, int &sel)
     {
-        return recon7(f, delta, sel);
+        if constexpr (ORDER == 5) {
+            const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
+            const double a3 = f[4] - f[3], a4 = f[5] - f[4], a5 = f[6] - f[5];
+            const double b0 = a1 - a0, b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3, b4 = a5 - a4;
+            const double c0 = b1 - b0, c1 = b2 - b1, c2 = b3 - b2, c3 = b4 - b3;
+            const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
+            const double e0 = d1 - d0, e1 = d2 - d1;
+            const double is_top = fmin(fabs(e0), fabs(e1));  // S_{j-2}^{j+2}
+            if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
+                sel = 5;
+                return row_dot<W, FluxRows<5>::TW>(f, tab, 5);
+            }
+            const double ad1 = fabs(d1);
+            double is[6];
+            is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
+            is[1] = fmin(fabs(b2), fabs(b3));                              // S_j^{j+1}
+            is[2] = fmin(fabs(c1), fabs(c2));                              // S_{j-1}^{j+1}
+            is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
+            is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
+            is[5] = is_top;
+            sel = select_candidate<6>(is, delta);
+        } else {
+            double is[9];
+            indicators7(f, is);
+            if (ENOAO_EARLY_EXIT && wave_all(is[8] <= delta)) {
+                sel = 8;
+                return row_dot<W, FluxRows<7>::TW>(f, tab, 8);
+            }
+            sel = select_candidate<9>(is, delta);
+        }
+        return row_dot<W, FluxRows<ORDER>::TW>(f, tab, sel);
     }
 };
 
@@ -161,6 +224,18 @@ template <> struct Recon<7> {
 //   Euler 2D : rho, m, n, E | F0..F3 | sqrt(rho), u, v, H
 // (for a y-sweep the two momentum components arrive exchanged, so the same
 //  x-direction formulas give the y-flux in exchanged order).
+// 1/x for positive normal x: hardware reciprocal refined by two Newton steps
+// (within an ulp or so; the kernels' reciprocals and quotients are rounding-level
+// different from IEEE division).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 template <int EQ> struct NodeTraits;
 template <> struct NodeTraits<ADVECTION> { static constexpr int NC = 1, NQ = 1; };
 template <> struct NodeTraits<EULER1D> { static constexpr int NC = 3, NQ = 9; };
@@ -176,7 +251,7 @@ __device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>
         return U[0] == U[0];
     } else if constexpr (EQ == EULER1D) {
         const double rho = U[0], m = U[1], E = U[2];
-        const double ir = 1.0 / rho;
+        const double ir = rcp_nr(rho);
         const double u = m * ir;
         const double p = gm1 * (E - 0.5 * rho * (u * u));
         q[0] = rho; q[1] = m; q[2] = E;
@@ -185,7 +260,7 @@ __device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>
         return rho > 0.0 && p > 0.0;
     } else {
         const double rho = U[0], m = U[1], n = U[2], E = U[3];
-        const double ir = 1.0 / rho;
+        const double ir = rcp_nr(rho);
         const double u = m * ir, v = n * ir;
         const double p = gm1 * (E - 0.5 * rho * fma(u, u, v * v));
         q[0] = rho; q[1] = m; q[2] = n; q[3] = E;
@@ -205,7 +280,7 @@ __device__ __forceinline__ RoeState roe_state(double sL, double uL, double vL, d
                                               double uR, double vR, double HR, double gm1)
 {
     RoeState r;
-    const double iw = 1.0 / (sL + sR);
+    const double iw = rcp_nr(sL + sR);
     const double wL = sL * iw, wR = sR * iw;
     r.u = fma(wL, uL, wR * uR);
     r.v = fma(wL, vL, wR * vR);
@@ -213,7 +288,7 @@ __device__ __forceinline__ RoeState roe_state(double sL, double uL, double vL, d
     r.q2h = 0.5 * fma(r.u, r.u, r.v * r.v);
     const double c2 = gm1 * (r.H - r.q2h);
     r.c = sqrt(c2);
-    r.ic = 1.0 / r.c;
+    r.ic = rcp_nr(r.c);
     r.b1 = gm1 * r.ic * r.ic;
     r.b2 = r.q2h * r.b1;
     return r;

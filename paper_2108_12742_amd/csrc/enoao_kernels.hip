@@ -123,10 +123,73 @@ template <int EQ> struct Maxima {
 // ---------------------------------------------------------------------------
 // One face: window node t (t = 0 .. 2G-1) of face j+1/2 is node j-H+t; the
 // plus side reads nodes j-H .. j+H, the minus side the mirror j+1+H .. j+1-H.
+
+// Characteristic fields F0 (and F1 >= 0) of an Euler face: project U and F of
+// every stencil node (the compiler drops the rows not used by these fields),
+// split, reconstruct both sides.  Taking the fields in two passes halves the
+// live window registers.
+template <int NC, int ORDER, int F0, int F1>
+__device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const RoeState &r, const double *al,
+                                           double delta, const double *tab, double (&wh)[NC], int (&sel)[2 * NC])
+{
+    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1;
+    constexpr int NF = F1 >= 0 ? 2 : 1;
+    constexpr int fs[2] = {F0, F1 >= 0 ? F1 : F0};
+    double gp[NF][W], gm[NF][W];
+    double U[NC], F[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        U[c] = w0[c * qs];
+        F[c] = w0[(NC + c) * qs];
+    }
+#pragma unroll
+    for (int t = 0; t < 2 * G; ++t) {
+        // next node's LDS reads go out before this node's arithmetic
+        double Un[NC], Fn[NC];
+        if (t + 1 < 2 * G) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Un[c] = w0[c * qs + (t + 1) * ns];
+                Fn[c] = w0[(NC + c) * qs + (t + 1) * ns];
+            }
+        }
+        double PU[NC], PF[NC];
+        project<NC>(r, U, PU);
+        project<NC>(r, F, PF);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int s = fs[i];
+            if (t < W) gp[i][t] = fma(al[s], PU[s], PF[s]);
+            if (t >= 1) gm[i][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
+        }
+        if (t + 1 < 2 * G) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                U[c] = Un[c];
+                F[c] = Fn[c];
+            }
+        }
+        // bound the live ranges: at most two nodes' U and F in flight
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const int s = fs[i];
+        // window = 2 * field_scale * w^(+/-)
+        const double sc = 2.0 * field_scale<NC>(s);
+        int sp, sm;
+        const double hp = Recon<ORDER>::run(gp[i], sc * delta, tab, sp);
+        const double hm = Recon<ORDER>::run(gm[i], sc * delta, tab, sm);
+        wh[s] = (hp + hm) * (1.0 / sc);
+        sel[2 * s] = sp;
+        sel[2 * s + 1] = sm;
+    }
+}
+
 template <int EQ, int ORDER>
 __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, const double *al, double gm1,
-                                          double delta, double adv, double (&Fh)[NodeTraits<EQ>::NC],
-                                          int (&sel)[2 * NodeTraits<EQ>::NC])
+                                          double delta, double adv, const double *tab,
+                                          double (&Fh)[NodeTraits<EQ>::NC], int (&sel)[2 * NodeTraits<EQ>::NC])
 {
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1;
     if constexpr (EQ == ADVECTION) {
@@ -140,8 +203,8 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
             if (t >= 1) gm[2 * H + 1 - t] = fma(-al[0], u, au);
         }
         int sp, sm;
-        const double hp = Recon<ORDER>::run(gp, 2.0 * delta, sp);
-        const double hm = Recon<ORDER>::run(gm, 2.0 * delta, sm);
+        const double hp = Recon<ORDER>::run(gp, 2.0 * delta, tab, sp);
+        const double hm = Recon<ORDER>::run(gm, 2.0 * delta, tab, sm);
         Fh[0] = 0.5 * (hp + hm);
         sel[0] = sp;
         sel[1] = sm;
@@ -155,34 +218,13 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
         else
             r = roe_state(nl[QR * qs], nl[(QR + 1) * qs], nl[(QR + 2) * qs], nl[(QR + 3) * qs], nr[QR * qs],
                           nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
-        double gp[NC][W], gm[NC][W];
-#pragma unroll
-        for (int t = 0; t < 2 * G; ++t) {
-            double U[NC], F[NC], PU[NC], PF[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                U[c] = w0[c * qs + t * ns];
-                F[c] = w0[(NC + c) * qs + t * ns];
-            }
-            project<NC>(r, U, PU);
-            project<NC>(r, F, PF);
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                if (t < W) gp[s][t] = fma(al[s], PU[s], PF[s]);
-                if (t >= 1) gm[s][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
-            }
-        }
         double wh[NC];
-#pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            // window = 2 * field_scale * w^(+/-)
-            const double sc = 2.0 * field_scale<NC>(s);
-            int sp, sm;
-            const double hp = Recon<ORDER>::run(gp[s], sc * delta, sp);
-            const double hm = Recon<ORDER>::run(gm[s], sc * delta, sm);
-            wh[s] = (hp + hm) * (1.0 / sc);
-            sel[2 * s] = sp;
-            sel[2 * s + 1] = sm;
+        if constexpr (NC == 4) {
+            field_pass<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, tab, wh, sel);
+            field_pass<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, tab, wh, sel);
+        } else {
+            field_pass<3, ORDER, 0, 2>(w0, qs, ns, r, al, delta, tab, wh, sel);
+            field_pass<3, ORDER, 1, -1>(w0, qs, ns, r, al, delta, tab, wh, sel);
         }
         back_project<NC>(r, wh, Fh);
     }
@@ -226,8 +268,69 @@ template <int MODE> __device__ __forceinline__ double *stage_out(const Inst &I)
 
 // ---------------------------------------------------------------------------
 // x-sweep.  Each wave: one segment of a grid line (64 faces, 63 cells).
+// Tiles are software-pipelined: the global operands of tile t+1 are loaded into
+// registers while tile t is reconstructed, so the memory latency hides behind
+// the face arithmetic.
+#ifndef ENOAO_SWEEP_WAVES_PER_EU
+#define ENOAO_SWEEP_WAVES_PER_EU 1
+#endif
+
+struct XSeg {
+    int k;        // instance
+    bool ok;      // this wave has a segment in the tile
+    bool active;  // the instance is still stepping (uniform over the tile)
+    int row, sx;  // grid line and first cell of the segment
+};
+
+__device__ __forceinline__ XSeg x_segment(const KParams &P, int n_inst, long long tile, int wseg)
+{
+    XSeg g;
+    g.k = find_inst<true>(P.inst, n_inst, tile);
+    const Inst &I = P.inst[g.k];
+    const long long seg = (tile - I.xtile0) * XW_SEGS + wseg;
+    g.ok = seg < (long long)I.ny * I.segs_per_row;
+    g.row = g.ok ? (int)(seg / I.segs_per_row) : 0;
+    g.sx = g.ok ? (int)(seg % I.segs_per_row) * XW_CELLS : 0;
+    g.active = I.ctrl->done == 0;
+    return g;
+}
+
+// a lane's global operands of one x tile: the nodes it stages (segment
+// positions lane and lane + 64) and, for a 1D stage 2 or 3, u^n at its cell
+template <int NC> struct XPre {
+    double U[2][NC];
+    double base[NC];
+};
+
+template <int EQ, int MODE, int G>
+__device__ __forceinline__ void x_prefetch(const Inst &I, const XSeg &g, int lane, XPre<NodeTraits<EQ>::NC> &pre)
+{
+    constexpr int NC = NodeTraits<EQ>::NC, NN = XW_FACES + 2 * G - 1;
+    if (!g.ok || !g.active) return;
+    const int nx = I.nx;
+    const long long plane = (long long)nx * I.ny;
+    const double *rowp = stage_in<MODE>(I) + (long long)g.row * nx;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = lane + 64 * j;
+        if (i < NN) {
+            const int x = bc_map(g.sx - G + i, nx, I.bcx);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pre.U[j][c] = rowp[c * plane + x];
+        }
+    }
+    if constexpr (EQ != EULER2D && (MODE == M_S2 || MODE == M_S3)) {
+        const int x = g.sx + lane;
+        if (lane < XW_CELLS && x < nx) {
+            const double *b = I.u + (long long)g.row * nx + x;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pre.base[c] = b[c * plane];
+        }
+    }
+}
+
 template <int EQ, int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) void sweep_x(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWEEP_WAVES_PER_EU))) void sweep_x(KParams P)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
@@ -237,6 +340,9 @@ __global__ __launch_bounds__(BLOCK) void sweep_x(KParams P)
     __shared__ double lds[NQ * XW_SEGS * NNP];
     __shared__ double fh[NC * XW_SEGS * XW_FACES];
     __shared__ double red[(BLOCK / 64) * 8];
+    __shared__ __attribute__((aligned(16))) double ftab[ReconTraits<ORDER>::K * FluxRows<ORDER>::TW];
+    load_flux_rows<ORDER>(ftab);
+    __syncthreads();
 
     const int tid = threadIdx.x, wseg = tid >> 6, lane = tid & 63;
     const int n_inst = P.hdr->n_inst;
@@ -245,54 +351,61 @@ __global__ __launch_bounds__(BLOCK) void sweep_x(KParams P)
     Maxima<EQ> mx;
     mx.reset();
     int cur = -1;
+    XPre<NC> pre;
+    if (t0 < t1) {
+        const XSeg g0 = x_segment(P, n_inst, t0, wseg);
+        x_prefetch<EQ, MODE, G>(P.inst[g0.k], g0, lane, pre);
+    }
 
     for (long long tile = t0; tile < t1; ++tile) {
-        const int k = find_inst<true>(P.inst, n_inst, tile);
-        const Inst &I = P.inst[k];
-        if (FULL && k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
-        cur = k;
-        if (I.ctrl->done) continue;
-        if (MODE != M_RHS && P.r_zero >= 0 && tile == I.xtile0 && tid < AMAX_VALS)
+        const XSeg g = x_segment(P, n_inst, tile, wseg);
+        const Inst &I = P.inst[g.k];
+        if (FULL && g.k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
+        cur = g.k;
+        if (g.active && MODE != M_RHS && P.r_zero >= 0 && tile == I.xtile0 && tid < AMAX_VALS)
             I.amax[P.r_zero * AMAX_VALS + tid] = 0ull;
+
+        // stage this tile's nodes (flux, Roe inputs) into LDS
+        double *L = lds + wseg * NNP;
+        if (g.active && g.ok) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int i = lane + 64 * j;
+                if (i < NN) {
+                    double q[NQ];
+                    node_quantities<EQ>(pre.U[j], P.gm1, q);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) L[m * XW_SEGS * NNP + i] = q[m];
+                }
+            }
+        }
+        double base[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) base[c] = pre.base[c];
+        // issue the next tile's loads before this tile's arithmetic
+        if (tile + 1 < t1) {
+            const XSeg gn = x_segment(P, n_inst, tile + 1, wseg);
+            x_prefetch<EQ, MODE, G>(P.inst[gn.k], gn, lane, pre);
+        }
+        if (!g.active) continue;  // uniform: all waves of a tile belong to one instance
+        __syncthreads();
 
         const int nx = I.nx, ny = I.ny;
         const long long plane = (long long)nx * ny;
-        const long long seg = (tile - I.xtile0) * XW_SEGS + wseg;
-        const bool seg_ok = seg < (long long)ny * I.segs_per_row;
-        const int row = seg_ok ? (int)(seg / I.segs_per_row) : 0;
-        const int sx = seg_ok ? (int)(seg % I.segs_per_row) * XW_CELLS : 0;
-        const double *in = stage_in<MODE>(I);
-        const double *rowp = in + (long long)row * nx;
-        double *L = lds + wseg * NNP;
-
-        // stage nodes sx-G .. sx+63+G-1 of the segment
-        if (seg_ok) {
-            for (int i = lane; i < NN; i += 64) {
-                const int x = bc_map(sx - G + i, nx, I.bcx);
-                double U[NC], q[NQ];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) U[c] = rowp[c * plane + x];
-                node_quantities<EQ>(U, P.gm1, q);
-#pragma unroll
-                for (int j = 0; j < NQ; ++j) L[j * XW_SEGS * NNP + i] = q[j];
-            }
-        }
-        __syncthreads();
-
         double al[NC];
         load_alpha<EQ>(I, P.r_in, false, al);
-        const int f = sx + lane;  // face index along the line
-        if (seg_ok) {
+        const int f = g.sx + lane;  // face index along the line
+        if (g.ok) {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, al, P.gm1, P.delta, I.adv, Fh, sel);
+            face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, al, P.gm1, P.delta, I.adv, ftab, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fh[(c * XW_SEGS + wseg) * XW_FACES + lane] = Fh[c];
             if (REC && I.sel && f <= nx) {
                 const long long xblock = (long long)ny * (nx + 1);
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
-                    const long long o = (long long)(2 * s) * xblock + (long long)row * (nx + 1) + f;
+                    const long long o = (long long)(2 * s) * xblock + (long long)g.row * (nx + 1) + f;
                     I.sel[o] = (uint8_t)sel[2 * s];
                     I.sel[o + xblock] = (uint8_t)sel[2 * s + 1];
                 }
@@ -300,10 +413,10 @@ __global__ __launch_bounds__(BLOCK) void sweep_x(KParams P)
         }
         __syncthreads();
 
-        const int x = sx + lane;
-        if (seg_ok && lane < XW_CELLS && x < nx) {
+        const int x = g.sx + lane;
+        if (g.ok && lane < XW_CELLS && x < nx) {
             const double idx = -1.0 / I.dx;
-            const long long o = (long long)row * nx + x;
+            const long long o = (long long)g.row * nx + x;
             double Lc[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -318,8 +431,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_x(KParams P)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const double uin = L[c * XW_SEGS * NNP + lane + G];
-                    const double base = MODE == M_S1 ? 0.0 : I.u[c * plane + o];
-                    Un[c] = rk_combine<MODE>(uin, base, dt, Lc[c]);
+                    Un[c] = rk_combine<MODE>(uin, base[c], dt, Lc[c]);
                     out[c * plane + o] = Un[c];
                 }
                 mx.add(Un, P.gamma, I.dx, I.dy);
@@ -333,8 +445,66 @@ __global__ __launch_bounds__(BLOCK) void sweep_x(KParams P)
 // ---------------------------------------------------------------------------
 // y-sweep (2D).  A workgroup: 16 columns x 16 faces along y, 16 x 15 cells.
 // Momentum components are exchanged on load so the x-direction formulas apply.
+// Pipelined like the x-sweep; the epilogue operands (x-part of L, u^n) are
+// prefetched with the nodes.
+struct YTile {
+    int k;
+    bool active;
+    int sy, col0;  // first cell row, first column
+};
+
+__device__ __forceinline__ YTile y_tile(const KParams &P, int n_inst, long long tile)
+{
+    YTile t;
+    t.k = find_inst<false>(P.inst, n_inst, tile);
+    const Inst &I = P.inst[t.k];
+    const long long tl = tile - I.ytile0;
+    t.sy = (int)(tl % I.ytiles_per_row) * YT_CELLS;
+    t.col0 = (int)(tl / I.ytiles_per_row) * YT_COLS;
+    t.active = I.ctrl->done == 0;
+    return t;
+}
+
+struct YPre {
+    double U[2][4];
+    double lx[4], base[4];
+};
+
+template <int MODE, int G>
+__device__ __forceinline__ void y_prefetch(const Inst &I, const YTile &t, int tid, YPre &pre)
+{
+    constexpr int NR = YT_FACES + 2 * G - 1;
+    const int perm[4] = {0, 2, 1, 3};
+    if (!t.active) return;
+    const int nx = I.nx, ny = I.ny;
+    const long long plane = (long long)nx * ny;
+    const double *in = stage_in<MODE>(I);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = tid + BLOCK * j;
+        if (i < NR * YT_COLS) {
+            const int r = i / YT_COLS, c0 = i % YT_COLS;
+            const int y = bc_map(t.sy - G + r, ny, I.bcy);
+            const int x = min(t.col0 + c0, nx - 1);
+            const double *p = in + (long long)y * nx + x;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pre.U[j][c] = p[perm[c] * plane];
+        }
+    }
+    const int fl = tid / YT_COLS, y = t.sy + fl, col = t.col0 + (tid & (YT_COLS - 1));
+    if (fl < YT_CELLS && y < ny && col < nx) {
+        const long long o = (long long)y * nx + col;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pre.lx[c] = I.lx[c * plane + o];
+        if constexpr (MODE == M_S2 || MODE == M_S3) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pre.base[c] = I.u[c * plane + o];
+        }
+    }
+}
+
 template <int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) void sweep_y(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWEEP_WAVES_PER_EU))) void sweep_y(KParams P)
 {
     constexpr int NC = 4, NQ = 12;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
@@ -343,7 +513,15 @@ __global__ __launch_bounds__(BLOCK) void sweep_y(KParams P)
     __shared__ double lds[NQ * QS];
     __shared__ double fh[NC * YT_FACES * YT_COLS];
     __shared__ double red[(BLOCK / 64) * 8];
+    __shared__ __attribute__((aligned(16))) double ftab[ReconTraits<ORDER>::K * FluxRows<ORDER>::TW];
+    // epilogue operands of the tile (x-part of L, u^n), staged from the prefetch
+    // registers so they are not held through the face arithmetic
+    constexpr bool BASE = MODE == M_S2 || MODE == M_S3;
+    __shared__ double elx[NC * BLOCK];
+    __shared__ double ebase[BASE ? NC * BLOCK : 1];
     const int perm[4] = {0, 2, 1, 3};
+    load_flux_rows<ORDER>(ftab);
+    __syncthreads();
 
     const int tid = threadIdx.x, cc = tid & (YT_COLS - 1), fl = tid / YT_COLS;
     const int n_inst = P.hdr->n_inst;
@@ -352,42 +530,53 @@ __global__ __launch_bounds__(BLOCK) void sweep_y(KParams P)
     Maxima<EULER2D> mx;
     mx.reset();
     int cur = -1;
+    YPre pre;
+    if (t0 < t1) {
+        const YTile y0 = y_tile(P, n_inst, t0);
+        y_prefetch<MODE, G>(P.inst[y0.k], y0, tid, pre);
+    }
 
     for (long long tile = t0; tile < t1; ++tile) {
-        const int k = find_inst<false>(P.inst, n_inst, tile);
-        const Inst &I = P.inst[k];
-        if (MODE != M_RHS && k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
-        cur = k;
-        if (I.ctrl->done) continue;
+        const YTile t = y_tile(P, n_inst, tile);
+        const Inst &I = P.inst[t.k];
+        if (MODE != M_RHS && t.k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
+        cur = t.k;
+
+        if (t.active) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int i = tid + BLOCK * j;
+                if (i < NR * YT_COLS) {
+                    double q[NQ];
+                    node_quantities<EULER2D>(pre.U[j], P.gm1, q);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) lds[m * QS + i] = q[m];
+                }
+            }
+        }
+        if (t.active) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                elx[c * BLOCK + tid] = pre.lx[c];
+                if constexpr (BASE) ebase[c * BLOCK + tid] = pre.base[c];
+            }
+        }
+        if (tile + 1 < t1) {
+            const YTile tn = y_tile(P, n_inst, tile + 1);
+            y_prefetch<MODE, G>(P.inst[tn.k], tn, tid, pre);
+        }
+        if (!t.active) continue;
+        __syncthreads();
 
         const int nx = I.nx, ny = I.ny;
         const long long plane = (long long)nx * ny;
-        const long long tl = tile - I.ytile0;
-        const int cg = (int)(tl / I.ytiles_per_row), rs = (int)(tl % I.ytiles_per_row);
-        const int sy = rs * YT_CELLS, col0 = cg * YT_COLS;
-        const double *in = stage_in<MODE>(I);
-
-        for (int i = tid; i < NR * YT_COLS; i += BLOCK) {
-            const int r = i / YT_COLS, c0 = i % YT_COLS;
-            const int y = bc_map(sy - G + r, ny, I.bcy);
-            const int x = min(col0 + c0, nx - 1);
-            const double *p = in + (long long)y * nx + x;
-            double U[NC], q[NQ];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) U[c] = p[perm[c] * plane];
-            node_quantities<EULER2D>(U, P.gm1, q);
-#pragma unroll
-            for (int j = 0; j < NQ; ++j) lds[j * QS + i] = q[j];
-        }
-        __syncthreads();
-
         double al[NC];
         load_alpha<EULER2D>(I, P.r_in, true, al);
-        const int col = col0 + cc, f = sy + fl;
+        const int col = t.col0 + cc, f = t.sy + fl;
         {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EULER2D, ORDER>(lds + fl * YT_COLS + cc, QS, YT_COLS, al, P.gm1, P.delta, 0.0, Fh, sel);
+            face_flux<EULER2D, ORDER>(lds + fl * YT_COLS + cc, QS, YT_COLS, al, P.gm1, P.delta, 0.0, ftab, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fh[(c * YT_FACES + fl) * YT_COLS + cc] = Fh[c];
             if (REC && I.sel && col < nx && f <= ny) {
@@ -403,7 +592,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_y(KParams P)
         }
         __syncthreads();
 
-        const int y = sy + fl;
+        const int y = t.sy + fl;
         if (fl < YT_CELLS && y < ny && col < nx) {
             const double idy = -1.0 / I.dy;
             const long long o = (long long)y * nx + col;
@@ -413,7 +602,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_y(KParams P)
                 Ly[perm[c]] = (fh[(c * YT_FACES + fl + 1) * YT_COLS + cc] - fh[(c * YT_FACES + fl) * YT_COLS + cc]) * idy;
             if constexpr (MODE == M_RHS) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) I.lx[c * plane + o] = I.lx[c * plane + o] + Ly[c];
+                for (int c = 0; c < NC; ++c) I.lx[c * plane + o] = elx[c * BLOCK + tid] + Ly[c];
             } else {
                 const double dt = I.ctrl->dt;
                 double *out = stage_out<MODE>(I);
@@ -421,9 +610,8 @@ __global__ __launch_bounds__(BLOCK) void sweep_y(KParams P)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const double uin = lds[perm[c] * QS + (fl + G) * YT_COLS + cc];
-                    const double base = MODE == M_S1 ? 0.0 : I.u[c * plane + o];
-                    const double Lc = I.lx[c * plane + o] + Ly[c];
-                    Un[c] = rk_combine<MODE>(uin, base, dt, Lc);
+                    const double base = BASE ? ebase[c * BLOCK + tid] : 0.0;
+                    Un[c] = rk_combine<MODE>(uin, base, dt, elx[c * BLOCK + tid] + Ly[c]);
                     out[c * plane + o] = Un[c];
                 }
                 mx.add(Un, P.gamma, I.dx, I.dy);

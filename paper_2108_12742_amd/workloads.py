@@ -33,6 +33,12 @@ import numpy as np
 
 GAMMA = 1.4
 
+# Seed of the 2D quadrant benchmark problem.  The draw of seed 0 (three cold,
+# hypersonic quadrants colliding) drives the fifth-order scheme to a negative
+# pressure within a few steps on every grid tried, in the CPU oracle as on the
+# GPU; seed 1 is the first draw the scheme advances cleanly.
+QUADRANT_BENCH_SEED = 1
+
 
 @dataclass
 class Instance:

@@ -240,7 +240,7 @@ def test_c2_full_size_rhs():
     evaluation of L against the oracle, with the launch configuration of the benchmark."""
     torch = PT.torch_cuda()
     E = _E()
-    inst = W.quadrants(0, 2048)
+    inst = W.quadrants(W.QUADRANT_BENCH_SEED, 2048)
     ep = E.problem_from_instance(inst, record_selection=True)
     op = PT.oracle_problem(ep)
     plan = E.enoao_plan_create(ep)

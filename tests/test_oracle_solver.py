@@ -357,3 +357,18 @@ def test_seeded_riemann_against_exact():
         ex = RX.sample(inst.meta["left"], inst.meta["right"], W.nodes(0.0, 1.0, 200), inst.meta["x0"], t)
         assert np.isfinite(u).all()
         assert np.abs(u[0, 0] - ex[0]).mean() < 0.05 * max(ex[0].max(), 1.0)
+
+
+def test_quadrant_bench_seed_is_physical():
+    """The benchmark's quadrant draw is advanced by the oracle without a non-physical state
+    (40 steps at 128^2, the physical time of several hundred steps at 2048^2), while the
+    draw of seed 0 is not."""
+    p = O.Problem(O.EULER2D, nx=128, ny=128)
+    u = W.quadrants(W.QUADRANT_BENCH_SEED, 128).u0
+    for _ in range(40):
+        u = O.step(p, u, O.cfl_dt(p, u, 0.3))
+    assert np.isfinite(u).all()
+    u = W.quadrants(0, 128).u0
+    with pytest.raises(O.OracleError):
+        for _ in range(10):
+            u = O.step(p, u, O.cfl_dt(p, u, 0.3))
