@@ -71,6 +71,106 @@ def cpu_baseline(n_sample=512, steps=2):
                       f"{el:.1f} s on one host core"}
 
 
+def bench_batched(steps=100, warmup=2, count=512):
+    """Batched workload: `count` 1D Euler Riemann instances, N ~ LogUniform[128, 16384],
+    `steps` CFL steps each (own dt per member), in one persistent launch per stage
+    (graph-captured), against the same solves launched one plan at a time."""
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import roofline as R
+    from paper_2108_12742_amd import tune as T
+    from paper_2108_12742_amd import workloads as W
+    insts = W.batch_1d(0, count)
+    probs = [E.problem_from_instance(i) for i in insts]
+    u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
+    states = [u.clone() for u in u0]
+    best, timing = T.tune_batch(probs, states, steps=3)
+    batch = E.enoao_batch_create(probs)
+    E.enoao_batch_set_launch(batch, best)
+    E.enoao_batch_step(batch, states, warmup, 0.3)
+    E.enoao_batch_destroy(batch)
+    batch = E.enoao_batch_create(probs)
+    E.enoao_batch_set_launch(batch, best)
+    for u, v in zip(states, u0):
+        u.copy_(v)
+    torch.cuda.synchronize()
+    E.enoao_batch_profile(batch, True)
+    t0 = time.perf_counter()
+    E.enoao_batch_step(batch, states, steps, 0.3)
+    _, nst, status = E.enoao_batch_query(batch)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = E.enoao_batch_profile_read(batch)
+    cells = sum(int(p.nx) for p in probs)
+    # plain: one plan per instance, solved one after another on the same stream
+    plans = [E.enoao_plan_create(p) for p in probs]
+    plain = [u.clone() for u in u0]
+    for pl, u, v in zip(plans, plain, u0):  # graph capture and first touch, untimed
+        E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=warmup)
+        u.copy_(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, u in zip(plans, plain):
+        E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=steps)
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t0
+    identical = all(torch.equal(a, b) for a, b in zip(states, plain))
+    ms, kind = max(((prof[k][0], k) for k in ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3")), key=lambda x: x[0])
+    stage = int(kind[-1])
+    roof = R.roofline_entry(cells * R.sweep_flops("euler1d", 5, "x", stage), cells * R.sweep_bytes("euler1d", "x", stage),
+                            ms * 1e-3)
+    roof["kernel"] = f"enoao::sweep_x<1, 5, {stage}, false>"
+    return {"workload": f"euler1d-riemann-batch{count}-{cells}cells-ao5", "members": count, "cells": cells, "steps": steps,
+            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+            "plain_value": cells * steps / el_plain, "speedup_vs_plain": el_plain / el,
+            "identical_to_plain": identical, "members_ok": int((status == 0).sum()),
+            "workgroups_per_cu": best, "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()},
+            "roofline": roof}
+
+
+def bench_served(requests=200, nsteps=50, rates=(0.5, 0.9), arena_gib=4.0):
+    """Served workload: Poisson arrivals of 2D Euler quadrant solves, N x N with
+    N ~ U{128..1024}, `nsteps` steps each, admitted into a device pool by arena
+    footprint; p50/p99 latency per arrival rate (fractions of the saturated rate)."""
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import serve as S
+    from paper_2108_12742_amd import workloads as W
+    t_arr, sizes, _ = W.arrivals(1, requests, 1.0)
+    # every request is the four-quadrant problem of the main workload at its own size
+    data = [W.quadrants(W.QUADRANT_BENCH_SEED, int(n)) for n in sizes]
+    probs = [E.problem_from_instance(d) for d in data]
+    like = probs[0]
+    arena = int(arena_gib * (1 << 30))
+
+    def server():
+        return S.Server(S.GpuPoolBackend(like, max_members=256, arena_bytes=arena), steps_per_round=1)
+
+    # saturated: every request submitted at once
+    srv = server()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, d in zip(probs, data):
+        srv.submit(p, d.u0, nsteps)
+    done = srv.drain()
+    sat_s = time.perf_counter() - t0
+    sat_rate = requests / sat_s
+    total_cu = sum(int(p.nx) * int(p.ny) for p in probs) * nsteps
+    out = {"workload": f"euler2d-served-{requests}req-{nsteps}steps-N128..1024-ao5", "requests": requests,
+           "saturated": {"requests_per_s": sat_rate, "cell_updates_per_s": total_cu / sat_s,
+                         "failed": sum(r.status != 0 for r in done)}, "rates": []}
+    for f in rates:
+        rate = f * sat_rate
+        arr = t_arr / t_arr[-1] * (requests - 1) / rate if requests > 1 else t_arr
+        srv = server()
+        reqs, wall = S.run_arrivals(srv, arr, lambda i: (probs[i], data[i].u0, nsteps))
+        st = S.latency_stats(reqs)
+        st.update({"rate_fraction": f, "requests_per_s": rate, "cell_updates_per_s": total_cu / wall,
+                   "failed": sum(r.status != 0 for r in reqs)})
+        out["rates"].append(st)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +179,9 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="nodes per direction")
     ap.add_argument("--order", type=int, default=5, choices=(5, 7))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (512 1D members, batched vs plain) and served (Poisson arrivals) legs")
+    ap.add_argument("--served-requests", type=int, default=120)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
@@ -159,6 +262,10 @@ def main():
         "kernels": kernels,
         "flops_per_cell_update": R.cell_update_flops("euler2d", args.order),
     }
+    del plan, u, u0
+    if not args.no_extras:
+        out["batched"] = bench_batched()
+        out["served"] = bench_served(requests=args.served_requests)
     print(json.dumps(out), flush=True)
 
 

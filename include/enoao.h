@@ -95,6 +95,7 @@ typedef struct enoao_problem {
 
 typedef struct enoao_plan enoao_plan;
 typedef struct enoao_batch enoao_batch;
+typedef struct enoao_pool enoao_pool;
 
 /* Validates *prob, allocates the plan's device workspace on the current HIP
  * device and returns the plan in *out.  stream: used for initialisation. */
@@ -165,6 +166,42 @@ enoao_status enoao_batch_reset(enoao_batch *batch, void *stream);
 enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, int32_t *member_status,
                                void *stream);
 
+/* ---- pools: members that join and leave between steps --------------------
+ * A pool advances a changing set of problems of one equation, order, gamma
+ * and delta (those of *like) with the batched kernels.  Member states and
+ * stage workspaces live in one device arena of arena_bytes owned by the pool;
+ * the step graph is captured once and stays valid as members come and go.
+ * Intended for serving loops: admit requests as memory frees up, step, poll,
+ * retire finished ones.
+ *
+ * enoao_pool_member_bytes: arena bytes a member needs (0 if invalid).
+ * enoao_pool_admit: copies the initial state u0 (host memory if u0_on_host,
+ *   else device memory) into the arena; the member runs CFL steps (cfl > 0)
+ *   until t_final or max_steps.  *slot_out receives its slot (0..max_members-1).
+ *   ENOAO_ENOMEM: no free slot or no arena space now (retry after a retire);
+ *   ENOAO_EINVAL: bad arguments, or the member can never fit the arena.
+ * enoao_pool_step: advances every active member by up to nsteps steps (a
+ *   member that has finished is skipped).  Members admitted since the last
+ *   step take alpha and their first step from their current state.
+ * enoao_pool_poll: synchronises stream; per slot (arrays of max_members):
+ *   done (1 finished, 0 running, -1 free slot), status (non-zero: non-
+ *   physical state), steps taken, time reached.
+ * enoao_pool_retire: copies the member's state to u_out (host or device, may
+ *   be NULL), synchronises stream and frees the slot and its arena space.
+ * A member's result does not depend on the other members of the pool. */
+size_t enoao_pool_member_bytes(const enoao_problem *prob);
+enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, size_t arena_bytes, void *stream,
+                               enoao_pool **out);
+enoao_status enoao_pool_destroy(enoao_pool *pool);
+enoao_status enoao_pool_set_launch(enoao_pool *pool, int32_t workgroups_per_cu);
+enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const double *u0, int32_t u0_on_host,
+                              double t_final, int64_t max_steps, double cfl, int32_t *slot_out, void *stream);
+enoao_status enoao_pool_step(enoao_pool *pool, int32_t nsteps, void *stream);
+enoao_status enoao_pool_poll(enoao_pool *pool, int32_t *done, int32_t *status, int64_t *steps, double *t,
+                             int32_t n, void *stream);
+enoao_status enoao_pool_retire(enoao_pool *pool, int32_t slot, double *u_out, int32_t u_out_on_host, void *stream);
+enoao_status enoao_pool_usage(const enoao_pool *pool, size_t *arena_used, size_t *arena_total, int32_t *members);
+
 /* ---- per-kernel timing -------------------------------------------------
  * enoao_profile(plan, 1): subsequent enoao_step / enoao_solve calls launch
  * eagerly (no graph replay) and record a hipEvent pair around every kernel on
@@ -179,8 +216,16 @@ enoao_status enoao_batch_profile(enoao_batch *batch, int32_t enable);
 enoao_status enoao_batch_profile_read(enoao_batch *batch, double *avg_ms, int64_t *count, int32_t n_kinds,
                                       void *stream);
 
-/* Tuning knobs of the persistent launches (0 = library default). */
+/* Launch shape of the persistent sweeps: workgroups resident per CU
+ * (1..64; 0 = the occupancy the compiler's register and LDS use allow).
+ * enoao_set_launch sets the default for plans and batches created afterwards
+ * (reserved must be 0); the per-object calls change an existing plan or batch
+ * (its captured graph is rebuilt on the next call).  Results do not depend on
+ * the launch shape: every tile is computed the same way whichever workgroup
+ * runs it. */
 enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved);
+enoao_status enoao_plan_set_launch(enoao_plan *plan, int32_t workgroups_per_cu);
+enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_cu);
 
 const char *enoao_status_string(enoao_status status);
 

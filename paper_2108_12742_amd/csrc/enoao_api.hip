@@ -73,6 +73,7 @@ size_t member_fixed_bytes() { return sizeof(Inst) + sizeof(Ctrl) + AMAX_SLOTS * 
 // A runtime = a batch of members sharing equation and order (a plan is one member).
 struct Runtime {
     int eq = 0, order = 5, nc = 1, n = 0;
+    int n_cap = 0;   // members the control and reset launches cover (>= n)
     double gamma = 1.4, delta = 1e-5;
     bool rec = false;
     int device = 0, cus = 256;
@@ -91,6 +92,7 @@ struct Runtime {
     int graph_k = 0;
     hipStream_t cap = nullptr;
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
+    int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
     // optional per-kernel timing: hipEvents recorded around every launch, on the
     // stream the kernel is launched on (eager launches, no graph)
     bool profiling = false;
@@ -145,10 +147,11 @@ struct Runtime {
         return p;
     }
 
+    bool dynamic = false;  // pool: the tile totals change, grids cover the whole machine
     int grid_for(long long tiles, int occ) const
     {
-        const int per_cu = g_wg_per_cu > 0 ? g_wg_per_cu : occ;
-        const long long g = std::min<long long>(tiles, (long long)cus * per_cu);
+        const int per_cu = wg_per_cu > 0 ? wg_per_cu : occ;
+        const long long g = dynamic ? (long long)cus * per_cu : std::min<long long>(tiles, (long long)cus * per_cu);
         return (int)std::max<long long>(g, 1);
     }
 
@@ -164,6 +167,7 @@ struct Runtime {
         order = ps[0].order;
         nc = ncomp_of(eq);
         n = count;
+        n_cap = count;
         gamma = ps[0].gamma;
         delta = ps[0].delta;
         rec = (ps[0].flags & ENOAO_F_RECORD_SELECTION) != 0;
@@ -201,34 +205,11 @@ struct Runtime {
         h_inst.resize(count);
         long long xt = 0, yt = 0;
         for (int i = 0; i < count; ++i) {
-            const enoao_problem &p = ps[i];
-            Inst &I = h_inst[i];
-            std::memset(&I, 0, sizeof(I));
-            const size_t cells = (size_t)nc * p.nx * p.ny;
             double *m = (double *)(base + o_mem[i]);
-            I.u = nullptr;
-            I.w1 = m;
-            I.w2 = m + cells;
-            I.lx = eq == EULER2D ? m + 2 * cells : nullptr;
-            I.sel = rec ? (uint8_t *)(m + (eq == EULER2D ? 3 : 2) * cells) : nullptr;
-            I.amax = d_amax + (size_t)i * AMAX_SLOTS * AMAX_VALS;
-            I.ctrl = d_ctrl + i;
-            I.nx = p.nx;
-            I.ny = p.ny;
-            I.bcx = p.bc_x;
-            I.bcy = eq == EULER2D ? p.bc_y : BC_PERIODIC;
-            I.dx = (p.x_hi - p.x_lo) / p.nx;
-            I.dy = eq == EULER2D ? (p.y_hi - p.y_lo) / p.ny : 1.0;
-            I.adv = p.adv_speed;
-            I.segs_per_row = (p.nx + XW_CELLS - 1) / XW_CELLS;
-            I.ytiles_per_row = (p.ny + YT_CELLS - 1) / YT_CELLS;
-            I.ycol_groups = (p.nx + YT_COLS - 1) / YT_COLS;
-            I.xtile0 = xt;
-            I.xtiles = ((long long)p.ny * I.segs_per_row + XW_SEGS - 1) / XW_SEGS;
-            I.ytile0 = yt;
-            I.ytiles = eq == EULER2D ? (long long)I.ytiles_per_row * I.ycol_groups : 0;
-            xt += I.xtiles;
-            yt += I.ytiles;
+            const size_t cells = (size_t)nc * ps[i].nx * ps[i].ny;
+            fill_inst(h_inst[i], ps[i], nullptr, m, m + cells, eq == EULER2D ? m + 2 * cells : nullptr,
+                      rec ? (uint8_t *)(m + (eq == EULER2D ? 3 : 2) * cells) : nullptr,
+                      d_amax + (size_t)i * AMAX_SLOTS * AMAX_VALS, d_ctrl + i, xt, yt);
         }
         h_hdr.n_inst = count;
         h_hdr.xtiles_total = xt;
@@ -245,13 +226,62 @@ struct Runtime {
         HIP_TRY(hipMemcpyAsync(d_ctrl, c0.data(), sizeof(Ctrl) * count, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
 
-        for (int m = 0; m < 4; ++m) {
-            grid_x[m] = grid_for(xt, occupancy_x(eq, order, m, false));
-            if (eq == EULER2D) grid_y[m] = grid_for(yt, occupancy_y(order, m, false));
-        }
-        grid_m = grid_for(xt, occupancy_maxima(eq));
+        wg_per_cu = g_wg_per_cu;
+        set_grids();
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         return ENOAO_OK;
+    }
+
+    // descriptor of one member; advances the running tile offsets
+    void fill_inst(Inst &I, const enoao_problem &p, double *u, double *w1, double *w2, double *lx, uint8_t *sel,
+                   unsigned long long *amax, Ctrl *ctrl, long long &xt, long long &yt) const
+    {
+        std::memset(&I, 0, sizeof(I));
+        I.u = u;
+        I.w1 = w1;
+        I.w2 = w2;
+        I.lx = lx;
+        I.sel = sel;
+        I.amax = amax;
+        I.ctrl = ctrl;
+        I.nx = p.nx;
+        I.ny = p.ny;
+        I.bcx = p.bc_x;
+        I.bcy = eq == EULER2D ? p.bc_y : BC_PERIODIC;
+        I.dx = (p.x_hi - p.x_lo) / p.nx;
+        I.dy = eq == EULER2D ? (p.y_hi - p.y_lo) / p.ny : 1.0;
+        I.adv = p.adv_speed;
+        I.segs_per_row = (p.nx + XW_CELLS - 1) / XW_CELLS;
+        I.ytiles_per_row = (p.ny + YT_CELLS - 1) / YT_CELLS;
+        I.ycol_groups = (p.nx + YT_COLS - 1) / YT_COLS;
+        I.xtile0 = xt;
+        I.xtiles = ((long long)p.ny * I.segs_per_row + XW_SEGS - 1) / XW_SEGS;
+        I.ytile0 = yt;
+        I.ytiles = eq == EULER2D ? (long long)I.ytiles_per_row * I.ycol_groups : 0;
+        xt += I.xtiles;
+        yt += I.ytiles;
+    }
+
+    void set_grids()
+    {
+        const long long xt = h_hdr.xtiles_total, yt = h_hdr.ytiles_total;
+        for (int m = 0; m < 4; ++m) {
+            grid_x[m] = grid_for(xt, occupancy_x(eq, order, m, false));
+            grid_y[m] = eq == EULER2D ? grid_for(yt, occupancy_y(order, m, false)) : 0;
+        }
+        grid_m = grid_for(xt, occupancy_maxima(eq));
+    }
+
+    // new launch shape: grids recomputed, the captured graph dropped
+    void set_launch(int wg)
+    {
+        wg_per_cu = wg;
+        set_grids();
+        if (graph) {
+            hipGraphExecDestroy(graph);
+            graph = nullptr;
+            graph_k = 0;
+        }
     }
 
     void release()
@@ -279,7 +309,7 @@ struct Runtime {
     enoao_status reset_and_maxima(hipStream_t s)
     {
         int slot;
-        HIP_TRY(launch_reset_maxima(params(0, 0, -1), n, s));
+        HIP_TRY(launch_reset_maxima(params(0, 0, -1), n_cap, s));
         HIP_TRY(prof_begin(PROF_MAXIMA, s, slot));
         HIP_TRY(launch_state_maxima(eq, params(-1, 0, -1), grid_m, s));
         HIP_TRY(prof_end(slot, s));
@@ -319,7 +349,7 @@ struct Runtime {
             if (control) {
                 int slot;
                 HIP_TRY(prof_begin(PROF_CONTROL, s, slot));
-                HIP_TRY(launch_step_control(eq, params(0, -1, -1), n, s));
+                HIP_TRY(launch_step_control(eq, params(0, -1, -1), n_cap, s));
                 HIP_TRY(prof_end(slot, s));
             }
             for (int st = 1; st <= 3; ++st)
@@ -357,7 +387,7 @@ struct Runtime {
 
     enoao_status read_ctrl(hipStream_t s)
     {
-        HIP_TRY(hipMemcpyAsync(h_ctrl, d_ctrl, sizeof(Ctrl) * n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_ctrl, d_ctrl, sizeof(Ctrl) * n_cap, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (profiling) prof_collect();
         return ENOAO_OK;
@@ -394,6 +424,94 @@ static enoao_status upload_ctrl(Runtime &rt, const std::vector<Ctrl> &c, hipStre
     return ENOAO_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Pool: members join and leave between steps.  States and workspaces live in
+// one device arena; the member list (descriptors, tile offsets) is rebuilt on
+// the host and uploaded when it changes, while the captured step graph stays
+// valid because the kernels read the list and its size from device memory.
+struct enoao_pool {
+    Runtime rt;
+    int max_members = 0;
+    size_t arena_bytes = 0;
+    char *arena = nullptr;
+    struct Slot {
+        bool used = false;
+        enoao_problem prob{};
+        size_t off = 0, bytes = 0;
+    };
+    std::vector<Slot> slots;
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted by offset
+    Ctrl *h_stage = nullptr;                           // pinned per-slot control staging
+    bool dirty = false;
+    int graph_steps = 0;
+
+    static size_t align(size_t b) { return (b + 255) / 256 * 256; }
+
+    bool arena_alloc(size_t bytes, size_t &off)
+    {
+        for (size_t i = 0; i < free_list.size(); ++i) {
+            if (free_list[i].second >= bytes) {
+                off = free_list[i].first;
+                free_list[i].first += bytes;
+                free_list[i].second -= bytes;
+                if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+                return true;
+            }
+        }
+        return false;
+    }
+
+    void arena_free(size_t off, size_t bytes)
+    {
+        auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(off, (size_t)0));
+        it = free_list.insert(it, {off, bytes});
+        // merge with the neighbours
+        size_t i = it - free_list.begin();
+        if (i + 1 < free_list.size() && free_list[i].first + free_list[i].second == free_list[i + 1].first) {
+            free_list[i].second += free_list[i + 1].second;
+            free_list.erase(free_list.begin() + i + 1);
+        }
+        if (i > 0 && free_list[i - 1].first + free_list[i - 1].second == free_list[i].first) {
+            free_list[i - 1].second += free_list[i].second;
+            free_list.erase(free_list.begin() + i);
+        }
+    }
+
+    enoao_status rebuild(hipStream_t s)
+    {
+        Runtime &r = rt;
+        r.h_inst.clear();
+        long long xt = 0, yt = 0;
+        for (int k = 0; k < max_members; ++k) {
+            if (!slots[k].used) continue;
+            const enoao_problem &p = slots[k].prob;
+            double *m = (double *)(arena + slots[k].off);
+            const size_t cells = (size_t)r.nc * p.nx * p.ny;
+            Inst I;
+            r.fill_inst(I, p, m, m + cells, m + 2 * cells, r.eq == EULER2D ? m + 3 * cells : nullptr, nullptr,
+                        r.d_amax + (size_t)k * AMAX_SLOTS * AMAX_VALS, r.d_ctrl + k, xt, yt);
+            r.h_inst.push_back(I);
+        }
+        r.n = (int)r.h_inst.size();
+        r.h_hdr.n_inst = r.n;
+        r.h_hdr.xtiles_total = xt;
+        r.h_hdr.ytiles_total = yt;
+        if (r.n > 0)
+            HIP_TRY(hipMemcpyAsync(r.d_inst, r.h_inst.data(), sizeof(Inst) * r.n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(r.d_hdr, &r.h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // host copies are reused by the next rebuild
+        dirty = false;
+        return ENOAO_OK;
+    }
+};
+
+static size_t pool_member_bytes(const enoao_problem *p)
+{
+    const size_t cells = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
+    return enoao_pool::align(cells * sizeof(double) * (p->equation == EULER2D ? 4 : 3));
+}
+
 extern "C" {
 
 const char *enoao_status_string(enoao_status s)
@@ -417,8 +535,22 @@ size_t enoao_workspace_bytes(const enoao_problem *prob)
 
 enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved)
 {
-    if (workgroups_per_cu < 0 || reserved != 0) return ENOAO_EINVAL;
+    if (workgroups_per_cu < 0 || workgroups_per_cu > 64 || reserved != 0) return ENOAO_EINVAL;
     g_wg_per_cu = workgroups_per_cu;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_plan_set_launch(enoao_plan *plan, int32_t workgroups_per_cu)
+{
+    if (!plan || workgroups_per_cu < 0 || workgroups_per_cu > 64) return ENOAO_EINVAL;
+    plan->rt.set_launch(workgroups_per_cu);
+    return ENOAO_OK;
+}
+
+enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_cu)
+{
+    if (!batch || workgroups_per_cu < 0 || workgroups_per_cu > 64) return ENOAO_EINVAL;
+    batch->rt.set_launch(workgroups_per_cu);
     return ENOAO_OK;
 }
 
@@ -674,6 +806,8 @@ enoao_status enoao_batch_step(enoao_batch *batch, double *const *u, int32_t nste
             if (c[i].status == 0) c[i].done = 0;
         }
         if (enoao_status e = upload_ctrl(rt, c, s)) return e;
+        // the caller may have changed the states since the last call
+        if (enoao_status e = rt.reset_and_maxima(s)) return e;
     }
     if (nsteps == 0) return ENOAO_OK;
     const int k = std::min(nsteps, 32);
@@ -701,6 +835,218 @@ enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, in
         if (rt.h_ctrl[i].status) st = ENOAO_ENONPHYSICAL;
     }
     return st;
+}
+
+// ---- pools ----
+size_t enoao_pool_member_bytes(const enoao_problem *prob)
+{
+    if (check_problem(prob) || (prob->flags & ENOAO_F_RECORD_SELECTION)) return 0;
+    return pool_member_bytes(prob);
+}
+
+enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, size_t arena_bytes, void *stream,
+                               enoao_pool **out)
+{
+    if (!out || !like || max_members < 1 || arena_bytes < 256) return ENOAO_EINVAL;
+    *out = nullptr;
+    if (check_problem(like) || (like->flags & ENOAO_F_RECORD_SELECTION)) return ENOAO_EINVAL;
+    enoao_pool *pl = new (std::nothrow) enoao_pool();
+    if (!pl) return ENOAO_ENOMEM;
+    Runtime &r = pl->rt;
+    hipStream_t s = (hipStream_t)stream;
+    auto fail = [&](enoao_status e) {
+        if (pl->h_stage) hipHostFree(pl->h_stage);
+        r.release();
+        delete pl;
+        return e;
+    };
+    r.eq = like->equation;
+    r.order = like->order;
+    r.nc = ncomp_of(r.eq);
+    r.gamma = like->gamma;
+    r.delta = like->delta;
+    r.rec = false;
+    r.dynamic = true;
+    r.n = 0;
+    r.n_cap = max_members;
+    r.probs.assign(1, *like);
+    if (hipGetDevice(&r.device) != hipSuccess ||
+        hipDeviceGetAttribute(&r.cus, hipDeviceAttributeMultiprocessorCount, r.device) != hipSuccess)
+        return fail(ENOAO_EDEVICE);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += enoao_pool::align(bytes);
+        return o;
+    };
+    const size_t o_hdr = take(sizeof(BatchHdr));
+    const size_t o_inst = take(sizeof(Inst) * max_members);
+    const size_t o_ctrl = take(sizeof(Ctrl) * max_members);
+    const size_t o_amax = take(8ull * AMAX_SLOTS * AMAX_VALS * max_members);
+    const size_t o_arena = take(arena_bytes);
+    if (hipMalloc(&r.d_block, off) != hipSuccess) {
+        r.d_block = nullptr;
+        return fail(ENOAO_ENOMEM);
+    }
+    char *base = (char *)r.d_block;
+    r.d_hdr = (BatchHdr *)(base + o_hdr);
+    r.d_inst = (Inst *)(base + o_inst);
+    r.d_ctrl = (Ctrl *)(base + o_ctrl);
+    r.d_amax = (unsigned long long *)(base + o_amax);
+    pl->arena = base + o_arena;
+    pl->arena_bytes = arena_bytes / 256 * 256;
+    pl->free_list.push_back({0, pl->arena_bytes});
+    pl->max_members = max_members;
+    pl->slots.assign(max_members, enoao_pool::Slot());
+    if (hipHostMalloc((void **)&r.h_ctrl, sizeof(Ctrl) * max_members, hipHostMallocDefault) != hipSuccess) {
+        r.h_ctrl = nullptr;
+        return fail(ENOAO_ENOMEM);
+    }
+    if (hipHostMalloc((void **)&pl->h_stage, sizeof(Ctrl) * max_members, hipHostMallocDefault) != hipSuccess) {
+        pl->h_stage = nullptr;
+        return fail(ENOAO_ENOMEM);
+    }
+    std::vector<Ctrl> c0(max_members);
+    for (auto &c : c0) {
+        std::memset(&c, 0, sizeof(Ctrl));
+        c.done = 1;
+    }
+    if (hipMemcpyAsync(r.d_ctrl, c0.data(), sizeof(Ctrl) * max_members, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(ENOAO_EDEVICE);
+    r.wg_per_cu = g_wg_per_cu;
+    r.set_grids();
+    if (hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking) != hipSuccess) return fail(ENOAO_EDEVICE);
+    if (pl->rebuild(s)) return fail(ENOAO_EDEVICE);
+    *out = pl;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_pool_destroy(enoao_pool *pool)
+{
+    if (!pool) return ENOAO_EINVAL;
+    hipDeviceSynchronize();
+    if (pool->h_stage) hipHostFree(pool->h_stage);
+    pool->rt.release();
+    delete pool;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_pool_set_launch(enoao_pool *pool, int32_t workgroups_per_cu)
+{
+    if (!pool || workgroups_per_cu < 0 || workgroups_per_cu > 64) return ENOAO_EINVAL;
+    pool->rt.set_launch(workgroups_per_cu);
+    return ENOAO_OK;
+}
+
+enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const double *u0, int32_t u0_on_host,
+                              double t_final, int64_t max_steps, double cfl, int32_t *slot_out, void *stream)
+{
+    if (!pool || !prob || !u0 || !slot_out || max_steps < 0 || !(cfl > 0.0) || !(t_final >= 0.0)) return ENOAO_EINVAL;
+    Runtime &r = pool->rt;
+    if (check_problem(prob) || (prob->flags & ENOAO_F_RECORD_SELECTION)) return ENOAO_EINVAL;
+    if (prob->equation != r.eq || prob->order != r.order || prob->gamma != r.gamma || prob->delta != r.delta)
+        return ENOAO_EINVAL;
+    const size_t bytes = pool_member_bytes(prob);
+    if (bytes > pool->arena_bytes) return ENOAO_EINVAL;  // can never fit
+    int slot = -1;
+    for (int k = 0; k < pool->max_members; ++k)
+        if (!pool->slots[k].used) { slot = k; break; }
+    if (slot < 0) return ENOAO_ENOMEM;
+    size_t off;
+    if (!pool->arena_alloc(bytes, off)) return ENOAO_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t state = (size_t)r.nc * prob->nx * prob->ny * sizeof(double);
+    if (hipMemcpyAsync(pool->arena + off, u0, state, u0_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                       s) != hipSuccess) {
+        pool->arena_free(off, bytes);
+        return ENOAO_EDEVICE;
+    }
+    Ctrl &c = pool->h_stage[slot];
+    std::memset(&c, 0, sizeof(Ctrl));
+    c.t_final = t_final;
+    c.cfl = cfl;
+    c.max_steps = max_steps;
+    if (hipMemcpyAsync(r.d_ctrl + slot, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s) != hipSuccess) {
+        pool->arena_free(off, bytes);
+        return ENOAO_EDEVICE;
+    }
+    pool->slots[slot].used = true;
+    pool->slots[slot].prob = *prob;
+    pool->slots[slot].off = off;
+    pool->slots[slot].bytes = bytes;
+    pool->dirty = true;
+    *slot_out = slot;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_pool_step(enoao_pool *pool, int32_t nsteps, void *stream)
+{
+    if (!pool || nsteps < 1) return ENOAO_EINVAL;
+    Runtime &r = pool->rt;
+    hipStream_t s = (hipStream_t)stream;
+    if (pool->dirty) {
+        if (enoao_status e = pool->rebuild(s)) return e;
+        if (r.n > 0) {
+            // alpha and the first step of every member from its current state
+            if (enoao_status e = r.reset_and_maxima(s)) return e;
+        }
+    }
+    if (r.n == 0) return ENOAO_OK;
+    return r.run_steps(nsteps, s);
+}
+
+enoao_status enoao_pool_poll(enoao_pool *pool, int32_t *done, int32_t *status, int64_t *steps, double *t,
+                             int32_t n, void *stream)
+{
+    if (!pool || n != pool->max_members) return ENOAO_EINVAL;
+    Runtime &r = pool->rt;
+    if (enoao_status e = r.read_ctrl((hipStream_t)stream)) return e;
+    for (int k = 0; k < n; ++k) {
+        const bool used = pool->slots[k].used;
+        if (done) done[k] = used ? r.h_ctrl[k].done : -1;
+        if (status) status[k] = used ? r.h_ctrl[k].status : 0;
+        if (steps) steps[k] = used ? r.h_ctrl[k].steps : 0;
+        if (t) t[k] = used ? r.h_ctrl[k].t : 0.0;
+    }
+    return ENOAO_OK;
+}
+
+enoao_status enoao_pool_retire(enoao_pool *pool, int32_t slot, double *u_out, int32_t u_out_on_host, void *stream)
+{
+    if (!pool || slot < 0 || slot >= pool->max_members || !pool->slots[slot].used) return ENOAO_EINVAL;
+    Runtime &r = pool->rt;
+    hipStream_t s = (hipStream_t)stream;
+    const enoao_problem &p = pool->slots[slot].prob;
+    if (u_out) {
+        const size_t state = (size_t)r.nc * p.nx * p.ny * sizeof(double);
+        HIP_TRY(hipMemcpyAsync(u_out, pool->arena + pool->slots[slot].off, state,
+                               u_out_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    }
+    // the member stops stepping at once; its memory is reused only after the copy
+    Ctrl &c = pool->h_stage[slot];
+    std::memset(&c, 0, sizeof(Ctrl));
+    c.done = 1;
+    HIP_TRY(hipMemcpyAsync(r.d_ctrl + slot, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    pool->arena_free(pool->slots[slot].off, pool->slots[slot].bytes);
+    pool->slots[slot].used = false;
+    pool->dirty = true;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_pool_usage(const enoao_pool *pool, size_t *arena_used, size_t *arena_total, int32_t *members)
+{
+    if (!pool) return ENOAO_EINVAL;
+    size_t fr = 0;
+    for (auto &f : pool->free_list) fr += f.second;
+    if (arena_used) *arena_used = pool->arena_bytes - fr;
+    if (arena_total) *arena_total = pool->arena_bytes;
+    if (members) {
+        int m = 0;
+        for (auto &sl : pool->slots) m += sl.used;
+        *members = m;
+    }
+    return ENOAO_OK;
 }
 
 }  // extern "C"

@@ -101,6 +101,8 @@ def lib():
             "enoao_batch_query": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int32), vp], st),
             "enoao_set_launch": ([ctypes.c_int32, ctypes.c_int32], st),
+            "enoao_plan_set_launch": ([vp, ctypes.c_int32], st),
+            "enoao_batch_set_launch": ([vp, ctypes.c_int32], st),
             "enoao_profile": ([vp, ctypes.c_int32], st),
             "enoao_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.c_int32, vp], st),
@@ -108,6 +110,18 @@ def lib():
             "enoao_batch_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                           ctypes.c_int32, vp], st),
             "enoao_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "enoao_pool_member_bytes": ([pp], ctypes.c_size_t),
+            "enoao_pool_create": ([pp, ctypes.c_int32, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+            "enoao_pool_destroy": ([vp], st),
+            "enoao_pool_set_launch": ([vp, ctypes.c_int32], st),
+            "enoao_pool_admit": ([vp, pp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.POINTER(ctypes.c_int32), vp], st),
+            "enoao_pool_step": ([vp, ctypes.c_int32, vp], st),
+            "enoao_pool_poll": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp], st),
+            "enoao_pool_retire": ([vp, ctypes.c_int32, vp, ctypes.c_int32, vp], st),
+            "enoao_pool_usage": ([vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                  ctypes.POINTER(ctypes.c_int32)], st),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -291,3 +305,105 @@ def enoao_batch_profile_read(batch: Batch, stream=None):
 
 def enoao_set_launch(workgroups_per_cu: int):
     _check(lib().enoao_set_launch(int(workgroups_per_cu), 0), "enoao_set_launch")
+
+
+def enoao_plan_set_launch(plan: Plan, workgroups_per_cu: int):
+    _check(lib().enoao_plan_set_launch(plan.handle, int(workgroups_per_cu)), "enoao_plan_set_launch")
+
+
+def enoao_batch_set_launch(batch: Batch, workgroups_per_cu: int):
+    _check(lib().enoao_batch_set_launch(batch.handle, int(workgroups_per_cu)), "enoao_batch_set_launch")
+
+
+class Pool:
+    def __init__(self, handle, like, max_members):
+        self.handle = handle
+        self.like = like
+        self.max_members = max_members
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                lib().enoao_pool_destroy(self.handle)
+            except Exception:  # noqa: BLE001
+                pass
+            self.handle = None
+
+
+def enoao_pool_member_bytes(problem: Problem) -> int:
+    return lib().enoao_pool_member_bytes(ctypes.byref(problem))
+
+
+def enoao_pool_create(like: Problem, max_members: int, arena_bytes: int, stream=None) -> Pool:
+    h = ctypes.c_void_p()
+    _check(lib().enoao_pool_create(ctypes.byref(like), int(max_members), int(arena_bytes), _stream(stream),
+                                   ctypes.byref(h)), "enoao_pool_create")
+    return Pool(h, like, int(max_members))
+
+
+def enoao_pool_destroy(pool: Pool):
+    if pool.handle:
+        _check(lib().enoao_pool_destroy(pool.handle), "enoao_pool_destroy")
+        pool.handle = None
+
+
+def enoao_pool_set_launch(pool: Pool, workgroups_per_cu: int):
+    _check(lib().enoao_pool_set_launch(pool.handle, int(workgroups_per_cu)), "enoao_pool_set_launch")
+
+
+def enoao_pool_admit(pool: Pool, problem: Problem, u0, t_final=1e300, max_steps=1 << 62, cfl=0.3, stream=None):
+    """Admit a member; u0 is a numpy array (copied from host) or a GPU tensor.  Returns the
+    slot, or None when the pool has no room now (ENOMEM)."""
+    slot = ctypes.c_int32()
+    if isinstance(u0, np.ndarray):
+        a = np.ascontiguousarray(u0, dtype=np.float64)
+        if a.shape != problem.shape:
+            raise ValueError(f"u0 has shape {a.shape}, expected {problem.shape}")
+        st = lib().enoao_pool_admit(pool.handle, ctypes.byref(problem), a.ctypes.data_as(ctypes.c_void_p), 1,
+                                    float(t_final), int(max_steps), float(cfl), ctypes.byref(slot), _stream(stream))
+    else:
+        st = lib().enoao_pool_admit(pool.handle, ctypes.byref(problem), _dev_ptr(u0, problem.shape), 0,
+                                    float(t_final), int(max_steps), float(cfl), ctypes.byref(slot), _stream(stream))
+    if st == ENOMEM:
+        return None
+    _check(st, "enoao_pool_admit")
+    return slot.value
+
+
+def enoao_pool_step(pool: Pool, nsteps=1, stream=None):
+    _check(lib().enoao_pool_step(pool.handle, int(nsteps), _stream(stream)), "enoao_pool_step")
+
+
+def enoao_pool_poll(pool: Pool, stream=None):
+    """(done, status, steps, t) per slot as numpy arrays (done = -1 for a free slot)."""
+    n = pool.max_members
+    d = (ctypes.c_int32 * n)()
+    f = (ctypes.c_int32 * n)()
+    s = (ctypes.c_int64 * n)()
+    t = (ctypes.c_double * n)()
+    _check(lib().enoao_pool_poll(pool.handle, d, f, s, t, n, _stream(stream)), "enoao_pool_poll")
+    return np.array(d[:]), np.array(f[:]), np.array(s[:]), np.array(t[:])
+
+
+def enoao_pool_retire(pool: Pool, slot: int, shape=None, out=None, stream=None):
+    """Free a member.  With `shape` (and no `out`) its state is returned as a numpy array;
+    `out` may be a GPU tensor to receive it on the device."""
+    if out is not None:
+        _check(lib().enoao_pool_retire(pool.handle, int(slot), _dev_ptr(out), 0, _stream(stream)), "enoao_pool_retire")
+        return out
+    if shape is not None:
+        a = np.empty(shape, np.float64)
+        _check(lib().enoao_pool_retire(pool.handle, int(slot), a.ctypes.data_as(ctypes.c_void_p), 1, _stream(stream)),
+               "enoao_pool_retire")
+        return a
+    _check(lib().enoao_pool_retire(pool.handle, int(slot), None, 1, _stream(stream)), "enoao_pool_retire")
+    return None
+
+
+def enoao_pool_usage(pool: Pool):
+    """(arena bytes used, arena bytes total, members)."""
+    u = ctypes.c_size_t()
+    t = ctypes.c_size_t()
+    m = ctypes.c_int32()
+    _check(lib().enoao_pool_usage(pool.handle, ctypes.byref(u), ctypes.byref(t), ctypes.byref(m)), "enoao_pool_usage")
+    return u.value, t.value, m.value

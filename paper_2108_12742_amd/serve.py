@@ -1,0 +1,188 @@
+"""Continuous-batching service for ENO-AO solves.
+
+Requests (an initial state and a number of SSP-RK3 steps) arrive over time.
+The server admits them into a device pool as arena memory frees up (FIFO by
+arrival; a request that can never fit is rejected), advances every admitted
+request together with the batched kernels, and retires each one when its
+last step is done.  Request states stay in HBM between steps; admissions and
+retirements happen between step rounds, while other requests are on the GPU.
+
+The scheduling is independent of the device: `Server` drives any backend with
+the `Backend` methods below.  `GpuPoolBackend` is the HIP pool of the C ABI.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    problem: object            # enoao.Problem
+    u0: np.ndarray
+    nsteps: int
+    cfl: float
+    arrival: float
+    admitted: float | None = None
+    finished: float | None = None
+    slot: int | None = None
+    result: np.ndarray | None = None
+    status: int = 0            # 0 ok, non-zero: non-physical state or rejected
+    error: str | None = None
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+    @property
+    def cell_updates(self):
+        return int(self.problem.nx) * int(self.problem.ny) * self.nsteps
+
+
+class Backend:
+    """What the server needs from a device pool."""
+    max_members: int
+    arena_bytes: int
+
+    def member_bytes(self, problem) -> int: ...
+    def admit(self, problem, u0, nsteps, cfl): ...  # slot, or None when there is no room now
+    def step(self, nsteps: int): ...
+    def poll(self): ...                            # (done, status, steps) per slot
+    def retire(self, slot: int, shape): ...        # final state (numpy)
+
+
+class GpuPoolBackend(Backend):
+    def __init__(self, like, max_members=256, arena_bytes=8 << 30, stream=None, workgroups_per_cu=0):
+        from . import enoao as E
+        self.E = E
+        self.stream = stream
+        self.pool = E.enoao_pool_create(like, max_members, arena_bytes, stream)
+        if workgroups_per_cu:
+            E.enoao_pool_set_launch(self.pool, workgroups_per_cu)
+        self.max_members = max_members
+        self.arena_bytes = E.enoao_pool_usage(self.pool)[1]
+
+    def member_bytes(self, problem):
+        return self.E.enoao_pool_member_bytes(problem)
+
+    def admit(self, problem, u0, nsteps, cfl):
+        return self.E.enoao_pool_admit(self.pool, problem, u0, max_steps=nsteps, cfl=cfl, stream=self.stream)
+
+    def step(self, nsteps):
+        self.E.enoao_pool_step(self.pool, nsteps, self.stream)
+
+    def poll(self):
+        d, f, s, _ = self.E.enoao_pool_poll(self.pool, self.stream)
+        return d, f, s
+
+    def retire(self, slot, shape):
+        return self.E.enoao_pool_retire(self.pool, slot, shape=shape, stream=self.stream)
+
+    def close(self):
+        self.E.enoao_pool_destroy(self.pool)
+
+
+@dataclass
+class Server:
+    backend: Backend
+    steps_per_round: int = 1
+    clock: object = time.perf_counter
+    queue: deque = field(default_factory=deque)
+    active: dict = field(default_factory=dict)   # slot -> Request
+    done: list = field(default_factory=list)
+    rounds: int = 0
+    _next_id: int = 0
+
+    def submit(self, problem, u0, nsteps, cfl=0.3, arrival=None) -> Request:
+        r = Request(self._next_id, problem, np.ascontiguousarray(u0, np.float64), int(nsteps), float(cfl),
+                    self.clock() if arrival is None else arrival)
+        self._next_id += 1
+        if self.backend.member_bytes(problem) > self.backend.arena_bytes or nsteps < 1:
+            r.status, r.error, r.finished = -1, "request can never fit the device pool", r.arrival
+            self.done.append(r)
+        else:
+            self.queue.append(r)
+        return r
+
+    def admit(self):
+        """FIFO admission while slots and arena memory allow."""
+        n = 0
+        while self.queue and len(self.active) < self.backend.max_members:
+            r = self.queue[0]
+            slot = self.backend.admit(r.problem, r.u0, r.nsteps, r.cfl)
+            if slot is None:
+                break
+            self.queue.popleft()
+            r.slot, r.admitted = slot, self.clock()
+            self.active[slot] = r
+            n += 1
+        return n
+
+    def round(self):
+        """Admit, advance every admitted request, retire the finished ones."""
+        self.admit()
+        if not self.active:
+            return 0
+        self.backend.step(self.steps_per_round)
+        self.rounds += 1
+        done, status, steps = self.backend.poll()
+        finished = 0
+        for slot in list(self.active):
+            if done[slot] == 1 or status[slot] != 0:
+                r = self.active.pop(slot)
+                r.result = self.backend.retire(slot, r.problem.shape)
+                r.finished = self.clock()
+                r.status = int(status[slot])
+                if r.status:
+                    r.error = "non-physical state"
+                elif steps[slot] != r.nsteps:
+                    r.status, r.error = -2, f"stopped after {steps[slot]} of {r.nsteps} steps"
+                self.done.append(r)
+                finished += 1
+        return finished
+
+    def idle(self):
+        return not self.queue and not self.active
+
+    def drain(self):
+        while not self.idle():
+            self.round()
+        return self.done
+
+
+def latency_stats(requests):
+    lat = np.array([r.latency for r in requests if r.status == 0])
+    if lat.size == 0:
+        return {"count": 0}
+    return {"count": int(lat.size), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "max_s": float(lat.max())}
+
+
+def run_arrivals(server: Server, arrivals, make_request):
+    """Drive a server with a timed request stream.
+
+    arrivals: increasing arrival offsets (s) from the start; make_request(i) ->
+    (problem, u0, nsteps).  Requests are submitted when the wall clock passes
+    their arrival time; the server runs rounds meanwhile and sleeps only when it
+    has nothing to do.  Returns (requests, wall seconds from first arrival to
+    last completion)."""
+    t0 = server.clock()
+    pending = deque(range(len(arrivals)))
+    reqs = []
+    while pending or not server.idle():
+        now = server.clock() - t0
+        while pending and arrivals[pending[0]] <= now:
+            i = pending.popleft()
+            p, u0, ns = make_request(i)
+            reqs.append(server.submit(p, u0, ns, arrival=t0 + arrivals[i]))
+        if server.idle():
+            if pending:
+                time.sleep(max(0.0, arrivals[pending[0]] - (server.clock() - t0)))
+            continue
+        server.round()
+    end = max(r.finished for r in reqs)
+    return reqs, end - t0

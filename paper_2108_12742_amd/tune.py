@@ -1,0 +1,75 @@
+"""Autotuner of the persistent launches.
+
+The sweeps run as persistent grids of (CUs x W) workgroups; W (workgroups, i.e.
+waves/4, resident per CU) trades latency hiding against the tail of the last
+tiles.  The tuner times a few steps of the caller's batch for each candidate W
+and keeps the fastest per (equation, order, size bucket) in a JSON cache
+(ENOAO_TUNE_CACHE, default ~/.cache/enoao_tune.json).  Results do not depend on
+W, so tuning never changes answers.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+CANDIDATES = (0, 1, 2, 3, 4, 6, 8)  # 0 = the occupancy the kernels' resources allow
+
+
+def cache_path():
+    return os.environ.get("ENOAO_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "enoao_tune.json"))
+
+
+def bucket_key(problems) -> str:
+    """(equation, order, log2 of the total cell count, log2 of the member count)."""
+    cells = sum(int(p.nx) * int(p.ny) for p in problems)
+    return f"eq{problems[0].equation}-o{problems[0].order}-c{int(math.log2(max(cells, 1)))}-m{int(math.log2(len(problems)))}"
+
+
+def load_cache():
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def store(key, value):
+    c = load_cache()
+    c[key] = value
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + f".tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(c, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune_batch(problems, states, steps=4, candidates=CANDIDATES, cfl=0.3, use_cache=True):
+    """Best workgroups-per-CU for advancing `problems` (GPU tensors `states`, restored
+    afterwards) and the timing of every candidate (ms per step)."""
+    import torch
+    from . import enoao as E
+    key = bucket_key(problems)
+    if use_cache:
+        hit = load_cache().get(key)
+        if hit is not None:
+            return hit["workgroups_per_cu"], hit["ms_per_step"]
+    saved = [u.clone() for u in states]
+    timing = {}
+    for w in candidates:
+        batch = E.enoao_batch_create(problems)
+        E.enoao_batch_set_launch(batch, w)
+        E.enoao_batch_step(batch, states, 1, cfl)  # warm-up: graph capture, first touch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E.enoao_batch_step(batch, states, steps, cfl)
+        torch.cuda.synchronize()
+        timing[w] = (time.perf_counter() - t0) * 1e3 / steps
+        E.enoao_batch_destroy(batch)
+        for u, s in zip(states, saved):
+            u.copy_(s)
+    best = min(timing, key=timing.get)
+    store(key, {"workgroups_per_cu": best, "ms_per_step": timing})
+    return best, timing

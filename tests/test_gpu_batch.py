@@ -1,0 +1,133 @@
+"""Batched and pooled launches on the GPU: every member's result equals its solve alone
+(bitwise: same kernels, same per-member arithmetic), and matches the oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12742_amd import workloads as W
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def _E():
+    from paper_2108_12742_amd import enoao as E
+    return E
+
+
+def _alone(torch, E, inst, nsteps, cfl=0.3, t_final=1e300):
+    plan = E.enoao_plan_create(E.problem_from_instance(inst))
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, t_final, cfl=cfl, max_steps=nsteps)
+    return u.cpu().numpy(), t, n
+
+
+def test_batch_1d_members_match_alone_and_oracle():
+    torch = PT.torch_cuda()
+    E = _E()
+    sizes = [128, 5, 63, 64, 300, 1031, 2000, 77]
+    insts = [W.riemann_1d(100 + k, n) for k, n in enumerate(sizes)]
+    probs = [E.problem_from_instance(i) for i in insts]
+    batch = E.enoao_batch_create(probs)
+    us = [PT.to_dev(torch, i.u0) for i in insts]
+    E.enoao_batch_step(batch, us, 10, 0.3)
+    t, steps, status = E.enoao_batch_query(batch)
+    assert (steps == 10).all() and (status == 0).all()
+    for k, inst in enumerate(insts):
+        ref, ta, na = _alone(torch, E, inst, 10)
+        assert torch.equal(us[k].cpu(), torch.from_numpy(ref)), f"member {k} (N={sizes[k]}) differs from alone"
+        assert t[k] == ta
+    for k in (0, 4):
+        ur, _, _ = O.solve(PT.oracle_problem(probs[k]), insts[k].u0, 1e300, cfl=0.3, max_steps=10)
+        PT.assert_close_by_component(us[k].cpu().numpy(), ur, rtol=1e-11, what=f"member {k}")
+
+
+def test_batch_continues_across_calls_and_stops_at_t_final():
+    torch = PT.torch_cuda()
+    E = _E()
+    insts = [W.riemann_1d(7, 200), W.riemann_1d(8, 500), W.advection(3, 150)]
+    insts = insts[:2]
+    probs = [E.problem_from_instance(i) for i in insts]
+    batch = E.enoao_batch_create(probs)
+    us = [PT.to_dev(torch, i.u0) for i in insts]
+    tf = [0.002, 0.05]
+    E.enoao_batch_step(batch, us, 6, 0.3, t_final=tf)
+    E.enoao_batch_step(batch, us, 6, 0.3, t_final=tf)
+    t, steps, status = E.enoao_batch_query(batch)
+    for k, inst in enumerate(insts):
+        ref, ta, na = _alone(torch, E, inst, 12, t_final=tf[k])
+        assert steps[k] == na and t[k] == ta
+        assert torch.equal(us[k].cpu(), torch.from_numpy(ref))
+    assert t[0] == tf[0] and steps[0] < 12   # the first member reached its end time early
+
+
+def test_batch_2d_members_and_launch_shape():
+    torch = PT.torch_cuda()
+    E = _E()
+    insts = [W.quadrants(1, 40, 37), W.quadrants(3, 16, 15), W.quadrants(5, 70, 31), W.quadrants(6, 5, 9)]
+    probs = [E.problem_from_instance(i) for i in insts]
+    outs = []
+    for wg in (0, 1):
+        batch = E.enoao_batch_create(probs)
+        E.enoao_batch_set_launch(batch, wg)
+        us = [PT.to_dev(torch, i.u0) for i in insts]
+        E.enoao_batch_step(batch, us, 4, 0.3)
+        outs.append([u.cpu() for u in us])
+    for k, inst in enumerate(insts):
+        ref, _, _ = _alone(torch, E, inst, 4)
+        assert torch.equal(outs[0][k], torch.from_numpy(ref))
+        assert torch.equal(outs[1][k], outs[0][k])
+
+
+def test_pool_members_join_and_leave():
+    """Members admitted at different rounds, retired when done: each equals its solve alone."""
+    torch = PT.torch_cuda()
+    E = _E()
+    insts = [W.quadrants(s, n, n) for s, n in ((1, 48), (2, 33), (3, 64), (5, 20), (1, 40))]
+    nsteps = [5, 3, 4, 6, 2]
+    like = E.problem_from_instance(insts[0])
+    bytes_per = [E.enoao_pool_member_bytes(E.problem_from_instance(i)) for i in insts]
+    pool = E.enoao_pool_create(like, 3, sum(sorted(bytes_per)[-2:]) + 4096)
+    results, slots, pending = {}, {}, list(range(len(insts)))
+    rounds = 0
+    while pending or slots:
+        while pending:  # FIFO admission while there is room
+            k = pending[0]
+            s = E.enoao_pool_admit(pool, E.problem_from_instance(insts[k]), insts[k].u0, max_steps=nsteps[k])
+            if s is None:
+                break
+            slots[s] = k
+            pending.pop(0)
+        E.enoao_pool_step(pool, 1)
+        rounds += 1
+        done, status, steps, _ = E.enoao_pool_poll(pool)
+        for s in list(slots):
+            assert status[s] == 0
+            if done[s] == 1:
+                k = slots.pop(s)
+                assert steps[s] == nsteps[k]
+                results[k] = E.enoao_pool_retire(pool, s, shape=insts[k].u0.shape)
+        assert rounds < 100
+    for k, inst in enumerate(insts):
+        ref, _, _ = _alone(torch, E, inst, nsteps[k])
+        np.testing.assert_array_equal(results[k], ref)
+    assert E.enoao_pool_usage(pool)[0] == 0
+
+
+def test_server_on_gpu_pool():
+    PT.torch_cuda()
+    E = _E()
+    from paper_2108_12742_amd import serve as S
+    insts = [W.quadrants(s % 3 + 1, n, n) for s, n in enumerate((32, 48, 40, 24, 56, 32))]
+    like = E.problem_from_instance(insts[0])
+    arena = 2 * E.enoao_pool_member_bytes(E.problem_from_instance(insts[4])) + 4096
+    srv = S.Server(S.GpuPoolBackend(like, max_members=4, arena_bytes=arena), steps_per_round=2)
+    reqs = [srv.submit(E.problem_from_instance(i), i.u0, nsteps=3 + k % 3) for k, i in enumerate(insts)]
+    srv.drain()
+    torch = PT.torch_cuda()
+    for r, inst in zip(reqs, insts):
+        assert r.status == 0, r.error
+        ref, _, _ = _alone(torch, E, inst, r.nsteps)
+        np.testing.assert_array_equal(r.result, ref)
+    st = S.latency_stats(reqs)
+    assert st["count"] == len(insts)

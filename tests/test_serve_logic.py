@@ -1,0 +1,125 @@
+"""Scheduling logic of the continuous-batching server, on the CPU: a fake pool that
+steps its members with the oracle, a virtual clock, and the real Server."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12742_amd import serve as S
+from paper_2108_12742_amd import workloads as W
+
+
+class FakeProblem:
+    def __init__(self, inst):
+        self.inst = inst
+        self.nx, self.ny = inst.nx, inst.ny
+        self.shape = inst.u0.shape
+
+    def oracle(self):
+        return O.Problem(O.EULER1D, nx=self.nx, x_lo=self.inst.x_lo, x_hi=self.inst.x_hi, bc_x=O.TRANSMISSIVE)
+
+
+class FakePool(S.Backend):
+    """Same contract as the HIP pool: slots, an arena budget in bytes, members that stop at
+    their own step count; steps with the oracle."""
+
+    def __init__(self, max_members, arena_bytes, clock):
+        self.max_members, self.arena_bytes, self.clock = max_members, arena_bytes, clock
+        self.used = 0
+        self.members = {}
+        self.stepped = []
+
+    def member_bytes(self, problem):
+        return 3 * 8 * problem.nx * problem.ny * 3
+
+    def admit(self, problem, u0, nsteps, cfl):
+        b = self.member_bytes(problem)
+        free = [k for k in range(self.max_members) if k not in self.members]
+        if not free or self.used + b > self.arena_bytes:
+            return None
+        self.used += b
+        self.members[free[0]] = [problem, u0.copy(), 0, nsteps, cfl, b]
+        return free[0]
+
+    def step(self, nsteps):
+        self.stepped.append(sorted(self.members))
+        for m in self.members.values():
+            p, u, k, n, cfl, _ = m
+            for _ in range(min(nsteps, n - k)):
+                op = p.oracle()
+                u = O.step(op, u, O.cfl_dt(op, u, cfl))
+                k += 1
+            m[1], m[2] = u, k
+        self.clock.t += 1.0
+
+    def poll(self):
+        done = np.full(self.max_members, -1)
+        steps = np.zeros(self.max_members, int)
+        for s, m in self.members.items():
+            done[s] = int(m[2] >= m[3])
+            steps[s] = m[2]
+        return done, np.zeros(self.max_members, int), steps
+
+    def retire(self, slot, shape):
+        m = self.members.pop(slot)
+        self.used -= m[5]
+        return m[1]
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+def _request(seed, n):
+    inst = W.riemann_1d(seed, n)
+    return FakeProblem(inst), inst.u0
+
+
+def test_footprint_admission_fifo_and_results():
+    clock = Clock()
+    small, big = _request(1, 32), _request(2, 64)
+    budget = 3 * 8 * 3 * (32 + 64)  # room for one small and one big request at a time
+    pool = FakePool(max_members=8, arena_bytes=budget, clock=clock)
+    srv = S.Server(pool, steps_per_round=2, clock=clock)
+    reqs = [srv.submit(*small, nsteps=4), srv.submit(*big, nsteps=4), srv.submit(*big, nsteps=2),
+            srv.submit(*small, nsteps=6)]
+    srv.admit()
+    assert [r.slot is not None for r in reqs] == [True, True, False, False]  # arena full: FIFO waits
+    srv.drain()
+    assert all(r.status == 0 for r in reqs)
+    # every member of every round fitted the arena; requests 3 and 4 joined while others ran
+    assert max(len(s) for s in pool.stepped) == 2
+    assert reqs[2].admitted > reqs[1].admitted and reqs[3].admitted >= reqs[2].admitted
+    # results do not depend on the mix: each equals its solve alone
+    for r, (prob, u0) in zip(reqs, [small, big, big, small]):
+        op = prob.oracle()
+        u = u0
+        for _ in range(r.nsteps):
+            u = O.step(op, u, O.cfl_dt(op, u, 0.3))
+        np.testing.assert_array_equal(r.result, u)
+    st = S.latency_stats(reqs)
+    assert st["count"] == 4 and st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_never_fitting_request_rejected():
+    clock = Clock()
+    pool = FakePool(max_members=4, arena_bytes=1000, clock=clock)
+    srv = S.Server(pool, clock=clock)
+    r = srv.submit(*_request(3, 64), nsteps=3)
+    assert r.status != 0 and "never fit" in r.error
+    assert srv.idle()
+
+
+def test_slot_limit():
+    clock = Clock()
+    pool = FakePool(max_members=2, arena_bytes=1 << 30, clock=clock)
+    srv = S.Server(pool, clock=clock)
+    reqs = [srv.submit(*_request(k, 16), nsteps=1 + k) for k in range(5)]
+    srv.admit()
+    assert sum(r.slot is not None for r in reqs) == 2
+    srv.drain()
+    assert all(r.status == 0 and r.finished is not None for r in reqs)
+    assert max(len(s) for s in pool.stepped) == 2
