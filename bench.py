@@ -258,13 +258,18 @@ def main():
         "config": {"workload": workload, "nx": n, "ny": n, "order": args.order,
                    "bc": "periodic", "cfl": 0.3, "seed": W.QUADRANT_BENCH_SEED, "parallelism": "single-gpu"},
         "roofline": roof,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(),
+        "cpu_baseline": None,
         "kernels": kernels,
         "flops_per_cell_update": R.cell_update_flops("euler2d", args.order),
     }
     del plan, u, u0
+    if not args.no_cpu_baseline:
+        print("[bench] oracle baseline on the host ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
     if not args.no_extras:
+        print(f"[bench] main workload: {value:.4g} cell-updates/s; batched leg ...", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
+        print("[bench] batched leg done; served leg ...", file=sys.stderr, flush=True)
         out["served"] = bench_served(requests=args.served_requests)
     print(json.dumps(out), flush=True)
 

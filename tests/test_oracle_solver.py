@@ -372,3 +372,28 @@ def test_quadrant_bench_seed_is_physical():
     with pytest.raises(O.OracleError):
         for _ in range(10):
             u = O.step(p, u, O.cfl_dt(p, u, 0.3))
+
+
+def test_batch_1d_draws_are_moderate_and_physical():
+    """Every member of the 512-member 1D batch satisfies the draw's bounds (sound speeds
+    within 4x, velocity jump below the smaller sound speed); its ten smallest members
+    are advanced 100 steps by the oracle without a non-physical state.  The unbounded
+    draw of member 143 (a cold, fast left state against a dense right one) is not."""
+    insts = W.batch_1d(0, 512)
+    g = W.GAMMA
+    for i in insts:
+        (rL, uL, pL), (rR, uR, pR) = i.meta["left"], i.meta["right"]
+        for r in (rR * 0.8, rR * 1.2):
+            cL, cR = np.sqrt(g * pL / rL), np.sqrt(g * pR / r)
+            assert max(cL, cR) <= 4 * min(cL, cR) and abs(uR - uL) <= min(cL, cR)
+    for i in sorted(insts, key=lambda i: i.nx)[:10]:
+        p = O.Problem(O.EULER1D, nx=i.nx, x_lo=i.x_lo, x_hi=i.x_hi, bc_x=O.TRANSMISSIVE)
+        u, _, n = O.solve(p, i.u0, 1e300, cfl=0.3, max_steps=100)
+        assert n == 100 and np.isfinite(u).all()
+    n = 259
+    x = W.nodes(0.0, 1.0, n)
+    rho = np.where(x < 0.6904, 0.11715, 6.8277 * (1 + 0.2 * np.sin(2 * np.pi * 5 * x + 4.2453)))
+    u0 = W.conserved_1d(rho, np.where(x < 0.6904, -1.7667, 1.7844), np.where(x < 0.6904, 1.4748, 0.42522))
+    p = O.Problem(O.EULER1D, nx=n, x_lo=0.0, x_hi=1.0, bc_x=O.TRANSMISSIVE)
+    with pytest.raises(O.OracleError):
+        O.solve(p, u0.reshape(3, 1, n), 1e300, cfl=0.3, max_steps=100)
