@@ -19,8 +19,13 @@
 //     IS <= delta and IS_k <= min(lower IS); the last winner is the choice.
 //     This is the highest-priority candidate with IS <= delta if any, else the
 //     highest-priority one among the smallest indicators;
-//   * only the chosen candidate's flux is evaluated, as a dot product of the
-//     window with that row of the flux table (rows held in LDS);
+//   * the candidate fluxes of the table of numerical fluxes are taken in
+//     Newton form on the same difference table: each candidate's row equals a
+//     lower candidate's row plus a rational multiple of one undivided
+//     difference (an exact identity of the table's rows, e.g. for order 5
+//     S_{j-1}^{j+1} = S_j^{j+1} - 1/6 (f_{j+1} - 2 f_j + f_{j-1})), so all
+//     candidates cost one multiply-add each and the chosen one is selected
+//     with the index, without a table in memory;
 //   * a window may be scaled by a power of two before reconstruction (the
 //     factor 1/2 of the splitting is applied after it); scaling by 2^k is
 //     exact, so indicators, comparisons and selections are unchanged when delta
@@ -36,7 +41,7 @@ namespace enoao {
 // highest-priority candidate on both sides of a field, that candidate is every
 // lane's choice (first principle), so the selection logic is skipped.  Each
 // lane's result is bitwise the same as on the full path (same indicators, same
-// row); only the work differs.
+// candidate flux); only the work differs.
 #ifndef ENOAO_EARLY_EXIT
 #define ENOAO_EARLY_EXIT 1
 #endif
@@ -48,50 +53,17 @@ template <int ORDER> struct ReconTraits;
 template <> struct ReconTraits<5> { static constexpr int H = 3, K = 6; };
 template <> struct ReconTraits<7> { static constexpr int H = 4, K = 9; };
 
-// Rows of the table of numerical fluxes (Table "Flux_reconstruction") as
-// weights on the whole window, candidates in increasing priority; row stride
-// TW doubles (16-byte aligned).  The kernels copy the rows to LDS and each lane
-// evaluates only its selected row.
-template <int ORDER> struct FluxRows;
-template <> struct FluxRows<5> {
-    static constexpr int TW = 8;
-    // window f_{j-3} .. f_{j+3}
-    static constexpr double num[6][7] = {
-        {0, 0, 0, 1, 0, 0, 0},        {0, 0, 0, 1, 1, 0, 0},       {0, 0, -1, 5, 2, 0, 0},
-        {0, 1, -5, 13, 3, 0, 0},      {0, 0, -1, 7, 7, -1, 0},     {0, 2, -13, 47, 27, -3, 0}};
-    static constexpr double den[6] = {1, 2, 6, 12, 12, 60};
-};
-template <> struct FluxRows<7> {
-    static constexpr int TW = 10;
-    // window f_{j-4} .. f_{j+4}
-    static constexpr double num[9][9] = {
-        {0, 0, 0, 0, 1, 0, 0, 0, 0},          {0, 0, 0, 0, 1, 1, 0, 0, 0},
-        {0, 0, 0, -1, 5, 2, 0, 0, 0},         {0, 0, 1, -5, 13, 3, 0, 0, 0},
-        {0, 0, 0, -1, 7, 7, -1, 0, 0},        {0, 0, 2, -13, 47, 27, -3, 0, 0},
-        {0, -1, 7, -23, 57, 22, -2, 0, 0},    {0, 0, 1, -8, 37, 37, -8, 1, 0},
-        {0, -3, 25, -101, 319, 214, -38, 4, 0}};
-    static constexpr double den[9] = {1, 2, 6, 12, 12, 60, 60, 60, 420};
-};
-
-// Fill the LDS copy of the flux rows (weights num/den), all threads of a block.
-template <int ORDER> __device__ __forceinline__ void load_flux_rows(double *tab)
-{
-    using R = FluxRows<ORDER>;
-    constexpr int K = ReconTraits<ORDER>::K, W = 2 * ReconTraits<ORDER>::H + 1;
-    for (int i = threadIdx.x; i < K * R::TW; i += blockDim.x) {
-        const int k = i / R::TW, t = i % R::TW;
-        tab[i] = t < W ? R::num[k][t] / R::den[k] : 0.0;
-    }
-}
-
 // Two principles of Section 3.2 on the indicators is[0..K-1] (increasing
 // priority): the highest-priority candidate with IS <= delta if there is one,
 // else the last minimum.  The comparisons produce lane masks; the logic between
-// them stays in scalar registers, the lane's index is one select per candidate.
+// them stays in scalar registers, the lane's index and flux are one select each
+// per candidate.
 template <int K>
-__device__ __forceinline__ int select_candidate(const double (&is)[K], double delta)
+__device__ __forceinline__ double select_candidate(const double (&is)[K], const double (&h)[K], double delta,
+                                                   int &sel)
 {
     int s = 0;
+    double v = h[0];
     bool any = is[0] <= delta;
     double mn = is[0];
 #pragma unroll
@@ -99,24 +71,15 @@ __device__ __forceinline__ int select_candidate(const double (&is)[K], double de
         const bool le = is[k] <= delta;
         const bool win = le || (!any && is[k] <= mn);
         s = win ? k : s;
+        v = win ? h[k] : v;
         any = any || le;
         mn = fmin(mn, is[k]);
     }
-    return s;
+    sel = s;
+    return v;
 }
 
-// selected flux: one row of the table, as a dot product with the window
-template <int W, int TW>
-__device__ __forceinline__ double row_dot(const double (&f)[W], const double *tab, int s)
-{
-    const double *r = tab + s * TW;
-    double q = r[0] * f[0];
-#pragma unroll
-    for (int t = 1; t < W; ++t) q = fma(r[t], f[t], q);
-    return q;
-}
-
-// Indicators of all candidates of one window, in increasing priority.
+// Candidates of one window, in increasing priority.
 // Order 5: f[0..6] = f_{j-3} .. f_{j+3}; candidates 0: S_j^j, 1: S_j^{j+1},
 // 2: S_{j-1}^{j+1}, 3: S_{j-2}^{j+1}, 4: S_{j-1}^{j+2}, 5: S_{j-2}^{j+2}.
 // Order 7: f[0..8] = f_{j-4} .. f_{j+4}; then 6: S_{j-3}^{j+2},
@@ -124,63 +87,18 @@ __device__ __forceinline__ double row_dot(const double (&f)[W], const double *ta
 // delta_L / delta_R of every candidate are entries of one difference table
 // (level k holds the k-th undivided differences); rows shared by two
 // candidates are one entry.
-__device__ __forceinline__ void indicators5(const double (&f)[7], double (&is)[6])
-{
-    const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
-    const double a3 = f[4] - f[3], a4 = f[5] - f[4], a5 = f[6] - f[5];
-    const double b0 = a1 - a0, b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3, b4 = a5 - a4;
-    const double c0 = b1 - b0, c1 = b2 - b1, c2 = b3 - b2, c3 = b4 - b3;
-    const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
-    const double e0 = d1 - d0, e1 = d2 - d1;
-    const double ad1 = fabs(d1);
-    is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
-    is[1] = fmin(fabs(b2), fabs(b3));                              // S_j^{j+1}
-    is[2] = fmin(fabs(c1), fabs(c2));                              // S_{j-1}^{j+1}
-    is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
-    is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
-    is[5] = fmin(fabs(e0), fabs(e1));                              // S_{j-2}^{j+2}
-}
-
-__device__ __forceinline__ void indicators7(const double (&f)[9], double (&is)[9])
-{
-    double a[8], b[7], c[6], d[5], e[4], g[3], h[2];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] = f[i + 1] - f[i];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) b[i] = a[i + 1] - a[i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) c[i] = b[i + 1] - b[i];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) d[i] = c[i + 1] - c[i];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) e[i] = d[i + 1] - d[i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) g[i] = e[i + 1] - e[i];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) h[i] = g[i + 1] - g[i];
-    const double ad2 = fabs(d[2]), ag1 = fabs(g[1]);
-    is[0] = 0.5 * fmin(fabs(a[3]) + fabs(a[2]), fabs(a[4]) + fabs(a[5])); // S_j^j
-    is[1] = fmin(fabs(b[3]), fabs(b[4]));                                  // S_j^{j+1}
-    is[2] = fmin(fabs(c[2]), fabs(c[3]));                                  // S_{j-1}^{j+1}
-    is[3] = fmin(fabs(d[1]), ad2);                                         // S_{j-2}^{j+1}
-    is[4] = fmin(ad2, fabs(d[3]));                                         // S_{j-1}^{j+2}
-    is[5] = fmin(fabs(e[1]), fabs(e[2]));                                  // S_{j-2}^{j+2}
-    is[6] = fmin(fabs(g[0]), ag1);                                         // S_{j-3}^{j+2}
-    is[7] = fmin(ag1, fabs(g[2]));                                         // S_{j-2}^{j+3}
-    is[8] = fmin(fabs(h[0]), fabs(h[1]));                                  // S_{j-3}^{j+3}
-}
-
 template <int ORDER> struct Recon {
     static constexpr int H = ReconTraits<ORDER>::H, K = ReconTraits<ORDER>::K, W = 2 * H + 1;
-    __device__ __forceinline__ static void indicators(const double (&f)[W], double (&is)[K])
-    {
-        if constexpr (ORDER == 5) indicators5(f, is);
-        else indicators7(f, is);
-    }
-    // One side of one field: the chosen candidate's value at x_{j+1/2}.  The
-    // wave skips the other indicators and the selection when every lane's top
-    // candidate has IS <= delta.
-    __device__ __forceinline__ static double run(const double (&f)[W], double delta, const double *tab, int &sel)
+    // One side of one field: the chosen candidate's value at x_{j+1/2} and its
+    // index.  Candidate fluxes (table of numerical fluxes) in Newton form:
+    //   order 5 (f_j = f[3]):  h0 = f_j, h1 = h0 + a3/2, h2 = h1 - b2/6,
+    //     h3 = h2 - c1/12, h4 = h2 - c2/12, h5 = h3 - d1/20;
+    //   order 7 (f_j = f[4]): the same on the shifted table, then
+    //     h6 = h5 + e1/60, h7 = h5 + e2/60, h8 = h6 + g1/105,
+    // (a, b, c, ... the 1st, 2nd, 3rd ... undivided differences, index = first
+    // node).  The wave skips the other indicators and the selection when every
+    // lane's top candidate has IS <= delta (then it is every lane's choice).
+    __device__ __forceinline__ static double run(const double (&f)[W], double delta, int &sel)
     {
         if constexpr (ORDER == 5) {
             const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
@@ -190,10 +108,17 @@ template <int ORDER> struct Recon {
             const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
             const double e0 = d1 - d0, e1 = d2 - d1;
             const double is_top = fmin(fabs(e0), fabs(e1));  // S_{j-2}^{j+2}
+            double h[6];
+            h[0] = f[3];
+            h[1] = fma(0.5, a3, h[0]);
+            h[2] = fma(-1.0 / 6.0, b2, h[1]);
+            h[3] = fma(-1.0 / 12.0, c1, h[2]);
+            h[5] = fma(-1.0 / 20.0, d1, h[3]);
             if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
                 sel = 5;
-                return row_dot<W, FluxRows<5>::TW>(f, tab, 5);
+                return h[5];
             }
+            h[4] = fma(-1.0 / 12.0, c2, h[2]);
             const double ad1 = fabs(d1);
             double is[6];
             is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
@@ -202,17 +127,51 @@ template <int ORDER> struct Recon {
             is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
             is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
             is[5] = is_top;
-            sel = select_candidate<6>(is, delta);
+            return select_candidate<6>(is, h, delta, sel);
         } else {
-            double is[9];
-            indicators7(f, is);
-            if (ENOAO_EARLY_EXIT && wave_all(is[8] <= delta)) {
+            double a[8], b[7], c[6], d[5], e[4], g[3], q[2];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = f[i + 1] - f[i];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) b[i] = a[i + 1] - a[i];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) c[i] = b[i + 1] - b[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) d[i] = c[i + 1] - c[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[i] = d[i + 1] - d[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) g[i] = e[i + 1] - e[i];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) q[i] = g[i + 1] - g[i];
+            const double is_top = fmin(fabs(q[0]), fabs(q[1]));  // S_{j-3}^{j+3}
+            double h[9];
+            h[0] = f[4];
+            h[1] = fma(0.5, a[4], h[0]);
+            h[2] = fma(-1.0 / 6.0, b[3], h[1]);
+            h[3] = fma(-1.0 / 12.0, c[2], h[2]);
+            h[5] = fma(-1.0 / 20.0, d[2], h[3]);
+            h[6] = fma(1.0 / 60.0, e[1], h[5]);
+            h[8] = fma(1.0 / 105.0, g[1], h[6]);
+            if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
                 sel = 8;
-                return row_dot<W, FluxRows<7>::TW>(f, tab, 8);
+                return h[8];
             }
-            sel = select_candidate<9>(is, delta);
+            h[4] = fma(-1.0 / 12.0, c[3], h[2]);
+            h[7] = fma(1.0 / 60.0, e[2], h[5]);
+            const double ad2 = fabs(d[2]), ag1 = fabs(g[1]);
+            double is[9];
+            is[0] = 0.5 * fmin(fabs(a[3]) + fabs(a[2]), fabs(a[4]) + fabs(a[5])); // S_j^j
+            is[1] = fmin(fabs(b[3]), fabs(b[4]));                                  // S_j^{j+1}
+            is[2] = fmin(fabs(c[2]), fabs(c[3]));                                  // S_{j-1}^{j+1}
+            is[3] = fmin(fabs(d[1]), ad2);                                         // S_{j-2}^{j+1}
+            is[4] = fmin(ad2, fabs(d[3]));                                         // S_{j-1}^{j+2}
+            is[5] = fmin(fabs(e[1]), fabs(e[2]));                                  // S_{j-2}^{j+2}
+            is[6] = fmin(fabs(g[0]), ag1);                                         // S_{j-3}^{j+2}
+            is[7] = fmin(ag1, fabs(g[2]));                                         // S_{j-2}^{j+3}
+            is[8] = is_top;
+            return select_candidate<9>(is, h, delta, sel);
         }
-        return row_dot<W, FluxRows<ORDER>::TW>(f, tab, sel);
     }
 };
 

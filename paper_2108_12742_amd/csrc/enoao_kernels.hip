@@ -130,7 +130,7 @@ template <int EQ> struct Maxima {
 // live window registers.
 template <int NC, int ORDER, int F0, int F1>
 __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const RoeState &r, const double *al,
-                                           double delta, const double *tab, double (&wh)[NC], int (&sel)[2 * NC])
+                                           double delta, double (&wh)[NC], int (&sel)[2 * NC])
 {
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1;
     constexpr int NF = F1 >= 0 ? 2 : 1;
@@ -178,8 +178,8 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
         // window = 2 * field_scale * w^(+/-)
         const double sc = 2.0 * field_scale<NC>(s);
         int sp, sm;
-        const double hp = Recon<ORDER>::run(gp[i], sc * delta, tab, sp);
-        const double hm = Recon<ORDER>::run(gm[i], sc * delta, tab, sm);
+        const double hp = Recon<ORDER>::run(gp[i], sc * delta, sp);
+        const double hm = Recon<ORDER>::run(gm[i], sc * delta, sm);
         wh[s] = (hp + hm) * (1.0 / sc);
         sel[2 * s] = sp;
         sel[2 * s + 1] = sm;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
 
 template <int EQ, int ORDER>
 __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, const double *al, double gm1,
-                                          double delta, double adv, const double *tab,
+                                          double delta, double adv,
                                           double (&Fh)[NodeTraits<EQ>::NC], int (&sel)[2 * NodeTraits<EQ>::NC])
 {
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1;
@@ -203,8 +203,8 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
             if (t >= 1) gm[2 * H + 1 - t] = fma(-al[0], u, au);
         }
         int sp, sm;
-        const double hp = Recon<ORDER>::run(gp, 2.0 * delta, tab, sp);
-        const double hm = Recon<ORDER>::run(gm, 2.0 * delta, tab, sm);
+        const double hp = Recon<ORDER>::run(gp, 2.0 * delta, sp);
+        const double hm = Recon<ORDER>::run(gm, 2.0 * delta, sm);
         Fh[0] = 0.5 * (hp + hm);
         sel[0] = sp;
         sel[1] = sm;
@@ -220,11 +220,11 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
                           nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
         double wh[NC];
         if constexpr (NC == 4) {
-            field_pass<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, tab, wh, sel);
-            field_pass<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, tab, wh, sel);
+            field_pass<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, wh, sel);
+            field_pass<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, wh, sel);
         } else {
-            field_pass<3, ORDER, 0, 2>(w0, qs, ns, r, al, delta, tab, wh, sel);
-            field_pass<3, ORDER, 1, -1>(w0, qs, ns, r, al, delta, tab, wh, sel);
+            field_pass<3, ORDER, 0, 2>(w0, qs, ns, r, al, delta, wh, sel);
+            field_pass<3, ORDER, 1, -1>(w0, qs, ns, r, al, delta, wh, sel);
         }
         back_project<NC>(r, wh, Fh);
     }
@@ -282,17 +282,30 @@ struct XSeg {
     int row, sx;  // grid line and first cell of the segment
 };
 
+// (segment counts of an instance fit 32 bits: ny * ceil(nx / 63) segments)
 __device__ __forceinline__ XSeg x_segment(const KParams &P, int n_inst, long long tile, int wseg)
 {
     XSeg g;
     g.k = find_inst<true>(P.inst, n_inst, tile);
     const Inst &I = P.inst[g.k];
-    const long long seg = (tile - I.xtile0) * XW_SEGS + wseg;
-    g.ok = seg < (long long)I.ny * I.segs_per_row;
-    g.row = g.ok ? (int)(seg / I.segs_per_row) : 0;
-    g.sx = g.ok ? (int)(seg % I.segs_per_row) * XW_CELLS : 0;
+    const unsigned seg = (unsigned)(tile - I.xtile0) * XW_SEGS + (unsigned)wseg;
+    const unsigned spr = (unsigned)I.segs_per_row;
+    g.ok = seg < (unsigned)I.ny * spr;
+    const unsigned row = seg / spr;
+    g.row = g.ok ? (int)row : 0;
+    g.sx = g.ok ? (int)(seg - row * spr) * XW_CELLS : 0;
     g.active = I.ctrl->done == 0;
     return g;
+}
+
+// LDS exchange among the lanes of one wave: the wave's LDS operations are
+// performed in order, so a wavefront-scope fence pair around a wave barrier
+// orders each lane's writes before every lane's later reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // a lane's global operands of one x tile: the nodes it stages (segment
@@ -340,11 +353,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
     __shared__ double lds[NQ * XW_SEGS * NNP];
     __shared__ double fh[NC * XW_SEGS * XW_FACES];
     __shared__ double red[(BLOCK / 64) * 8];
-    __shared__ __attribute__((aligned(16))) double ftab[ReconTraits<ORDER>::K * FluxRows<ORDER>::TW];
-    load_flux_rows<ORDER>(ftab);
-    __syncthreads();
 
-    const int tid = threadIdx.x, wseg = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wseg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->xtiles_total;
     const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
@@ -352,13 +363,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
     mx.reset();
     int cur = -1;
     XPre<NC> pre;
+    XSeg gn{};  // segment of the next tile
     if (t0 < t1) {
-        const XSeg g0 = x_segment(P, n_inst, t0, wseg);
-        x_prefetch<EQ, MODE, G>(P.inst[g0.k], g0, lane, pre);
+        gn = x_segment(P, n_inst, t0, wseg);
+        x_prefetch<EQ, MODE, G>(P.inst[gn.k], gn, lane, pre);
     }
 
+    // Each wave owns its segment's LDS (nodes and face fluxes), so within the
+    // tile loop the waves synchronise only with themselves; all waves of a
+    // workgroup walk the same tiles, so the maxima flush (a workgroup
+    // reduction) is reached by all of them together.
     for (long long tile = t0; tile < t1; ++tile) {
-        const XSeg g = x_segment(P, n_inst, tile, wseg);
+        const XSeg g = gn;
         const Inst &I = P.inst[g.k];
         if (FULL && g.k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
         cur = g.k;
@@ -384,11 +400,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
         for (int c = 0; c < NC; ++c) base[c] = pre.base[c];
         // issue the next tile's loads before this tile's arithmetic
         if (tile + 1 < t1) {
-            const XSeg gn = x_segment(P, n_inst, tile + 1, wseg);
+            gn = x_segment(P, n_inst, tile + 1, wseg);
             x_prefetch<EQ, MODE, G>(P.inst[gn.k], gn, lane, pre);
         }
         if (!g.active) continue;  // uniform: all waves of a tile belong to one instance
-        __syncthreads();
+        wave_sync();
 
         const int nx = I.nx, ny = I.ny;
         const long long plane = (long long)nx * ny;
@@ -398,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
         if (g.ok) {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, al, P.gm1, P.delta, I.adv, ftab, Fh, sel);
+            face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, al, P.gm1, P.delta, I.adv, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fh[(c * XW_SEGS + wseg) * XW_FACES + lane] = Fh[c];
             if (REC && I.sel && f <= nx) {
@@ -411,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
 
         const int x = g.sx + lane;
         if (g.ok && lane < XW_CELLS && x < nx) {
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
                 mx.add(Un, P.gamma, I.dx, I.dy);
             }
         }
-        __syncthreads();
+        wave_sync();
     }
     if (FULL && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
 }
@@ -513,15 +529,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
     __shared__ double lds[NQ * QS];
     __shared__ double fh[NC * YT_FACES * YT_COLS];
     __shared__ double red[(BLOCK / 64) * 8];
-    __shared__ __attribute__((aligned(16))) double ftab[ReconTraits<ORDER>::K * FluxRows<ORDER>::TW];
     // epilogue operands of the tile (x-part of L, u^n), staged from the prefetch
     // registers so they are not held through the face arithmetic
     constexpr bool BASE = MODE == M_S2 || MODE == M_S3;
     __shared__ double elx[NC * BLOCK];
     __shared__ double ebase[BASE ? NC * BLOCK : 1];
     const int perm[4] = {0, 2, 1, 3};
-    load_flux_rows<ORDER>(ftab);
-    __syncthreads();
 
     const int tid = threadIdx.x, cc = tid & (YT_COLS - 1), fl = tid / YT_COLS;
     const int n_inst = P.hdr->n_inst;
@@ -576,7 +589,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
         {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EULER2D, ORDER>(lds + fl * YT_COLS + cc, QS, YT_COLS, al, P.gm1, P.delta, 0.0, ftab, Fh, sel);
+            face_flux<EULER2D, ORDER>(lds + fl * YT_COLS + cc, QS, YT_COLS, al, P.gm1, P.delta, 0.0, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fh[(c * YT_FACES + fl) * YT_COLS + cc] = Fh[c];
             if (REC && I.sel && col < nx && f <= ny) {
