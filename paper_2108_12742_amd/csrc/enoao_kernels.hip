@@ -19,6 +19,14 @@
 #include "enoao_device.hpp"
 #include "enoao_kernels.hpp"
 
+// Tuning switches (defaults are the measured best on gfx950).
+#ifndef ENOAO_NODE_PREFETCH
+#define ENOAO_NODE_PREFETCH 1  // stencil nodes whose LDS reads are in flight ahead of use
+#endif
+#ifndef ENOAO_NODE_SCHED
+#define ENOAO_NODE_SCHED 1     // scheduling barrier per stencil node (bounds register use)
+#endif
+
 namespace enoao {
 
 __device__ __forceinline__ int bc_map(int k, int n, int bc)
@@ -58,23 +66,23 @@ template <int EQ> struct Maxima {
         for (int i = 0; i < 7; ++i) v[i] = 0.0;
         bad = 0;
     }
-    // U in the natural component order
-    __device__ void add(const double *U, double gamma, double dx, double dy)
+    // U in the natural component order; idx, idy = 1/dx, 1/dy
+    __device__ void add(const double *U, double gamma, double idx, double idy)
     {
         if constexpr (EQ == ADVECTION) {
             bad |= !(U[0] == U[0]);
         } else if constexpr (EQ == EULER1D) {
-            const double rho = U[0], u = U[1] / rho;
+            const double rho = U[0], ir = rcp_nr(rho), u = U[1] * ir;
             const double p = (gamma - 1.0) * (U[2] - 0.5 * rho * (u * u));
-            const double c = sqrt(gamma * p / rho);
+            const double c = sqrt(gamma * p * ir);
             bad |= !(rho > 0.0 && p > 0.0);
             v[0] = fmax(v[0], fabs(u - c));
             v[1] = fmax(v[1], fabs(u));
             v[2] = fmax(v[2], fabs(u + c));
         } else {
-            const double rho = U[0], u = U[1] / rho, w = U[2] / rho;
+            const double rho = U[0], ir = rcp_nr(rho), u = U[1] * ir, w = U[2] * ir;
             const double p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + w * w));
-            const double c = sqrt(gamma * p / rho);
+            const double c = sqrt(gamma * p * ir);
             bad |= !(rho > 0.0 && p > 0.0);
             v[0] = fmax(v[0], fabs(u - c));
             v[1] = fmax(v[1], fabs(u));
@@ -82,11 +90,11 @@ template <int EQ> struct Maxima {
             v[3] = fmax(v[3], fabs(w - c));
             v[4] = fmax(v[4], fabs(w));
             v[5] = fmax(v[5], fabs(w + c));
-            v[6] = fmax(v[6], (fabs(u) + c) / dx + (fabs(w) + c) / dy);
+            v[6] = fmax(v[6], fma(fabs(u) + c, idx, (fabs(w) + c) * idy));
         }
     }
     // workgroup reduction, then one atomic per value into the instance's slot
-    __device__ void flush(const Inst &I, int slot, double *red)
+    __device__ void flush(unsigned long long *amax, Ctrl *ctrl, int slot, double *red)
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -110,9 +118,9 @@ template <int EQ> struct Maxima {
             for (int w = 1; w < BLOCK / 64; ++w) x = fmax(x, red[w * 8 + threadIdx.x]);
             if (threadIdx.x < 7) {
                 if (EQ != ADVECTION && slot >= 0)
-                    atomicMax(&I.amax[slot * AMAX_VALS + threadIdx.x], as_bits(x));
+                    atomicMax(&amax[slot * AMAX_VALS + threadIdx.x], as_bits(x));
             } else if (x != 0.0) {
-                atomicOr(&I.ctrl->status, 1);
+                atomicOr(&ctrl->status, 1);
             }
         }
         __syncthreads();
@@ -136,41 +144,37 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
     constexpr int NF = F1 >= 0 ? 2 : 1;
     constexpr int fs[2] = {F0, F1 >= 0 ? F1 : F0};
     double gp[NF][W], gm[NF][W];
-    double U[NC], F[NC];
+    // node t's LDS reads go out NODE_PREFETCH nodes ahead of its arithmetic
+    constexpr int D = ENOAO_NODE_PREFETCH;
+    double Uq[2 * G][NC], Fq[2 * G][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        U[c] = w0[c * qs];
-        F[c] = w0[(NC + c) * qs];
+    for (int t = 0; t < D && t < 2 * G; ++t) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Uq[t][c] = w0[c * qs + t * ns];
+            Fq[t][c] = w0[(NC + c) * qs + t * ns];
+        }
     }
 #pragma unroll
     for (int t = 0; t < 2 * G; ++t) {
-        // next node's LDS reads go out before this node's arithmetic
-        double Un[NC], Fn[NC];
-        if (t + 1 < 2 * G) {
+        if (t + D < 2 * G) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                Un[c] = w0[c * qs + (t + 1) * ns];
-                Fn[c] = w0[(NC + c) * qs + (t + 1) * ns];
+                Uq[t + D][c] = w0[c * qs + (t + D) * ns];
+                Fq[t + D][c] = w0[(NC + c) * qs + (t + D) * ns];
             }
         }
         double PU[NC], PF[NC];
-        project<NC>(r, U, PU);
-        project<NC>(r, F, PF);
+        project<NC>(r, Uq[t], PU);
+        project<NC>(r, Fq[t], PF);
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             const int s = fs[i];
             if (t < W) gp[i][t] = fma(al[s], PU[s], PF[s]);
             if (t >= 1) gm[i][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
         }
-        if (t + 1 < 2 * G) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                U[c] = Un[c];
-                F[c] = Fn[c];
-            }
-        }
-        // bound the live ranges: at most two nodes' U and F in flight
-        __builtin_amdgcn_sched_barrier(0);
+        // bound the live ranges: at most D + 1 nodes' U and F in flight
+        if (ENOAO_NODE_SCHED) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
@@ -230,22 +234,6 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
     }
 }
 
-template <int EQ>
-__device__ __forceinline__ void load_alpha(const Inst &I, int slot, bool ydir, double *al)
-{
-    constexpr int NC = NodeTraits<EQ>::NC;
-    if constexpr (EQ == ADVECTION) {
-        al[0] = fabs(I.adv);
-    } else {
-        const unsigned long long *a = I.amax + slot * AMAX_VALS + (ydir ? 3 : 0);
-        const double m0 = as_double(a[0]), m1 = as_double(a[1]), m2 = as_double(a[2]);
-        al[0] = m0;
-        al[1] = m1;
-        if (NC == 4) al[2] = m1;
-        al[NC - 1] = m2;
-    }
-}
-
 // RK stage combine (Shu-Osher form): s = 1: in + dt L; s = 2: 3/4 base +
 // 1/4 (in + dt L); s = 3: 1/3 base + 2/3 (in + dt L).
 template <int MODE>
@@ -257,13 +245,73 @@ __device__ __forceinline__ double rk_combine(double in, double base, double dt, 
     else return fma(1.0 / 3.0, base, (2.0 / 3.0) * y);
 }
 
-template <int MODE> __device__ __forceinline__ const double *stage_in(const Inst &I)
+// wave-uniform copy of a value (scalar registers)
+template <typename T> __device__ __forceinline__ T uniform(T x)
 {
-    return MODE == M_S2 ? I.w1 : (MODE == M_S3 ? I.w2 : I.u);
+    static_assert(sizeof(T) % 4 == 0, "32-bit multiple");
+    union { T v; int w[sizeof(T) / 4]; } a;
+    a.v = x;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) a.w[i] = __builtin_amdgcn_readfirstlane(a.w[i]);
+    return a.v;
 }
-template <int MODE> __device__ __forceinline__ double *stage_out(const Inst &I)
+
+// Per-instance values of one sweep launch.  A workgroup walks a contiguous
+// chunk of the tile list, so it reloads them only when the walk crosses into
+// another instance; within an instance no tile reads a descriptor.
+template <int EQ, int MODE> struct View {
+    static constexpr int NC = NodeTraits<EQ>::NC;
+    long long t0, t1;      // the instance's tiles in the batch list
+    int k, nx, ny, per_row, bc;
+    int active;            // the instance is still stepping
+    const double *in;      // stage input
+    double *out;           // stage output
+    const double *base;    // u^n (stages 2 and 3)
+    double *lx;            // x-part of L (2D) / L (rhs)
+    uint8_t *sel;
+    unsigned long long *amax;
+    Ctrl *ctrl;
+    double idx, idy, adv, dt;
+    double al[NC];
+};
+
+template <int EQ, int MODE, bool Y>
+__device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst, long long tile)
 {
-    return MODE == M_S1 ? I.w1 : (MODE == M_S2 ? I.w2 : I.u);
+    constexpr int NC = NodeTraits<EQ>::NC;
+    View<EQ, MODE> v;
+    v.k = uniform(find_inst<!Y>(P.inst, n_inst, tile));
+    const Inst &I = P.inst[v.k];
+    v.t0 = uniform(Y ? I.ytile0 : I.xtile0);
+    v.t1 = v.t0 + uniform(Y ? I.ytiles : I.xtiles);
+    v.nx = uniform(I.nx);
+    v.ny = uniform(I.ny);
+    v.per_row = uniform(Y ? I.ytiles_per_row : I.segs_per_row);
+    v.bc = uniform(Y ? I.bcy : I.bcx);
+    Ctrl *ctrl = uniform(I.ctrl);
+    v.ctrl = ctrl;
+    v.active = uniform(ctrl->done) == 0;
+    v.dt = uniform(ctrl->dt);
+    v.in = uniform(MODE == M_S2 ? I.w1 : (MODE == M_S3 ? I.w2 : I.u));
+    v.out = uniform(MODE == M_S1 ? I.w1 : (MODE == M_S2 ? I.w2 : I.u));
+    v.base = uniform(I.u);
+    v.lx = uniform(I.lx);
+    v.sel = uniform(I.sel);
+    v.amax = uniform(I.amax);
+    v.idx = 1.0 / uniform(I.dx);
+    v.idy = 1.0 / uniform(I.dy);
+    v.adv = uniform(I.adv);
+    if constexpr (EQ == ADVECTION) {
+        v.al[0] = fabs(v.adv);
+    } else {
+        const unsigned long long *a = v.amax + P.r_in * AMAX_VALS + (Y ? 3 : 0);
+        const double m0 = uniform(as_double(a[0])), m1 = uniform(as_double(a[1])), m2 = uniform(as_double(a[2]));
+        v.al[0] = m0;
+        v.al[1] = m1;
+        if (NC == 4) v.al[2] = m1;
+        v.al[NC - 1] = m2;
+    }
+    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -271,31 +319,34 @@ template <int MODE> __device__ __forceinline__ double *stage_out(const Inst &I)
 // Tiles are software-pipelined: the global operands of tile t+1 are loaded into
 // registers while tile t is reconstructed, so the memory latency hides behind
 // the face arithmetic.
-#ifndef ENOAO_SWEEP_WAVES_PER_EU
-#define ENOAO_SWEEP_WAVES_PER_EU 1
+#ifndef ENOAO_X_WAVES_PER_EU
+#define ENOAO_X_WAVES_PER_EU 1
+#endif
+#ifndef ENOAO_Y_WAVES_PER_EU
+#define ENOAO_Y_WAVES_PER_EU 1
 #endif
 
-struct XSeg {
-    int k;        // instance
-    bool ok;      // this wave has a segment in the tile
-    bool active;  // the instance is still stepping (uniform over the tile)
-    int row, sx;  // grid line and first cell of the segment
+// a wave's segment within its instance: grid line and segment index along it
+struct XCur {
+    int row, segx;
 };
 
-// (segment counts of an instance fit 32 bits: ny * ceil(nx / 63) segments)
-__device__ __forceinline__ XSeg x_segment(const KParams &P, int n_inst, long long tile, int wseg)
+__device__ __forceinline__ XCur x_cursor(long long tile, long long t0, int per_row, int wseg)
 {
-    XSeg g;
-    g.k = find_inst<true>(P.inst, n_inst, tile);
-    const Inst &I = P.inst[g.k];
-    const unsigned seg = (unsigned)(tile - I.xtile0) * XW_SEGS + (unsigned)wseg;
-    const unsigned spr = (unsigned)I.segs_per_row;
-    g.ok = seg < (unsigned)I.ny * spr;
-    const unsigned row = seg / spr;
-    g.row = g.ok ? (int)row : 0;
-    g.sx = g.ok ? (int)(seg - row * spr) * XW_CELLS : 0;
-    g.active = I.ctrl->done == 0;
-    return g;
+    // (segment counts of an instance fit 32 bits: ny * ceil(nx / 63))
+    const unsigned seg = (unsigned)(tile - t0) * XW_SEGS + (unsigned)wseg;
+    const unsigned row = seg / (unsigned)per_row;
+    return XCur{(int)row, (int)(seg - row * (unsigned)per_row)};
+}
+
+__device__ __forceinline__ XCur x_advance(XCur c, int per_row)
+{
+    c.segx += XW_SEGS;
+    while (c.segx >= per_row) {
+        c.segx -= per_row;
+        ++c.row;
+    }
+    return c;
 }
 
 // LDS exchange among the lanes of one wave: the wave's LDS operations are
@@ -316,34 +367,34 @@ template <int NC> struct XPre {
 };
 
 template <int EQ, int MODE, int G>
-__device__ __forceinline__ void x_prefetch(const Inst &I, const XSeg &g, int lane, XPre<NodeTraits<EQ>::NC> &pre)
+__device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int lane, XPre<NodeTraits<EQ>::NC> &pre)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NN = XW_FACES + 2 * G - 1;
-    if (!g.ok || !g.active) return;
-    const int nx = I.nx;
-    const long long plane = (long long)nx * I.ny;
-    const double *rowp = stage_in<MODE>(I) + (long long)g.row * nx;
+    if (c.row >= v.ny) return;
+    const int nx = v.nx, sx = c.segx * XW_CELLS;
+    const long long plane = (long long)nx * v.ny;
+    const double *rowp = v.in + (long long)c.row * nx;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int i = lane + 64 * j;
         if (i < NN) {
-            const int x = bc_map(g.sx - G + i, nx, I.bcx);
+            const int x = bc_map(sx - G + i, nx, v.bc);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) pre.U[j][c] = rowp[c * plane + x];
+            for (int q = 0; q < NC; ++q) pre.U[j][q] = rowp[q * plane + x];
         }
     }
     if constexpr (EQ != EULER2D && (MODE == M_S2 || MODE == M_S3)) {
-        const int x = g.sx + lane;
+        const int x = sx + lane;
         if (lane < XW_CELLS && x < nx) {
-            const double *b = I.u + (long long)g.row * nx + x;
+            const double *b = v.base + (long long)c.row * nx + x;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) pre.base[c] = b[c * plane];
+            for (int q = 0; q < NC; ++q) pre.base[q] = b[q * plane];
         }
     }
 }
 
 template <int EQ, int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWEEP_WAVES_PER_EU))) void sweep_x(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
@@ -361,124 +412,128 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
     const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
     Maxima<EQ> mx;
     mx.reset();
-    int cur = -1;
     XPre<NC> pre;
-    XSeg gn{};  // segment of the next tile
-    if (t0 < t1) {
-        gn = x_segment(P, n_inst, t0, wseg);
-        x_prefetch<EQ, MODE, G>(P.inst[gn.k], gn, lane, pre);
-    }
+    double *L = lds + wseg * NNP;
 
     // Each wave owns its segment's LDS (nodes and face fluxes), so within the
-    // tile loop the waves synchronise only with themselves; all waves of a
-    // workgroup walk the same tiles, so the maxima flush (a workgroup
-    // reduction) is reached by all of them together.
-    for (long long tile = t0; tile < t1; ++tile) {
-        const XSeg g = gn;
-        const Inst &I = P.inst[g.k];
-        if (FULL && g.k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
-        cur = g.k;
-        if (g.active && MODE != M_RHS && P.r_zero >= 0 && tile == I.xtile0 && tid < AMAX_VALS)
-            I.amax[P.r_zero * AMAX_VALS + tid] = 0ull;
+    // tile loop the waves synchronise only with themselves.  The outer loop
+    // runs once per instance met by the workgroup's chunk (uniform over the
+    // workgroup, so the maxima flush, a workgroup reduction, is reached by all
+    // waves together).
+    for (long long tile = t0; tile < t1;) {
+        const View<EQ, MODE> v = load_view<EQ, MODE, false>(P, n_inst, tile);
+        const long long tend = v.t1 < t1 ? v.t1 : t1;
+        if (!v.active) {
+            tile = tend;
+            continue;
+        }
+        if (MODE != M_RHS && P.r_zero >= 0 && tile == v.t0 && tid < AMAX_VALS)
+            v.amax[P.r_zero * AMAX_VALS + tid] = 0ull;
+        const int nx = v.nx;
+        const long long plane = (long long)nx * v.ny;
+        XCur c = x_cursor(tile, v.t0, v.per_row, wseg);
+        x_prefetch<EQ, MODE, G>(v, c, lane, pre);
+        for (; tile < tend; ++tile) {
+            const bool ok = c.row < v.ny;
+            const int sx = c.segx * XW_CELLS;
 
-        // stage this tile's nodes (flux, Roe inputs) into LDS
-        double *L = lds + wseg * NNP;
-        if (g.active && g.ok) {
+            // stage this tile's nodes (flux, Roe inputs) into LDS
+            if (ok) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int i = lane + 64 * j;
-                if (i < NN) {
-                    double q[NQ];
-                    node_quantities<EQ>(pre.U[j], P.gm1, q);
+                for (int j = 0; j < 2; ++j) {
+                    const int i = lane + 64 * j;
+                    if (i < NN) {
+                        double q[NQ];
+                        node_quantities<EQ>(pre.U[j], P.gm1, q);
 #pragma unroll
-                    for (int m = 0; m < NQ; ++m) L[m * XW_SEGS * NNP + i] = q[m];
+                        for (int m = 0; m < NQ; ++m) L[m * XW_SEGS * NNP + i] = q[m];
+                    }
                 }
             }
-        }
-        double base[NC];
+            double base[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) base[c] = pre.base[c];
-        // issue the next tile's loads before this tile's arithmetic
-        if (tile + 1 < t1) {
-            gn = x_segment(P, n_inst, tile + 1, wseg);
-            x_prefetch<EQ, MODE, G>(P.inst[gn.k], gn, lane, pre);
-        }
-        if (!g.active) continue;  // uniform: all waves of a tile belong to one instance
-        wave_sync();
+            for (int q = 0; q < NC; ++q) base[q] = pre.base[q];
+            // issue the next tile's loads before this tile's arithmetic
+            const XCur cn = x_advance(c, v.per_row);
+            if (tile + 1 < tend) x_prefetch<EQ, MODE, G>(v, cn, lane, pre);
+            wave_sync();
 
-        const int nx = I.nx, ny = I.ny;
-        const long long plane = (long long)nx * ny;
-        double al[NC];
-        load_alpha<EQ>(I, P.r_in, false, al);
-        const int f = g.sx + lane;  // face index along the line
-        if (g.ok) {
-            double Fh[NC];
-            int sel[2 * NC];
-            face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, al, P.gm1, P.delta, I.adv, Fh, sel);
+            const int f = sx + lane;  // face index along the line
+            if (ok) {
+                double Fh[NC];
+                int sel[2 * NC];
+                face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, v.al, P.gm1, P.delta, v.adv, Fh, sel);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) fh[(c * XW_SEGS + wseg) * XW_FACES + lane] = Fh[c];
-            if (REC && I.sel && f <= nx) {
-                const long long xblock = (long long)ny * (nx + 1);
+                for (int q = 0; q < NC; ++q) fh[(q * XW_SEGS + wseg) * XW_FACES + lane] = Fh[q];
+                if (REC && v.sel && f <= nx) {
+                    const long long xblock = (long long)v.ny * (nx + 1);
 #pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const long long o = (long long)(2 * s) * xblock + (long long)g.row * (nx + 1) + f;
-                    I.sel[o] = (uint8_t)sel[2 * s];
-                    I.sel[o + xblock] = (uint8_t)sel[2 * s + 1];
+                    for (int s = 0; s < NC; ++s) {
+                        const long long o = (long long)(2 * s) * xblock + (long long)c.row * (nx + 1) + f;
+                        v.sel[o] = (uint8_t)sel[2 * s];
+                        v.sel[o + xblock] = (uint8_t)sel[2 * s + 1];
+                    }
                 }
             }
-        }
-        wave_sync();
+            wave_sync();
 
-        const int x = g.sx + lane;
-        if (g.ok && lane < XW_CELLS && x < nx) {
-            const double idx = -1.0 / I.dx;
-            const long long o = (long long)g.row * nx + x;
-            double Lc[NC];
+            const int x = sx + lane;
+            if (ok && lane < XW_CELLS && x < nx) {
+                const long long o = (long long)c.row * nx + x;
+                double Lc[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                Lc[c] = (fh[(c * XW_SEGS + wseg) * XW_FACES + lane + 1] - fh[(c * XW_SEGS + wseg) * XW_FACES + lane]) * idx;
-            if constexpr (!FULL) {
+                for (int q = 0; q < NC; ++q)
+                    Lc[q] = -(fh[(q * XW_SEGS + wseg) * XW_FACES + lane + 1] - fh[(q * XW_SEGS + wseg) * XW_FACES + lane]) * v.idx;
+                if constexpr (!FULL) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) I.lx[c * plane + o] = Lc[c];
-            } else {
-                const double dt = I.ctrl->dt;
-                double *out = stage_out<MODE>(I);
-                double Un[NC];
+                    for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = Lc[q];
+                } else {
+                    double Un[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const double uin = L[c * XW_SEGS * NNP + lane + G];
-                    Un[c] = rk_combine<MODE>(uin, base[c], dt, Lc[c]);
-                    out[c * plane + o] = Un[c];
+                    for (int q = 0; q < NC; ++q) {
+                        const double uin = L[q * XW_SEGS * NNP + lane + G];
+                        Un[q] = rk_combine<MODE>(uin, base[q], v.dt, Lc[q]);
+                        v.out[q * plane + o] = Un[q];
+                    }
+                    mx.add(Un, P.gamma, v.idx, v.idy);
                 }
-                mx.add(Un, P.gamma, I.dx, I.dy);
             }
+            wave_sync();
+            c = cn;
         }
-        wave_sync();
+        if (FULL) mx.flush(v.amax, v.ctrl, P.r_out, red);
     }
-    if (FULL && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D).  A workgroup: 16 columns x 16 faces along y, 16 x 15 cells.
-// Momentum components are exchanged on load so the x-direction formulas apply.
-// Pipelined like the x-sweep; the epilogue operands (x-part of L, u^n) are
-// prefetched with the nodes.
-struct YTile {
-    int k;
-    bool active;
-    int sy, col0;  // first cell row, first column
+// y-sweep (2D).  A workgroup tile: 16 columns x 16 faces along y (16 x 15
+// cells); each wave owns a strip of 4 columns (lane = 4 * face row + column),
+// stages its strip's nodes itself and exchanges face fluxes only among its own
+// lanes, so the tile loop has no workgroup barrier.  Momentum components are
+// exchanged on load so the x-direction formulas apply.  Pipelined like the
+// x-sweep; the epilogue operands (x-part of L, u^n) are prefetched with the
+// nodes.
+constexpr int YW_COLS = YT_COLS / (BLOCK / 64);  // columns per wave
+
+// a tile's position within its instance: tile row along y, column group
+struct YCur {
+    int ty, cg;
 };
 
-__device__ __forceinline__ YTile y_tile(const KParams &P, int n_inst, long long tile)
+__device__ __forceinline__ YCur y_cursor(long long tile, long long t0, int per_row)
 {
-    YTile t;
-    t.k = find_inst<false>(P.inst, n_inst, tile);
-    const Inst &I = P.inst[t.k];
-    const long long tl = tile - I.ytile0;
-    t.sy = (int)(tl % I.ytiles_per_row) * YT_CELLS;
-    t.col0 = (int)(tl / I.ytiles_per_row) * YT_COLS;
-    t.active = I.ctrl->done == 0;
-    return t;
+    // (tile counts of an instance fit 32 bits)
+    const unsigned tl = (unsigned)(tile - t0), cg = tl / (unsigned)per_row;
+    return YCur{(int)(tl - cg * (unsigned)per_row), (int)cg};
+}
+
+__device__ __forceinline__ YCur y_advance(YCur c, int per_row)
+{
+    if (++c.ty == per_row) {
+        c.ty = 0;
+        ++c.cg;
+    }
+    return c;
 }
 
 struct YPre {
@@ -486,49 +541,50 @@ struct YPre {
     double lx[4], base[4];
 };
 
+// a lane's global operands of one y tile: the strip nodes it stages (strip
+// positions lane and lane + 64) and the x-part of L (+ u^n) at its cell
 template <int MODE, int G>
-__device__ __forceinline__ void y_prefetch(const Inst &I, const YTile &t, int tid, YPre &pre)
+__device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c, int wv, int lane, YPre &pre)
 {
     constexpr int NR = YT_FACES + 2 * G - 1;
     const int perm[4] = {0, 2, 1, 3};
-    if (!t.active) return;
-    const int nx = I.nx, ny = I.ny;
+    const int nx = v.nx, ny = v.ny;
     const long long plane = (long long)nx * ny;
-    const double *in = stage_in<MODE>(I);
+    const int sy = c.ty * YT_CELLS, cbase = c.cg * YT_COLS + wv * YW_COLS;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const int i = tid + BLOCK * j;
-        if (i < NR * YT_COLS) {
-            const int r = i / YT_COLS, c0 = i % YT_COLS;
-            const int y = bc_map(t.sy - G + r, ny, I.bcy);
-            const int x = min(t.col0 + c0, nx - 1);
-            const double *p = in + (long long)y * nx + x;
+        const int i = lane + 64 * j;
+        if (i < NR * YW_COLS) {
+            const int r = i / YW_COLS, c0 = i % YW_COLS;
+            const int y = bc_map(sy - G + r, ny, v.bc);
+            const int x = min(cbase + c0, nx - 1);
+            const double *p = v.in + (long long)y * nx + x;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) pre.U[j][c] = p[perm[c] * plane];
+            for (int q = 0; q < 4; ++q) pre.U[j][q] = p[perm[q] * plane];
         }
     }
-    const int fl = tid / YT_COLS, y = t.sy + fl, col = t.col0 + (tid & (YT_COLS - 1));
+    const int fl = lane / YW_COLS, y = sy + fl, col = cbase + (lane % YW_COLS);
     if (fl < YT_CELLS && y < ny && col < nx) {
         const long long o = (long long)y * nx + col;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pre.lx[c] = I.lx[c * plane + o];
+        for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
         if constexpr (MODE == M_S2 || MODE == M_S3) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) pre.base[c] = I.u[c * plane + o];
+            for (int q = 0; q < 4; ++q) pre.base[q] = v.base[q * plane + o];
         }
     }
 }
 
 template <int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWEEP_WAVES_PER_EU))) void sweep_y(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_WAVES_PER_EU))) void sweep_y(KParams P)
 {
-    constexpr int NC = 4, NQ = 12;
+    constexpr int NC = 4, NQ = 12, NW = BLOCK / 64;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
     constexpr int NR = YT_FACES + 2 * G - 1;  // node rows staged
-    constexpr int QS = NR * YT_COLS;         // LDS stride between quantities
-    __shared__ double lds[NQ * QS];
-    __shared__ double fh[NC * YT_FACES * YT_COLS];
-    __shared__ double red[(BLOCK / 64) * 8];
+    constexpr int QS = NR * YW_COLS;         // a wave's LDS stride between quantities
+    __shared__ double lds[NW * NQ * QS];
+    __shared__ double fh[NW * NC * YT_FACES * YW_COLS];
+    __shared__ double red[NW * 8];
     // epilogue operands of the tile (x-part of L, u^n), staged from the prefetch
     // registers so they are not held through the face arithmetic
     constexpr bool BASE = MODE == M_S2 || MODE == M_S3;
@@ -536,103 +592,99 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_SWE
     __shared__ double ebase[BASE ? NC * BLOCK : 1];
     const int perm[4] = {0, 2, 1, 3};
 
-    const int tid = threadIdx.x, cc = tid & (YT_COLS - 1), fl = tid / YT_COLS;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cc = lane % YW_COLS, fl = lane / YW_COLS;
+    double *W = lds + wv * NQ * QS;
+    double *WF = fh + wv * NC * YT_FACES * YW_COLS;
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->ytiles_total;
     const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
     Maxima<EULER2D> mx;
     mx.reset();
-    int cur = -1;
     YPre pre;
-    if (t0 < t1) {
-        const YTile y0 = y_tile(P, n_inst, t0);
-        y_prefetch<MODE, G>(P.inst[y0.k], y0, tid, pre);
-    }
 
-    for (long long tile = t0; tile < t1; ++tile) {
-        const YTile t = y_tile(P, n_inst, tile);
-        const Inst &I = P.inst[t.k];
-        if (MODE != M_RHS && t.k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
-        cur = t.k;
-
-        if (t.active) {
+    // one outer iteration per instance met by the workgroup's chunk (uniform
+    // over the workgroup: the maxima flush is reached by all waves together)
+    for (long long tile = t0; tile < t1;) {
+        const View<EULER2D, MODE> v = load_view<EULER2D, MODE, true>(P, n_inst, tile);
+        const long long tend = v.t1 < t1 ? v.t1 : t1;
+        if (!v.active) {
+            tile = tend;
+            continue;
+        }
+        const int nx = v.nx, ny = v.ny;
+        const long long plane = (long long)nx * ny;
+        YCur c = y_cursor(tile, v.t0, v.per_row);
+        y_prefetch<MODE, G>(v, c, wv, lane, pre);
+        for (; tile < tend; ++tile) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int i = tid + BLOCK * j;
-                if (i < NR * YT_COLS) {
+                const int i = lane + 64 * j;
+                if (i < NR * YW_COLS) {
                     double q[NQ];
                     node_quantities<EULER2D>(pre.U[j], P.gm1, q);
 #pragma unroll
-                    for (int m = 0; m < NQ; ++m) lds[m * QS + i] = q[m];
+                    for (int m = 0; m < NQ; ++m) W[m * QS + i] = q[m];
                 }
             }
-        }
-        if (t.active) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                elx[c * BLOCK + tid] = pre.lx[c];
-                if constexpr (BASE) ebase[c * BLOCK + tid] = pre.base[c];
+            for (int q = 0; q < NC; ++q) {
+                elx[q * BLOCK + tid] = pre.lx[q];
+                if constexpr (BASE) ebase[q * BLOCK + tid] = pre.base[q];
             }
-        }
-        if (tile + 1 < t1) {
-            const YTile tn = y_tile(P, n_inst, tile + 1);
-            y_prefetch<MODE, G>(P.inst[tn.k], tn, tid, pre);
-        }
-        if (!t.active) continue;
-        __syncthreads();
+            const YCur cn = y_advance(c, v.per_row);
+            if (tile + 1 < tend) y_prefetch<MODE, G>(v, cn, wv, lane, pre);
+            wave_sync();
 
-        const int nx = I.nx, ny = I.ny;
-        const long long plane = (long long)nx * ny;
-        double al[NC];
-        load_alpha<EULER2D>(I, P.r_in, true, al);
-        const int col = t.col0 + cc, f = t.sy + fl;
-        {
-            double Fh[NC];
-            int sel[2 * NC];
-            face_flux<EULER2D, ORDER>(lds + fl * YT_COLS + cc, QS, YT_COLS, al, P.gm1, P.delta, 0.0, Fh, sel);
+            const int sy = c.ty * YT_CELLS;
+            const int col = c.cg * YT_COLS + wv * YW_COLS + cc, f = sy + fl;
+            {
+                double Fh[NC];
+                int sel[2 * NC];
+                face_flux<EULER2D, ORDER>(W + fl * YW_COLS + cc, QS, YW_COLS, v.al, P.gm1, P.delta, 0.0, Fh, sel);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) fh[(c * YT_FACES + fl) * YT_COLS + cc] = Fh[c];
-            if (REC && I.sel && col < nx && f <= ny) {
-                const long long xblock = (long long)ny * (nx + 1), yblock = (long long)(ny + 1) * nx;
-                const long long ybase = (long long)NC * 2 * xblock;
+                for (int q = 0; q < NC; ++q) WF[(q * YT_FACES + fl) * YW_COLS + cc] = Fh[q];
+                if (REC && v.sel && col < nx && f <= ny) {
+                    const long long xblock = (long long)ny * (nx + 1), yblock = (long long)(ny + 1) * nx;
+                    const long long ybase = (long long)NC * 2 * xblock;
 #pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const long long o = ybase + (long long)(2 * s) * yblock + (long long)f * nx + col;
-                    I.sel[o] = (uint8_t)sel[2 * s];
-                    I.sel[o + yblock] = (uint8_t)sel[2 * s + 1];
+                    for (int s = 0; s < NC; ++s) {
+                        const long long o = ybase + (long long)(2 * s) * yblock + (long long)f * nx + col;
+                        v.sel[o] = (uint8_t)sel[2 * s];
+                        v.sel[o + yblock] = (uint8_t)sel[2 * s + 1];
+                    }
                 }
             }
-        }
-        __syncthreads();
+            wave_sync();
 
-        const int y = t.sy + fl;
-        if (fl < YT_CELLS && y < ny && col < nx) {
-            const double idy = -1.0 / I.dy;
-            const long long o = (long long)y * nx + col;
-            double Ly[NC];  // natural component order
+            const int y = sy + fl;
+            if (fl < YT_CELLS && y < ny && col < nx) {
+                const long long o = (long long)y * nx + col;
+                double Ly[NC];  // natural component order
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                Ly[perm[c]] = (fh[(c * YT_FACES + fl + 1) * YT_COLS + cc] - fh[(c * YT_FACES + fl) * YT_COLS + cc]) * idy;
-            if constexpr (MODE == M_RHS) {
+                for (int q = 0; q < NC; ++q)
+                    Ly[perm[q]] = -(WF[(q * YT_FACES + fl + 1) * YW_COLS + cc] - WF[(q * YT_FACES + fl) * YW_COLS + cc]) * v.idy;
+                if constexpr (MODE == M_RHS) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) I.lx[c * plane + o] = elx[c * BLOCK + tid] + Ly[c];
-            } else {
-                const double dt = I.ctrl->dt;
-                double *out = stage_out<MODE>(I);
-                double Un[NC];
+                    for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = elx[q * BLOCK + tid] + Ly[q];
+                } else {
+                    double Un[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const double uin = lds[perm[c] * QS + (fl + G) * YT_COLS + cc];
-                    const double base = BASE ? ebase[c * BLOCK + tid] : 0.0;
-                    Un[c] = rk_combine<MODE>(uin, base, dt, elx[c * BLOCK + tid] + Ly[c]);
-                    out[c * plane + o] = Un[c];
+                    for (int q = 0; q < NC; ++q) {
+                        const double uin = W[perm[q] * QS + (fl + G) * YW_COLS + cc];
+                        const double base = BASE ? ebase[q * BLOCK + tid] : 0.0;
+                        Un[q] = rk_combine<MODE>(uin, base, v.dt, elx[q * BLOCK + tid] + Ly[q]);
+                        v.out[q * plane + o] = Un[q];
+                    }
+                    mx.add(Un, P.gamma, v.idx, v.idy);
                 }
-                mx.add(Un, P.gamma, I.dx, I.dy);
             }
+            wave_sync();
+            c = cn;
         }
-        __syncthreads();
+        if (MODE != M_RHS) mx.flush(v.amax, v.ctrl, P.r_out, red);
     }
-    if (MODE != M_RHS && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -642,32 +694,45 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
 {
     constexpr int NC = NodeTraits<EQ>::NC;
     __shared__ double red[(BLOCK / 64) * 8];
-    const int tid = threadIdx.x, wseg = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wseg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->xtiles_total;
     const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
     Maxima<EQ> mx;
     mx.reset();
     int cur = -1;
+    long long end = -1;
+    int nx = 0, ny = 0, spr = 1;
+    long long first = 0;
+    const double *u = nullptr;
+    double idx = 0.0, idy = 0.0;
     for (long long tile = t0; tile < t1; ++tile) {
-        const int k = find_inst<true>(P.inst, n_inst, tile);
-        const Inst &I = P.inst[k];
-        if (k != cur && cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
-        cur = k;
-        const int nx = I.nx, ny = I.ny;
+        if (tile >= end) {
+            const int k = find_inst<true>(P.inst, n_inst, tile);
+            if (cur >= 0) mx.flush(P.inst[cur].amax, P.inst[cur].ctrl, P.r_out, red);
+            cur = k;
+            const Inst &I = P.inst[k];
+            first = I.xtile0;
+            end = first + I.xtiles;
+            nx = I.nx;
+            ny = I.ny;
+            spr = I.segs_per_row;
+            u = I.u;
+            idx = 1.0 / I.dx;
+            idy = 1.0 / I.dy;
+        }
         const long long plane = (long long)nx * ny;
-        const long long seg = (tile - I.xtile0) * XW_SEGS + wseg;
-        if (seg < (long long)ny * I.segs_per_row && lane < XW_CELLS) {
-            const int row = (int)(seg / I.segs_per_row), x = (int)(seg % I.segs_per_row) * XW_CELLS + lane;
-            if (x < nx) {
-                double U[NC];
+        const XCur c = x_cursor(tile, first, spr, wseg);
+        const int x = c.segx * XW_CELLS + lane;
+        if (c.row < ny && lane < XW_CELLS && x < nx) {
+            double U[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) U[c] = I.u[c * plane + (long long)row * nx + x];
-                mx.add(U, P.gamma, I.dx, I.dy);
-            }
+            for (int q = 0; q < NC; ++q) U[q] = u[q * plane + (long long)c.row * nx + x];
+            mx.add(U, P.gamma, idx, idy);
         }
     }
-    if (cur >= 0) mx.flush(P.inst[cur], P.r_out, red);
+    if (cur >= 0) mx.flush(P.inst[cur].amax, P.inst[cur].ctrl, P.r_out, red);
 }
 
 // zero all maxima slots and the status of every instance
