@@ -245,6 +245,15 @@ __device__ __forceinline__ double rk_combine(double in, double base, double dt, 
     else return fma(1.0 / 3.0, base, (2.0 / 3.0) * y);
 }
 
+// 2D stages: the x-sweep folds its part of L into the combine,
+//   z = rk_combine(in, base, dt, L_x),
+// and the y-sweep finishes it with its part, u_out = z + w dt L_y, w = 1, 1/4,
+// 2/3 for stages 1, 2, 3 (the same combine with L = L_x + L_y, up to rounding).
+template <int MODE> __device__ __forceinline__ double rk_weight()
+{
+    return MODE == M_S1 ? 1.0 : (MODE == M_S2 ? 0.25 : 2.0 / 3.0);
+}
+
 // wave-uniform copy of a value (scalar registers)
 template <typename T> __device__ __forceinline__ T uniform(T x)
 {
@@ -383,7 +392,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
             for (int q = 0; q < NC; ++q) pre.U[j][q] = rowp[q * plane + x];
         }
     }
-    if constexpr (EQ != EULER2D && (MODE == M_S2 || MODE == M_S3)) {
+    if constexpr (MODE == M_S2 || MODE == M_S3) {
         const int x = sx + lane;
         if (lane < XW_CELLS && x < nx) {
             const double *b = v.base + (long long)c.row * nx + x;
@@ -484,9 +493,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
 #pragma unroll
                 for (int q = 0; q < NC; ++q)
                     Lc[q] = -(fh[(q * XW_SEGS + wseg) * XW_FACES + lane + 1] - fh[(q * XW_SEGS + wseg) * XW_FACES + lane]) * v.idx;
-                if constexpr (!FULL) {
+                if constexpr (MODE == M_RHS) {
 #pragma unroll
                     for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = Lc[q];
+                } else if constexpr (!FULL) {  // 2D stage: x-part of the combine
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+                        v.lx[q * plane + o] = rk_combine<MODE>(L[q * XW_SEGS * NNP + lane + G], base[q], v.dt, Lc[q]);
                 } else {
                     double Un[NC];
 #pragma unroll
@@ -538,7 +551,7 @@ __device__ __forceinline__ YCur y_advance(YCur c, int per_row)
 
 struct YPre {
     double U[2][4];
-    double lx[4], base[4];
+    double lx[4];  // x-part of L (rhs) or of the stage combine
 };
 
 // a lane's global operands of one y tile: the strip nodes it stages (strip
@@ -568,10 +581,6 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
         const long long o = (long long)y * nx + col;
 #pragma unroll
         for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
-        if constexpr (MODE == M_S2 || MODE == M_S3) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pre.base[q] = v.base[q * plane + o];
-        }
     }
 }
 
@@ -585,11 +594,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
     __shared__ double lds[NW * NQ * QS];
     __shared__ double fh[NW * NC * YT_FACES * YW_COLS];
     __shared__ double red[NW * 8];
-    // epilogue operands of the tile (x-part of L, u^n), staged from the prefetch
-    // registers so they are not held through the face arithmetic
-    constexpr bool BASE = MODE == M_S2 || MODE == M_S3;
+    // epilogue operand of the tile (x-part), staged from the prefetch registers
+    // so it is not held through the face arithmetic
     __shared__ double elx[NC * BLOCK];
-    __shared__ double ebase[BASE ? NC * BLOCK : 1];
     const int perm[4] = {0, 2, 1, 3};
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -629,10 +636,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
                 }
             }
 #pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                elx[q * BLOCK + tid] = pre.lx[q];
-                if constexpr (BASE) ebase[q * BLOCK + tid] = pre.base[q];
-            }
+            for (int q = 0; q < NC; ++q) elx[q * BLOCK + tid] = pre.lx[q];
             const YCur cn = y_advance(c, v.per_row);
             if (tile + 1 < tend) y_prefetch<MODE, G>(v, cn, wv, lane, pre);
             wave_sync();
@@ -669,12 +673,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
 #pragma unroll
                     for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = elx[q * BLOCK + tid] + Ly[q];
                 } else {
+                    const double wdt = rk_weight<MODE>() * v.dt;
                     double Un[NC];
 #pragma unroll
                     for (int q = 0; q < NC; ++q) {
-                        const double uin = W[perm[q] * QS + (fl + G) * YW_COLS + cc];
-                        const double base = BASE ? ebase[q * BLOCK + tid] : 0.0;
-                        Un[q] = rk_combine<MODE>(uin, base, v.dt, elx[q * BLOCK + tid] + Ly[q]);
+                        Un[q] = fma(wdt, Ly[q], elx[q * BLOCK + tid]);
                         v.out[q * plane + o] = Un[q];
                     }
                     mx.add(Un, P.gamma, v.idx, v.idy);
