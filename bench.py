@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 METRIC = "cell-updates/s + % HBM/FP64 roofline; batched vs plain; p50/p99 latency"
 KERNEL_NAMES = {  # profile kind -> kernel symbol as rocprofv3 prints it (order 5, no selection record)
     "sweep_x_s1": "enoao::sweep_x<2, 5, 1, false>", "sweep_x_s2": "enoao::sweep_x<2, 5, 2, false>",
@@ -53,9 +55,9 @@ def measured_traffic(symbol, workload):
     return None if v is None else round(v)
 
 
-def cpu_baseline(n_sample=512, steps=2):
-    """The oracle (single-threaded C, FP64) on a bounded sample of the workload:
-    `steps` SSP-RK3 steps of the same seeded quadrant problem at n_sample^2 nodes."""
+def cpu_baseline(n_sample=2048, steps=1):
+    """The oracle (single-threaded C, FP64) on a bounded sample of the workload: the
+    first `steps` of its SSP-RK3 steps (same seeded quadrant problem, same size)."""
     from oracle import oracle as O
     from paper_2108_12742_amd import workloads as W
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n_sample)
@@ -128,7 +130,38 @@ def bench_batched(steps=100, warmup=2, count=512):
             "roofline": roof}
 
 
-def bench_served(requests=200, nsteps=50, rates=(0.5, 0.9), arena_gib=4.0):
+def bench_discontinuous(order=5):
+    """Discontinuous workloads of the paper at its meshes: the combination profile
+    (advection, N = 400, t = 20) and the Lax tube (1D Euler, N = 200, t = 0.26), each a
+    whole CFL-0.3 solve on the GPU; error against the exact solution."""
+    import numpy as np
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import workloads as W
+    from tests import riemann_exact as RX
+    out = {}
+    for name, inst, tf in (("combination_wave", W.combination_wave(400), 20.0), ("lax_tube", W.lax_tube(200), 0.26)):
+        plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order))
+        u = torch.from_numpy(inst.u0).cuda()
+        E.enoao_solve(plan, u, tf, cfl=0.3)  # warm-up (graph capture)
+        u.copy_(torch.from_numpy(inst.u0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, n = E.enoao_solve(plan, u, tf, cfl=0.3)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g = u.cpu().numpy()
+        if name == "lax_tube":
+            ex = RX.sample((0.445, 0.698, 3.528), (0.5, 0.0, 0.571), W.nodes(0.0, 2.0, inst.nx), 1.0, tf)[0]
+        else:
+            ex = inst.u0[0, 0]
+        out[name] = {"n": inst.nx, "order": order, "t_final": t, "steps": n, "seconds": el,
+                     "us_per_step": el * 1e6 / n, "cell_updates_per_s": inst.nx * n / el,
+                     "l1_error_vs_exact": float(np.abs(g[0, 0] - ex).mean())}
+    return out
+
+
+def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), arena_gib=4.0):
     """Served workload: Poisson arrivals of 2D Euler quadrant solves, N x N with
     N ~ U{128..1024}, `nsteps` steps each, admitted into a device pool by arena
     footprint; p50/p99 latency per arrival rate (fractions of the saturated rate)."""
@@ -181,7 +214,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (512 1D members, batched vs plain) and served (Poisson arrivals) legs")
-    ap.add_argument("--served-requests", type=int, default=120)
+    ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
@@ -262,14 +295,28 @@ def main():
         "kernels": kernels,
         "flops_per_cell_update": R.cell_update_flops("euler2d", args.order),
     }
-    del plan, u, u0
+    # stencil choices on the state the timed steps reached (the metric depends on them:
+    # waves whose faces all take the top candidate skip the rest of the selection)
+    rec = E.enoao_plan_create(E.problem_from_instance(inst, order=args.order, record_selection=True))
+    Lh = torch.empty_like(u)
+    E.enoao_rhs(rec, u, Lh)
+    sel = E.enoao_get_selection(rec)
+    nxs = 4 * 2 * n * (n + 1)
+    K = 6 if args.order == 5 else 9
+    out["selection_histogram"] = {
+        "candidates": "increasing priority; index K-1 is the full stencil",
+        "x": [round(float(v), 5) for v in np.bincount(sel[:nxs], minlength=K) / nxs],
+        "y": [round(float(v), 5) for v in np.bincount(sel[nxs:], minlength=K) / (sel.size - nxs)]}
+    del plan, u, u0, rec, Lh
     if not args.no_cpu_baseline:
         print("[bench] oracle baseline on the host ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     if not args.no_extras:
         print(f"[bench] main workload: {value:.4g} cell-updates/s; batched leg ...", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
-        print("[bench] batched leg done; served leg ...", file=sys.stderr, flush=True)
+        print("[bench] batched leg done; discontinuous workloads ...", file=sys.stderr, flush=True)
+        out["discontinuous"] = bench_discontinuous()
+        print("[bench] served leg ...", file=sys.stderr, flush=True)
         out["served"] = bench_served(requests=args.served_requests)
     print(json.dumps(out), flush=True)
 

@@ -134,6 +134,31 @@ def riemann_1d(seed: int, n: int = 2000, amp: float = 0.2, wavenumber: float = 5
                     meta={"seed": seed, "x0": x0, "left": (rL, uL, pL), "right": (rR, uR, pR), "phi": phi})
 
 
+def combination_wave(n: int = 400) -> Instance:
+    """Advected combination of Gaussians, a square wave, a triangle and a half ellipse
+    (the Jiang-Shu profile of Section 4.1) on [-1, 1], periodic, unit speed; the exact
+    solution returns to u0 after every period of 2."""
+    a, z, d, al = 0.5, -0.7, 0.005, 10.0
+    beta = math.log(2.0) / (36.0 * d * d)
+    x = nodes(-1.0, 1.0, n)
+
+    def G(zz):
+        return np.exp(-beta * (x - zz) ** 2)
+
+    def F(aa):
+        return np.sqrt(np.maximum(1.0 - al * al * (x - aa) ** 2, 0.0))
+
+    u = np.zeros(n)
+    m = (x >= -0.8) & (x <= -0.6)
+    u[m] = ((G(z - d) + 4.0 * G(z) + G(z + d)) / 6.0)[m]
+    u[(x >= -0.4) & (x <= -0.2)] = 1.0
+    m = (x >= 0.0) & (x <= 0.2)
+    u[m] = (1.0 - 10.0 * np.abs(x - 0.1))[m]
+    m = (x >= 0.4) & (x <= 0.6)
+    u[m] = ((F(a - d) + 4.0 * F(a) + F(a + d)) / 6.0)[m]
+    return Instance("advection", u.reshape(1, 1, n).copy(), -1.0, 1.0, meta={"kind": "combination"})
+
+
 def lax_tube(n: int = 200) -> Instance:
     """Lax shock tube of Section 4.2 on [0, 2]: (0.445, 0.698, 3.528) | (0.5, 0, 0.571)."""
     x = nodes(0.0, 2.0, n)

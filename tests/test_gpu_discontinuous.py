@@ -1,0 +1,108 @@
+"""GPU parity on the discontinuous workloads of Sections 4.1 and 4.2: the advected
+Jiang-Shu combination profile (Gaussians, square wave, triangle, half ellipse) and the
+Lax shock tube.  Near discontinuities the lower-order candidates are selected and the
+wave-uniform early exit is rarely taken, so these runs exercise the full selection path.
+
+Per step: from the oracle's state, the GPU's L (with selections) and one GPU step match
+the oracle.  Whole runs: step counts and end times match, and the GPU's error against the
+exact solution agrees with the oracle's (the two trajectories may part at rounding-level
+near-ties, so the end states are compared through their errors, not cell by cell)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_12742_amd import workloads as W
+from tests import parity as PT
+from tests import riemann_exact as RX
+
+pytestmark = pytest.mark.gpu
+
+LAX = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+
+
+def _E():
+    from paper_2108_12742_amd import enoao as E
+    return E
+
+
+def _trajectory_parity(torch, E, inst, order, nsteps, cfl=0.3):
+    ep = E.problem_from_instance(inst, order=order, record_selection=True)
+    op = PT.oracle_problem(ep)
+    plan_rec = E.enoao_plan_create(ep)
+    plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order))
+    ur = inst.u0.copy()
+    low = 0
+    for k in range(nsteps):
+        u = PT.to_dev(torch, ur)
+        L = torch.empty_like(u)
+        E.enoao_rhs(plan_rec, u, L)
+        sel = E.enoao_get_selection(plan_rec)
+        Lr, selr, tier = O.rhs(op, ur, with_selection=True)
+        mask = PT.compare_selection(op, sel, selr, tier)
+        PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what=f"L step {k}")
+        low += int((selr < O.num_candidates(order) - 1).sum())
+        dt = O.cfl_dt(op, ur, cfl)
+        E.enoao_step(plan, u, dt)
+        ur = O.step(op, ur, dt)
+        PT.assert_close_by_component(u.cpu().numpy(), ur, mask=mask, what=f"u step {k}")
+    return low
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_combination_wave_steps(order):
+    torch = PT.torch_cuda()
+    E = _E()
+    print(f"combination wave, order {order}, N = 400", flush=True)
+    low = _trajectory_parity(torch, E, W.combination_wave(400), order, 25)
+    assert low > 0  # lower-order candidates were taken and compared
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_combination_wave_ten_periods(order):
+    """N = 400 (dx = 1/200), t = 20 as in Section 4.1: 13334 CFL steps on the GPU and in
+    the oracle."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.combination_wave(400)
+    ep = E.problem_from_instance(inst, order=order)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, 20.0, cfl=0.3)
+    ur, tr, nr = O.solve(PT.oracle_problem(ep), inst.u0, 20.0, cfl=0.3)
+    assert n == nr and t == tr == 20.0
+    g = u.cpu().numpy()[0, 0]
+    e_g = np.abs(g - inst.u0[0, 0]).mean()
+    e_r = np.abs(ur[0, 0] - inst.u0[0, 0]).mean()
+    assert abs(e_g / e_r - 1) < 1e-3, (e_g, e_r)
+    assert np.abs(g - ur[0, 0]).max() < 1e-5
+    assert g.max() <= 1.0 + 1e-3 and g.min() >= -1e-3
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_lax_tube_steps(order):
+    torch = PT.torch_cuda()
+    E = _E()
+    print(f"Lax tube, order {order}, N = 200", flush=True)
+    low = _trajectory_parity(torch, E, W.lax_tube(200), order, 40)
+    assert low > 0
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_lax_tube_to_t026(order):
+    """dx = 1/100, t = 0.26 as in Section 4.2; the GPU's density error against the exact
+    Riemann solution equals the oracle's."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.lax_tube(200)
+    ep = E.problem_from_instance(inst, order=order)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, 0.26, cfl=0.3)
+    ur, tr, nr = O.solve(PT.oracle_problem(ep), inst.u0, 0.26, cfl=0.3)
+    assert n == nr and t == tr == 0.26
+    ex = RX.sample(*LAX, W.nodes(0.0, 2.0, 200), 1.0, 0.26)
+    g = u.cpu().numpy()
+    e_g = np.abs(g[0, 0] - ex[0]).mean()
+    e_r = np.abs(ur[0, 0] - ex[0]).mean()
+    assert abs(e_g / e_r - 1) < 1e-6, (e_g, e_r)
+    PT.assert_close_by_component(g, ur, rtol=1e-9, what="u(t=0.26)")

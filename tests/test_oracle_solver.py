@@ -397,3 +397,46 @@ def test_batch_1d_draws_are_moderate_and_physical():
     p = O.Problem(O.EULER1D, nx=n, x_lo=0.0, x_hi=1.0, bc_x=O.TRANSMISSIVE)
     with pytest.raises(O.OracleError):
         O.solve(p, u0.reshape(3, 1, n), 1e300, cfl=0.3, max_steps=100)
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_combination_wave_one_period(order):
+    """Discontinuous advection (the Jiang-Shu combination profile of Section 4.1): after one
+    period the scheme stays essentially non-oscillatory (over- and undershoots below 1e-4
+    of the unit jump), conserves the total, and the L1 error falls by about half per mesh
+    halving (first-order convergence of a discontinuous solution)."""
+    prev = None
+    for n in (200, 400, 800):
+        inst = W.combination_wave(n)
+        p = O.Problem(O.ADVECTION, nx=n, order=order, adv_speed=1.0)
+        u, t, _ = O.solve(p, inst.u0, 2.0, cfl=0.3)
+        assert abs(t - 2.0) < 1e-13
+        e = np.abs(u[0, 0] - inst.u0[0, 0])
+        l1 = np.append(e, e[0]).mean()
+        assert u.max() <= 1.0 + 1e-4 and u.min() >= -1e-4, (n, u.max(), u.min())
+        assert abs(u.sum() - inst.u0.sum()) <= 1e-13 * np.abs(inst.u0).sum() * 10
+        if prev is not None:
+            assert prev / l1 > 1.8, (n, prev, l1)
+        prev = l1
+    assert prev < 6e-3
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_lax_tube_against_exact_riemann(order):
+    """The Lax shock tube of Section 4.2 ([0, 2], t = 0.26, transmissive ends) against the
+    exact Riemann solution: the density L1 error halves per mesh halving, and at the
+    paper's mesh (dx = 1/100) it is about one percent of the density range."""
+    prev = None
+    left, right = (0.445, 0.698, 3.528), (0.5, 0.0, 0.571)
+    for n in (100, 200, 400):
+        inst = W.lax_tube(n)
+        p = O.Problem(O.EULER1D, nx=n, order=order, x_lo=0.0, x_hi=2.0, bc_x=O.TRANSMISSIVE)
+        u, t, _ = O.solve(p, inst.u0, 0.26, cfl=0.3)
+        assert t == 0.26 and np.isfinite(u).all()
+        ex = RX.sample(left, right, W.nodes(0.0, 2.0, n), 1.0, 0.26)
+        l1 = np.abs(u[0, 0] - ex[0]).mean()
+        if n == 200:
+            assert l1 < 0.012, l1
+        if prev is not None:
+            assert prev / l1 > 1.7, (n, prev, l1)
+        prev = l1
