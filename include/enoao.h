@@ -207,9 +207,10 @@ enoao_status enoao_pool_usage(const enoao_pool *pool, size_t *arena_used, size_t
  * eagerly (no graph replay) and record a hipEvent pair around every kernel on
  * the stream the kernel runs on.  enoao_profile_read synchronises stream and
  * returns, per kernel kind, the mean duration in ms and the number of
- * launches since profiling was enabled.  Kinds (n_kinds <= 8):
+ * launches since profiling was enabled.  Kinds (n_kinds <= 9):
  *   0..2 x-sweep of stage 1..3, 3..5 y-sweep of stage 1..3 (2D only),
- *   6 time-step control, 7 initial per-field maxima. */
+ *   6 time-step control, 7 initial per-field maxima, 8 LDS-resident solver
+ *   (one launch per call: all of its controlled steps). */
 enoao_status enoao_profile(enoao_plan *plan, int32_t enable);
 enoao_status enoao_profile_read(enoao_plan *plan, double *avg_ms, int64_t *count, int32_t n_kinds, void *stream);
 enoao_status enoao_batch_profile(enoao_batch *batch, int32_t enable);
@@ -226,6 +227,19 @@ enoao_status enoao_batch_profile_read(enoao_batch *batch, double *avg_ms, int64_
 enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved);
 enoao_status enoao_plan_set_launch(enoao_plan *plan, int32_t workgroups_per_cu);
 enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_cu);
+
+/* LDS-resident solver for small 1D problems (advection and Euler 1D, any
+ * order, no selection record).  When every member of a plan or batch fits one
+ * workgroup's LDS (state, stage state and face fluxes of the whole line; about
+ * 1990 nodes for Euler 1D and 6600 for advection on gfx950), enoao_solve and
+ * enoao_batch_step run their time-step-controlled steps in one launch with one
+ * workgroup per member: the state is read from HBM once, every step and stage
+ * runs out of LDS, and the state is written back at the end of the call.  The
+ * arithmetic is the streaming kernels' (Sections 2 to 4 as above), so results
+ * are bitwise the same either way.  enable = 1 (default) allows it for plans
+ * and batches used afterwards, 0 forces the streaming kernels; other values
+ * return ENOAO_EINVAL.  enoao_step (host-given step) and pools always stream. */
+enoao_status enoao_set_resident(int32_t enable);
 
 const char *enoao_status_string(enoao_status status);
 

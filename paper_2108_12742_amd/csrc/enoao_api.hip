@@ -19,9 +19,10 @@ using namespace enoao;
 namespace {
 
 int g_wg_per_cu = 0;  // 0: occupancy of each kernel
+int g_resident = 1;   // small 1D members: LDS-resident solver for controlled steps
 
 // kernel kinds of the per-kernel timing (enoao_profile_read order)
-enum { PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_KINDS };
+enum { PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_RESIDENT, PROF_KINDS };
 
 int ncomp_of(int eq) { return eq == ADVECTION ? 1 : eq == EULER1D ? 3 : eq == EULER2D ? 4 : 0; }
 
@@ -93,6 +94,11 @@ struct Runtime {
     hipStream_t cap = nullptr;
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
     int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
+    // every member 1D and small enough for the LDS-resident solver (res_lds
+    // dynamic LDS bytes per workgroup); controlled steps then run there
+    bool resident = false;
+    size_t res_lds = 0;
+    bool use_resident() const { return resident && g_resident != 0; }
     // optional per-kernel timing: hipEvents recorded around every launch, on the
     // stream the kernel is launched on (eager launches, no graph)
     bool profiling = false;
@@ -228,6 +234,14 @@ struct Runtime {
 
         wg_per_cu = g_wg_per_cu;
         set_grids();
+        if (eq != EULER2D && !rec) {
+            const int nq = eq == ADVECTION ? 1 : 9, g = order == 5 ? 4 : 5;
+            size_t need = 0;
+            for (int i = 0; i < count; ++i)
+                need = std::max<size_t>(need, resident_lds_bytes(nc, nq, g, ps[i].nx));
+            res_lds = need;
+            resident = need <= resident_lds_limit();
+        }
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         return ENOAO_OK;
     }
@@ -345,6 +359,13 @@ struct Runtime {
 
     enoao_status steps(int k, bool control, hipStream_t s)
     {
+        if (control && use_resident()) {
+            int slot;
+            HIP_TRY(prof_begin(PROF_RESIDENT, s, slot));
+            HIP_TRY(launch_resident(eq, order, params(0, -1, -1), n_cap, k, res_lds, s));
+            HIP_TRY(prof_end(slot, s));
+            return ENOAO_OK;
+        }
         for (int i = 0; i < k; ++i) {
             if (control) {
                 int slot;
@@ -396,7 +417,7 @@ struct Runtime {
     // k controlled steps: one graph replay, or eager launches when profiling
     enoao_status run_steps(int k, hipStream_t s)
     {
-        if (profiling) return steps(k, true, s);
+        if (profiling || use_resident()) return steps(k, true, s);  // (resident: one launch already)
         if (enoao_status e = ensure_graph(k)) return e;
         HIP_TRY(hipGraphLaunch(graph, s));
         return ENOAO_OK;
@@ -537,6 +558,13 @@ enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved)
 {
     if (workgroups_per_cu < 0 || workgroups_per_cu > 64 || reserved != 0) return ENOAO_EINVAL;
     g_wg_per_cu = workgroups_per_cu;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_set_resident(int32_t enable)
+{
+    if (enable != 0 && enable != 1) return ENOAO_EINVAL;
+    g_resident = enable;
     return ENOAO_OK;
 }
 

@@ -66,6 +66,20 @@ struct Inst {
     long long xtiles, ytiles;   // number of x / y tiles
 };
 
+// LDS-resident solver of small 1D members: one workgroup of RES_BLOCK threads
+// holds a member's state, its stage state and its face fluxes in LDS for a
+// whole call; a stage stages node quantities for RES_BLOCK faces at a time.
+constexpr int RES_BLOCK = 512;
+constexpr int RES_WAVES = RES_BLOCK / 64;
+
+// dynamic LDS bytes of a resident member of n nodes (nc components, nq staged
+// quantities per node, halo width g): u^n, stage state, face fluxes, one chunk
+// of staged nodes, the reduction scratch
+constexpr unsigned long long resident_lds_bytes(int nc, int nq, int g, long long n)
+{
+    return 8ull * (unsigned long long)(2 * nc * n + nc * (n + 1) + nq * (RES_BLOCK + 2 * g) + RES_WAVES * 8 + 8);
+}
+
 // Batch header (device memory): kernels read the instance count and the tile
 // totals from here, so a captured graph stays valid when the active set changes.
 struct BatchHdr {

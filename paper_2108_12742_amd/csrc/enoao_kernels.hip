@@ -749,33 +749,29 @@ __global__ void reset_maxima(KParams P)
     }
 }
 
-// Time-step control, one thread per instance: CFL (or fixed) step from the
-// maxima of the state at the start of the step, clipped to land on t_final.
+// Time-step control of one instance: CFL (or fixed) step from the maxima m of
+// the state at the start of the step (m[0], m[2]: max |u-c|, |u+c|; m[6]: the
+// 2D sum), clipped to land on t_final.  Returns whether a step is taken.
 template <int EQ>
-__global__ void step_control(KParams P)
+__device__ __forceinline__ bool control_update(Ctrl &C, double m0, double m2, double m6, double dx, double adv)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P.hdr->n_inst) return;
-    const Inst &I = P.inst[k];
-    Ctrl &C = *I.ctrl;
-    if (C.done) return;
-    if (C.status != 0 || C.steps >= C.max_steps) { C.done = 1; return; }
+    if (C.done) return false;
+    if (C.status != 0 || C.steps >= C.max_steps) { C.done = 1; return false; }
     const double rem = C.t_final - C.t;
-    if (!(rem > 0.0)) { C.done = 1; return; }
+    if (!(rem > 0.0)) { C.done = 1; return false; }
     double dt;
     if (C.dt_fixed > 0.0) {
         dt = C.dt_fixed;
     } else {
-        const unsigned long long *a = I.amax;  // slot 0: the state u^n
         if constexpr (EQ == ADVECTION) {
-            dt = C.cfl * I.dx / fabs(I.adv);
+            dt = C.cfl * dx / fabs(adv);
         } else if constexpr (EQ == EULER1D) {
-            const double smax = fmax(as_double(a[0]), as_double(a[2]));  // max(|u|+c)
-            if (!(smax > 0.0)) { C.status |= 1; C.done = 1; return; }
-            dt = C.cfl * I.dx / smax;
+            const double smax = fmax(m0, m2);  // max(|u|+c)
+            if (!(smax > 0.0)) { C.status |= 1; C.done = 1; return false; }
+            dt = C.cfl * dx / smax;
         } else {
-            const double smax = as_double(a[6]);
-            if (!(smax > 0.0)) { C.status |= 1; C.done = 1; return; }
+            const double smax = m6;
+            if (!(smax > 0.0)) { C.status |= 1; C.done = 1; return false; }
             dt = C.cfl / smax;
         }
     }
@@ -784,6 +780,158 @@ __global__ void step_control(KParams P)
     C.dt = dt;
     C.t = last ? C.t_final : C.t + dt;
     C.steps = C.steps + 1;
+    return true;
+}
+
+// one thread per instance; slot 0 of the maxima holds the state u^n
+template <int EQ>
+__global__ void step_control(KParams P)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.hdr->n_inst) return;
+    const Inst &I = P.inst[k];
+    const unsigned long long *a = I.amax;
+    control_update<EQ>(*I.ctrl, as_double(a[0]), as_double(a[2]), as_double(a[6]), I.dx, I.adv);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident solver of small 1D members.  One workgroup per member runs
+// `nsteps` controlled steps with the state, the stage state and the face
+// fluxes in LDS: HBM is touched only to load the state and store it back.
+// Every arithmetic step is the streaming path's (same node quantities, face
+// flux, flux difference, stage combine, maxima and step control), so a member's
+// result is bitwise the one of the streaming kernels.
+
+// workgroup maximum of the per-thread maxima; the non-physical flag goes to C
+template <int EQ>
+__device__ __forceinline__ void resident_reduce(Maxima<EQ> &mx, double *red, double *cm, Ctrl &C)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        double x = mx.v[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+        mx.v[i] = x;
+    }
+    int b = mx.bad;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b |= __shfl_xor(b, o, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) red[wv * 8 + i] = mx.v[i];
+        red[wv * 8 + 7] = (double)b;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double x = red[threadIdx.x];
+        for (int w = 1; w < RES_WAVES; ++w) x = fmax(x, red[w * 8 + threadIdx.x]);
+        if (threadIdx.x < 7) cm[threadIdx.x] = x;
+        else if (x != 0.0) C.status |= 1;
+    }
+    __syncthreads();
+}
+
+template <int EQ, int ORDER, int MODE>
+__device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, int n, double *un, double *w,
+                                               double *fx, double *q, double *red, double *cm, Ctrl &C, double dt)
+{
+    constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
+    constexpr int G = ReconTraits<ORDER>::H + 1;
+    constexpr int QS = RES_BLOCK + 2 * G;
+    const int tid = threadIdx.x;
+    double al[NC];
+    if constexpr (EQ == ADVECTION) {
+        al[0] = fabs(I.adv);
+    } else {
+        al[0] = cm[0];
+        al[1] = cm[1];
+        al[NC - 1] = cm[2];
+    }
+    const double *in = MODE == M_S1 ? un : w;
+    for (int c0 = 0; c0 <= n; c0 += RES_BLOCK) {
+        for (int i = tid; i < RES_BLOCK + 2 * G - 1; i += RES_BLOCK) {
+            const int x = bc_map(c0 - G + i, n, I.bcx);
+            double U[NC], qq[NQ];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) U[c] = in[c * n + x];
+            node_quantities<EQ>(U, P.gm1, qq);
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) q[m * QS + i] = qq[m];
+        }
+        __syncthreads();
+        const int f = c0 + tid;
+        if (f <= n) {
+            double Fh[NC];
+            int sel[2 * NC];
+            face_flux<EQ, ORDER>(q + tid, QS, 1, al, P.gm1, P.delta, I.adv, Fh, sel);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fx[c * (n + 1) + f] = Fh[c];
+        }
+        __syncthreads();
+    }
+    const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
+    double *out = MODE == M_S3 ? un : w;
+    Maxima<EQ> mx;
+    mx.reset();
+    for (int j = tid; j < n; j += RES_BLOCK) {
+        double Un[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double Lc = -(fx[c * (n + 1) + j + 1] - fx[c * (n + 1) + j]) * idx;
+            Un[c] = rk_combine<MODE>(in[c * n + j], un[c * n + j], dt, Lc);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c * n + j] = Un[c];
+        mx.add(Un, P.gamma, idx, idy);
+    }
+    resident_reduce<EQ>(mx, red, cm, C);
+}
+
+template <int EQ, int ORDER>
+__global__ __launch_bounds__(RES_BLOCK) void resident_1d(KParams P, int nsteps)
+{
+    constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
+    constexpr int G = ReconTraits<ORDER>::H + 1;
+    constexpr int QS = RES_BLOCK + 2 * G;
+    extern __shared__ double sm[];
+    __shared__ Ctrl C;
+    __shared__ int go;
+    const Inst &I = P.inst[blockIdx.x];
+    const int n = I.nx, tid = threadIdx.x;
+    double *un = sm;
+    double *w = un + NC * n;
+    double *fx = w + NC * n;
+    double *q = fx + NC * (n + 1);
+    double *red = q + NQ * QS;
+    double *cm = red + RES_WAVES * 8;
+    double *ug = I.u;
+    for (int i = tid; i < NC * n; i += RES_BLOCK) un[i] = ug[i];
+    if (tid == 0) C = *I.ctrl;
+    __syncthreads();
+    {
+        const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
+        Maxima<EQ> mx;
+        mx.reset();
+        for (int j = tid; j < n; j += RES_BLOCK) {
+            double U[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) U[c] = un[c * n + j];
+            mx.add(U, P.gamma, idx, idy);
+        }
+        resident_reduce<EQ>(mx, red, cm, C);
+    }
+    for (int step = 0; step < nsteps; ++step) {
+        if (tid == 0) go = control_update<EQ>(C, cm[0], cm[2], cm[6], I.dx, I.adv) ? 1 : 0;
+        __syncthreads();
+        if (!go) break;  // uniform: read after the barrier by every thread
+        const double dt = C.dt;
+        resident_stage<EQ, ORDER, M_S1>(P, I, n, un, w, fx, q, red, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S2>(P, I, n, un, w, fx, q, red, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S3>(P, I, n, un, w, fx, q, red, cm, C, dt);
+    }
+    for (int i = tid; i < NC * n; i += RES_BLOCK) ug[i] = un[i];
+    if (tid == 0) *I.ctrl = C;
 }
 
 // bind caller pointers into a member's descriptor (kernel arguments are
@@ -816,6 +964,7 @@ __global__ void set_dt(KParams P, double dt)
 // ---------------------------------------------------------------------------
 // kernel selection and launchers
 using KFn = void (*)(KParams);
+using KFn2 = void (*)(KParams, int);
 
 template <int EQ, int ORDER, bool REC> static KFn pick_x_mode(int mode)
 {
@@ -920,6 +1069,32 @@ hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, boo
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s)
 {
     return launch(clear_done, (n_inst + 63) / 64, 64, p, s);
+}
+
+static KFn2 pick_resident(int eq, int order)
+{
+    if (eq == ADVECTION) return order == 7 ? resident_1d<ADVECTION, 7> : resident_1d<ADVECTION, 5>;
+    return order == 7 ? resident_1d<EULER1D, 7> : resident_1d<EULER1D, 5>;
+}
+
+hipError_t launch_resident(int eq, int order, const KParams &p, int n_inst, int nsteps, size_t lds, hipStream_t s)
+{
+    if (eq == EULER2D) return hipErrorInvalidValue;
+    const KFn2 fn = pick_resident(eq, order);
+    // dynamic LDS beyond the default limit must be allowed per kernel
+    hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    KParams copy = p;
+    void *args[] = {&copy, &nsteps};
+    return hipLaunchKernel((const void *)fn, dim3(n_inst), dim3(RES_BLOCK), args, lds, s);
+}
+
+size_t resident_lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    // the kernel's static LDS (control copy, flag) comes on top of the dynamic part
+    return v > 256 ? (size_t)v - 256 : 0;
 }
 
 int occupancy_x(int eq, int order, int mode, bool rec) { return occupancy(pick_x(eq, order, mode, rec)); }

@@ -33,6 +33,11 @@ hipError_t launch_step_control(int eq, const KParams &p, int n_inst, hipStream_t
 hipError_t launch_set_dt(const KParams &p, int n_inst, double dt, hipStream_t s);
 hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, bool set_lx, hipStream_t s);
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
+// nsteps controlled steps of every member (all 1D, all fitting the LDS), one
+// workgroup per member; lds = dynamic LDS bytes per workgroup
+hipError_t launch_resident(int eq, int order, const KParams &p, int n_inst, int nsteps, size_t lds, hipStream_t s);
+// largest dynamic LDS a resident workgroup may use on this device (0: none)
+size_t resident_lds_limit();
 
 // resident workgroups per CU of each kernel (for persistent grid sizes)
 int occupancy_x(int eq, int order, int mode, bool rec);

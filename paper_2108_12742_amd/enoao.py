@@ -101,6 +101,7 @@ def lib():
             "enoao_batch_query": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int32), vp], st),
             "enoao_set_launch": ([ctypes.c_int32, ctypes.c_int32], st),
+            "enoao_set_resident": ([ctypes.c_int32], st),
             "enoao_plan_set_launch": ([vp, ctypes.c_int32], st),
             "enoao_batch_set_launch": ([vp, ctypes.c_int32], st),
             "enoao_profile": ([vp, ctypes.c_int32], st),
@@ -275,7 +276,7 @@ def enoao_batch_query(batch: Batch, stream=None, raise_on_failure=False):
 
 
 PROFILE_KINDS = ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3", "sweep_y_s1", "sweep_y_s2", "sweep_y_s3",
-                 "step_control", "state_maxima")
+                 "step_control", "state_maxima", "resident")
 
 
 def enoao_profile(plan: Plan, enable: bool):
@@ -301,6 +302,10 @@ def enoao_batch_profile_read(batch: Batch, stream=None):
     cnt = (ctypes.c_int64 * n)()
     _check(lib().enoao_batch_profile_read(batch.handle, ms, cnt, n, _stream(stream)), "enoao_batch_profile_read")
     return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
+
+
+def enoao_set_resident(enable: bool):
+    _check(lib().enoao_set_resident(1 if enable else 0), "enoao_set_resident")
 
 
 def enoao_set_launch(workgroups_per_cu: int):
