@@ -130,6 +130,44 @@ def bench_batched(steps=100, warmup=2, count=512):
             "roofline": roof}
 
 
+def bench_resident(steps=100, count=512, n_hi=1700):
+    """Small 1D members: `count` Euler Riemann instances with N ~ LogUniform[128, n_hi]
+    (each fits one workgroup's LDS), `steps` CFL steps, as one batch: the LDS-resident
+    solver (one launch for all steps) against the streaming persistent sweeps."""
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import workloads as W
+    insts = W.batch_1d(1, count, n_hi=n_hi)
+    probs = [E.problem_from_instance(i) for i in insts]
+    cells = sum(int(p.nx) for p in probs)
+    res = {"workload": f"euler1d-riemann-batch{count}-N128..{n_hi}-{cells}cells-ao5", "members": count,
+           "cells": cells, "steps": steps}
+    finals = []
+    for mode in ("resident", "streaming"):
+        E.enoao_set_resident(mode == "resident")
+        try:
+            b = E.enoao_batch_create(probs)
+            us = [torch.from_numpy(i.u0).cuda() for i in insts]
+            E.enoao_batch_step(b, us, 2, 0.3)  # warm-up
+            E.enoao_batch_destroy(b)
+            b = E.enoao_batch_create(probs)
+            us = [torch.from_numpy(i.u0).cuda() for i in insts]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            E.enoao_batch_step(b, us, steps, 0.3)
+            _, nst, status = E.enoao_batch_query(b)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        finally:
+            E.enoao_set_resident(True)
+        finals.append(us)
+        res[mode] = {"value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+                     "members_ok": int((status == 0).sum())}
+    res["identical"] = all(torch.equal(a, b) for a, b in zip(*finals))
+    res["speedup_resident"] = res["resident"]["value"] / res["streaming"]["value"]
+    return res
+
+
 def bench_discontinuous(order=5):
     """Discontinuous workloads of the paper at its meshes: the combination profile
     (advection, N = 400, t = 20) and the Lax tube (1D Euler, N = 200, t = 0.26), each a
@@ -141,23 +179,30 @@ def bench_discontinuous(order=5):
     from tests import riemann_exact as RX
     out = {}
     for name, inst, tf in (("combination_wave", W.combination_wave(400), 20.0), ("lax_tube", W.lax_tube(200), 0.26)):
-        plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order))
-        u = torch.from_numpy(inst.u0).cuda()
-        E.enoao_solve(plan, u, tf, cfl=0.3)  # warm-up (graph capture)
-        u.copy_(torch.from_numpy(inst.u0))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t, n = E.enoao_solve(plan, u, tf, cfl=0.3)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        g = u.cpu().numpy()
-        if name == "lax_tube":
-            ex = RX.sample((0.445, 0.698, 3.528), (0.5, 0.0, 0.571), W.nodes(0.0, 2.0, inst.nx), 1.0, tf)[0]
-        else:
-            ex = inst.u0[0, 0]
-        out[name] = {"n": inst.nx, "order": order, "t_final": t, "steps": n, "seconds": el,
-                     "us_per_step": el * 1e6 / n, "cell_updates_per_s": inst.nx * n / el,
-                     "l1_error_vs_exact": float(np.abs(g[0, 0] - ex).mean())}
+        entry = {"n": inst.nx, "order": order}
+        for mode in ("resident", "streaming"):
+            E.enoao_set_resident(mode == "resident")
+            try:
+                plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order))
+                u = torch.from_numpy(inst.u0).cuda()
+                E.enoao_solve(plan, u, tf, cfl=0.3)  # warm-up (graph capture)
+                u.copy_(torch.from_numpy(inst.u0))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t, n = E.enoao_solve(plan, u, tf, cfl=0.3)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+            finally:
+                E.enoao_set_resident(True)
+            g = u.cpu().numpy()
+            if name == "lax_tube":
+                ex = RX.sample((0.445, 0.698, 3.528), (0.5, 0.0, 0.571), W.nodes(0.0, 2.0, inst.nx), 1.0, tf)[0]
+            else:
+                ex = inst.u0[0, 0]
+            entry.update({"t_final": t, "steps": n})
+            entry[mode] = {"seconds": el, "us_per_step": el * 1e6 / n, "cell_updates_per_s": inst.nx * n / el,
+                           "l1_error_vs_exact": float(np.abs(g[0, 0] - ex).mean())}
+        out[name] = entry
     return out
 
 
@@ -314,7 +359,9 @@ def main():
     if not args.no_extras:
         print(f"[bench] main workload: {value:.4g} cell-updates/s; batched leg ...", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
-        print("[bench] batched leg done; discontinuous workloads ...", file=sys.stderr, flush=True)
+        print("[bench] batched leg done; LDS-resident small members ...", file=sys.stderr, flush=True)
+        out["batched_small"] = bench_resident()
+        print("[bench] discontinuous workloads ...", file=sys.stderr, flush=True)
         out["discontinuous"] = bench_discontinuous()
         print("[bench] served leg ...", file=sys.stderr, flush=True)
         out["served"] = bench_served(requests=args.served_requests)

@@ -660,6 +660,9 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
     } else {
         k = 64;
     }
+    // the resident solver runs a call's steps in one launch (it stops by itself at
+    // t_final): fewer, longer launches
+    if (rt.use_resident()) k = 1024;
     if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps);
     k = std::max(k, 1);
     enoao_status st = ENOAO_OK;
