@@ -52,12 +52,22 @@ size_t selection_count(const enoao_problem *p)
     return n;
 }
 
+// A member's state-sized buffers are laid out one after another with a gap of
+// BUF_STAGGER doubles (4352 bytes) between them: buffers that a kernel streams
+// together (stage input, x-part, stage output) then do not start at offsets
+// that are multiples of a large power of two, which made their lines contend
+// for the same cache sets and memory channels.
+constexpr size_t BUF_STAGGER = 544;
+
+// i-th state-sized buffer of a member block
+inline double *member_buffer(double *m, size_t cells, int i) { return m + (size_t)i * (cells + BUF_STAGGER); }
+
 // device bytes of one member: w1, w2 (+ Lx for 2D) and the selection record
 size_t member_bytes(const enoao_problem *p)
 {
     const size_t n = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
-    size_t b = 2 * n * sizeof(double);
-    if (p->equation == EULER2D) b += n * sizeof(double);
+    const int bufs = p->equation == EULER2D ? 3 : 2;
+    size_t b = bufs * (n + BUF_STAGGER) * sizeof(double);
     if (p->flags & ENOAO_F_RECORD_SELECTION) b += (selection_count(p) + 255) / 256 * 256;
     return b;
 }
@@ -213,8 +223,9 @@ struct Runtime {
         for (int i = 0; i < count; ++i) {
             double *m = (double *)(base + o_mem[i]);
             const size_t cells = (size_t)nc * ps[i].nx * ps[i].ny;
-            fill_inst(h_inst[i], ps[i], nullptr, m, m + cells, eq == EULER2D ? m + 2 * cells : nullptr,
-                      rec ? (uint8_t *)(m + (eq == EULER2D ? 3 : 2) * cells) : nullptr,
+            fill_inst(h_inst[i], ps[i], nullptr, member_buffer(m, cells, 0), member_buffer(m, cells, 1),
+                      eq == EULER2D ? member_buffer(m, cells, 2) : nullptr,
+                      rec ? (uint8_t *)member_buffer(m, cells, eq == EULER2D ? 3 : 2) : nullptr,
                       d_amax + (size_t)i * AMAX_SLOTS * AMAX_VALS, d_ctrl + i, xt, yt);
         }
         h_hdr.n_inst = count;
@@ -510,7 +521,8 @@ struct enoao_pool {
             double *m = (double *)(arena + slots[k].off);
             const size_t cells = (size_t)r.nc * p.nx * p.ny;
             Inst I;
-            r.fill_inst(I, p, m, m + cells, m + 2 * cells, r.eq == EULER2D ? m + 3 * cells : nullptr, nullptr,
+            r.fill_inst(I, p, member_buffer(m, cells, 0), member_buffer(m, cells, 1), member_buffer(m, cells, 2),
+                        r.eq == EULER2D ? member_buffer(m, cells, 3) : nullptr, nullptr,
                         r.d_amax + (size_t)k * AMAX_SLOTS * AMAX_VALS, r.d_ctrl + k, xt, yt);
             r.h_inst.push_back(I);
         }
@@ -530,7 +542,7 @@ struct enoao_pool {
 static size_t pool_member_bytes(const enoao_problem *p)
 {
     const size_t cells = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
-    return enoao_pool::align(cells * sizeof(double) * (p->equation == EULER2D ? 4 : 3));
+    return enoao_pool::align((cells + BUF_STAGGER) * sizeof(double) * (p->equation == EULER2D ? 4 : 3));
 }
 
 extern "C" {

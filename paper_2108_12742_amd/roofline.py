@@ -43,37 +43,46 @@ def face_flops(equation: str, order: int) -> int:
     return node + roe + projection + split + recon + back + diff
 
 
+def combine_flops(nc: int, stage: int) -> int:
+    """Shu-Osher stage combine per cell: in + dt L (one fma per component), and for
+    stages 2 and 3 the weighted sum with u^n (a multiply and an fma more)."""
+    return 2 * nc if stage == 1 else 5 * nc
+
+
+MAXIMA_FLOPS = {"advection": 1, "euler1d": 16, "euler2d": 28}  # per-field wave-speed maxima of a cell
+
+
 def stage_cell_flops(equation: str, stage: int) -> int:
-    """RK combine + maxima epilogue per cell of the last sweep of a stage."""
+    """Per-cell work of a stage besides the faces, summed over the stage's kernels:
+    1D: combine + maxima in the x-sweep; 2D: the x-sweep combines with its part of L,
+    the y-sweep adds its part (one fma per component) and takes the maxima."""
     nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
-    combine = 2 * nc if stage == 1 else 5 * nc
-    maxima = {"advection": 1, "euler1d": 16, "euler2d": 28}[equation]
-    add_x = nc if equation == "euler2d" else 0
-    return combine + maxima + add_x
+    extra = 2 * nc if equation == "euler2d" else 0
+    return combine_flops(nc, stage) + MAXIMA_FLOPS[equation] + extra
 
 
 def sweep_bytes(equation: str, kernel: str, stage: int) -> int:
-    """Compulsory HBM bytes per cell of one launch.
+    """Compulsory HBM bytes per cell of one launch (stage 0: evaluation of L only).
 
-    kernel 'x' (2D): read stage input, write the x-part of L.
-    kernel 'y' (2D) / 'x' (1D): read stage input (+ u^n for stages 2, 3)
-    (+ the x-part of L in 2D), write the stage output."""
+    1D 'x': read the stage input (+ u^n for stages 2, 3), write the stage output.
+    2D 'x': read the stage input (+ u^n for stages 2, 3), write the x-part z.
+    2D 'y': read the stage input and z, write the stage output (rhs: L)."""
     nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
     w = 8 * nc
-    if equation == "euler2d" and kernel == "x":
-        return 2 * w
-    b = 2 * w + (w if stage > 1 else 0)
-    if equation == "euler2d":
-        b += w
-    return b
+    if equation == "euler2d" and kernel == "y":
+        return 3 * w
+    return 2 * w + (w if stage > 1 else 0)
 
 
 def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
     """Algorithmic flops per cell of one launch."""
+    nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
     f = face_flops(equation, order)
-    if equation == "euler2d" and kernel == "x":
+    if stage == 0:
         return f
-    return f + stage_cell_flops(equation, stage)
+    if equation == "euler2d":
+        return f + (combine_flops(nc, stage) if kernel == "x" else 2 * nc + MAXIMA_FLOPS[equation])
+    return f + combine_flops(nc, stage) + MAXIMA_FLOPS[equation]
 
 
 def cell_update_flops(equation: str, order: int) -> int:
@@ -85,6 +94,13 @@ def cell_update_bytes(equation: str) -> int:
     if equation == "euler2d":
         return sum(sweep_bytes(equation, "x", s) + sweep_bytes(equation, "y", s) for s in (1, 2, 3))
     return sum(sweep_bytes(equation, "x", s) for s in (1, 2, 3))
+
+
+def resident_bytes(equation: str, steps: int) -> float:
+    """LDS-resident solver: the state is read once and written once per call, so the
+    compulsory HBM bytes per cell-update are 2 * state / steps."""
+    nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
+    return 2.0 * 8 * nc / max(steps, 1)
 
 
 def roofline_entry(flops: float, nbytes: float, seconds: float, traffic=None):
