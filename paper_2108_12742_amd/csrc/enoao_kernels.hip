@@ -24,7 +24,10 @@
 #define ENOAO_NODE_PREFETCH 1  // stencil nodes whose LDS reads are in flight ahead of use
 #endif
 #ifndef ENOAO_NODE_SCHED
-#define ENOAO_NODE_SCHED 1     // scheduling barrier per stencil node (bounds register use)
+#define ENOAO_NODE_SCHED 1     // stencil nodes between scheduling fences (0: none; bounds register use)
+#endif
+#ifndef ENOAO_JOINT_EXIT
+#define ENOAO_JOINT_EXIT 1     // one wave-uniform top-candidate shortcut per field pass
 #endif
 
 namespace enoao {
@@ -173,13 +176,38 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
             if (t < W) gp[i][t] = fma(al[s], PU[s], PF[s]);
             if (t >= 1) gm[i][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
         }
-        // bound the live ranges: at most D + 1 nodes' U and F in flight
-        if (ENOAO_NODE_SCHED) __builtin_amdgcn_sched_barrier(0);
+        // bound the live ranges: a scheduling fence every NODE_SCHED nodes
+        if (ENOAO_NODE_SCHED > 0 && t % ENOAO_NODE_SCHED == ENOAO_NODE_SCHED - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    // window = 2 * field_scale * w^(+/-).  Joint shortcut: when every window of
+    // the pass on every lane has IS <= delta for the top candidate, the top
+    // candidate is every choice (first principle) and the rest of the selection
+    // is skipped for the whole pass; the windows' work is then one straight-line
+    // block.  Results are bitwise those of the full selection.
+    if (ENOAO_JOINT_EXIT) {
+        double hp[NF], hm[NF];
+        bool all = true;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const double sd = 2.0 * field_scale<NC>(fs[i]) * delta;
+            double ip, im;
+            hp[i] = Recon<ORDER>::top(gp[i], ip);
+            hm[i] = Recon<ORDER>::top(gm[i], im);
+            all = all && ip <= sd && im <= sd;
+        }
+        if (wave_all(all)) {
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const int s = fs[i];
+                wh[s] = (hp[i] + hm[i]) * (1.0 / (2.0 * field_scale<NC>(s)));
+                sel[2 * s] = sel[2 * s + 1] = ReconTraits<ORDER>::K - 1;
+            }
+            return;
+        }
     }
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         const int s = fs[i];
-        // window = 2 * field_scale * w^(+/-)
         const double sc = 2.0 * field_scale<NC>(s);
         int sp, sm;
         const double hp = Recon<ORDER>::run(gp[i], sc * delta, sp);
