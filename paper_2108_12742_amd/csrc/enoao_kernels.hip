@@ -547,13 +547,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D).  A workgroup tile: 16 columns x 16 faces along y (16 x 15
-// cells); each wave owns a strip of 4 columns (lane = 4 * face row + column),
-// stages its strip's nodes itself and exchanges face fluxes only among its own
-// lanes, so the tile loop has no workgroup barrier.  Momentum components are
-// exchanged on load so the x-direction formulas apply.  Pipelined like the
-// x-sweep; the epilogue operands (x-part of L, u^n) are prefetched with the
-// nodes.
+// y-sweep (2D).  A workgroup tile: YT_COLS columns x YT_FACES faces along y
+// (YT_COLS x YT_CELLS cells); each wave owns a strip of YW_COLS columns (lane =
+// YW_COLS * face row + column), stages its strip's nodes itself and exchanges
+// face fluxes only among its own lanes, so the tile loop has no workgroup
+// barrier.  Momentum components are exchanged on load so the x-direction
+// formulas apply.  Pipelined like the x-sweep; the epilogue operand (the
+// x-part of L or of the stage combine) is prefetched with the nodes.
 constexpr int YW_COLS = YT_COLS / (BLOCK / 64);  // columns per wave
 
 // a tile's position within its instance: tile row along y, column group

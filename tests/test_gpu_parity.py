@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
 seeded inputs.  Sizes span several tiles and ragged tails (x segments hold 63 cells,
-y tiles 16 x 15 cells), plus the degenerate sizes below one tile."""
+y tiles 32 x 7 cells), plus the degenerate sizes below one tile."""
 import math
 
 import numpy as np
