@@ -18,16 +18,12 @@ enum Bc : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
 constexpr int XW_FACES = 64;
 constexpr int XW_CELLS = XW_FACES - 1;
 constexpr int XW_SEGS = 4;
-// y-sweep tiles: YT_COLS columns x YT_FACES faces per workgroup, updating
-// YT_COLS x (YT_FACES - 1) cells; each of the 4 waves owns YT_COLS / 4 columns
-// (YT_FACES faces x YT_COLS / 4 columns = 64 lanes).
-#ifndef ENOAO_YT_FACES
-#define ENOAO_YT_FACES 8
-#endif
-constexpr int YT_FACES = ENOAO_YT_FACES;
-constexpr int YT_COLS = 4 * (64 / YT_FACES);
-constexpr int YT_CELLS = YT_FACES - 1;
-static_assert(YT_FACES * (YT_COLS / 4) == 64, "a y strip is one wave");
+// y-sweep tiles: YT_COLS columns x YT_CELLS cell rows per workgroup; each of
+// the 4 waves owns YT_COLS / 4 columns (YT_CELLS rows x YT_COLS / 4 columns =
+// 64 lanes, one new face per lane and tile).
+constexpr int YT_CELLS = 8;
+constexpr int YT_COLS = 32;
+static_assert(YT_CELLS * (YT_COLS / 4) == 64, "a y strip is one wave");
 constexpr int BLOCK = 256;
 
 // per-field maxima kept per instance: three ring slots of 8 values each

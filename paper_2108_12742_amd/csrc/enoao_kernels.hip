@@ -547,13 +547,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D).  A workgroup tile: YT_COLS columns x YT_FACES faces along y
-// (YT_COLS x YT_CELLS cells); each wave owns a strip of YW_COLS columns (lane =
-// YW_COLS * face row + column), stages its strip's nodes itself and exchanges
-// face fluxes only among its own lanes, so the tile loop has no workgroup
-// barrier.  Momentum components are exchanged on load so the x-direction
-// formulas apply.  Pipelined like the x-sweep; the epilogue operand (the
-// x-part of L or of the stage combine) is prefetched with the nodes.
+// y-sweep (2D).  A workgroup tile is YT_COLS columns x YT_CELLS cell rows; each
+// wave owns a strip of YW_COLS columns (lane = YW_COLS * row + column) and
+// walks its tiles down the strip.  Successive tiles of a walk share node rows
+// and one face row, so a walk keeps a rolling buffer: after its first tile, a
+// tile copies the 2G-1 node rows it shares with the previous one, stages only
+// YT_CELLS new rows, reuses the previous tile's last face row, and computes
+// YT_CELLS new face rows -- one face and one staged node per lane and tile,
+// and every face of the walk is computed once.  Each wave exchanges data only
+// among its own lanes, so the tile loop has no workgroup barrier.  Momentum
+// components are exchanged on load so the x-direction formulas apply.  The
+// next tile's global operands are prefetched into registers.
 constexpr int YW_COLS = YT_COLS / (BLOCK / 64);  // columns per wave
 
 // a tile's position within its instance: tile row along y, column group
@@ -577,25 +581,38 @@ __device__ __forceinline__ YCur y_advance(YCur c, int per_row)
     return c;
 }
 
-struct YPre {
-    double U[2][4];
-    double lx[4];  // x-part of L (rhs) or of the stage combine
+// buffer rows of a walk: row b holds node row sy - G + b (sy = first cell row
+// of the tile); face row k (k = 0..YT_CELLS, the face below cell row sy + k)
+// reads buffer rows k .. k + 2G - 1
+template <int G> struct YBuf {
+    static constexpr int ROWS = YT_CELLS + 2 * G;
+    static constexpr int NODES = ROWS * YW_COLS;           // staged by a walk's first tile
+    static constexpr int J = (NODES + 63) / 64;            // nodes per lane then
+    static constexpr int FRESH = 2 * G;                    // first row a later tile stages
 };
 
-// a lane's global operands of one y tile: the strip nodes it stages (strip
-// positions lane and lane + 64) and the x-part of L (+ u^n) at its cell
+template <int G> struct YPre {
+    double U[YBuf<G>::J][4];
+    double lx[4];  // x-part of L (rhs) or of the stage combine at the lane's cell
+};
+
+// a lane's global operands of one y tile: the strip nodes it stages (all rows
+// for the first tile of a walk, rows FRESH.. for the others) and the x-part at
+// its cell
 template <int MODE, int G>
-__device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c, int wv, int lane, YPre &pre)
+__device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c, bool first, int wv, int lane,
+                                           YPre<G> &pre)
 {
-    constexpr int NR = YT_FACES + 2 * G - 1;
+    using B = YBuf<G>;
     const int perm[4] = {0, 2, 1, 3};
     const int nx = v.nx, ny = v.ny;
     const long long plane = (long long)nx * ny;
     const int sy = c.ty * YT_CELLS, cbase = c.cg * YT_COLS + wv * YW_COLS;
+    const int b0 = first ? 0 : B::FRESH;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int i = lane + 64 * j;
-        if (i < NR * YW_COLS) {
+    for (int j = 0; j < B::J; ++j) {
+        const int i = b0 * YW_COLS + lane + 64 * j;
+        if (i < B::NODES && (first || j == 0)) {
             const int r = i / YW_COLS, c0 = i % YW_COLS;
             const int y = bc_map(sy - G + r, ny, v.bc);
             const int x = min(cbase + c0, nx - 1);
@@ -605,10 +622,33 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
         }
     }
     const int fl = lane / YW_COLS, y = sy + fl, col = cbase + (lane % YW_COLS);
-    if (fl < YT_CELLS && y < ny && col < nx) {
+    if (y < ny && col < nx) {
         const long long o = (long long)y * nx + col;
 #pragma unroll
         for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
+    }
+}
+
+// one face of a y strip into the face buffer (and the selection record)
+template <int ORDER, bool REC, int MODE>
+__device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KParams &P, const double *W, int QS,
+                                       double *WF, int k, int cc, int col, int f)
+{
+    constexpr int NC = 4;
+    double Fh[NC];
+    int sel[2 * NC];
+    face_flux<EULER2D, ORDER>(W + k * YW_COLS + cc, QS, YW_COLS, v.al, P.gm1, P.delta, 0.0, Fh, sel);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) WF[(q * (YT_CELLS + 1) + k) * YW_COLS + cc] = Fh[q];
+    if (REC && v.sel && col < v.nx && f <= v.ny) {
+        const long long xblock = (long long)v.ny * (v.nx + 1), yblock = (long long)(v.ny + 1) * v.nx;
+        const long long ybase = (long long)NC * 2 * xblock;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const long long o = ybase + (long long)(2 * s) * yblock + (long long)f * v.nx + col;
+            v.sel[o] = (uint8_t)sel[2 * s];
+            v.sel[o + yblock] = (uint8_t)sel[2 * s + 1];
+        }
     }
 }
 
@@ -617,10 +657,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
 {
     constexpr int NC = 4, NQ = 12, NW = BLOCK / 64;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
-    constexpr int NR = YT_FACES + 2 * G - 1;  // node rows staged
-    constexpr int QS = NR * YW_COLS;         // a wave's LDS stride between quantities
+    using B = YBuf<G>;
+    constexpr int QS = B::NODES;  // a wave's LDS stride between quantities
     __shared__ double lds[NW * NQ * QS];
-    __shared__ double fh[NW * NC * YT_FACES * YW_COLS];
+    __shared__ double fh[NW * NC * (YT_CELLS + 1) * YW_COLS];
     __shared__ double red[NW * 8];
     // epilogue operand of the tile (x-part), staged from the prefetch registers
     // so it is not held through the face arithmetic
@@ -631,13 +671,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int cc = lane % YW_COLS, fl = lane / YW_COLS;
     double *W = lds + wv * NQ * QS;
-    double *WF = fh + wv * NC * YT_FACES * YW_COLS;
+    double *WF = fh + wv * NC * (YT_CELLS + 1) * YW_COLS;
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->ytiles_total;
     const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
     Maxima<EULER2D> mx;
     mx.reset();
-    YPre pre;
+    YPre<G> pre;
 
     // one outer iteration per instance met by the workgroup's chunk (uniform
     // over the workgroup: the maxima flush is reached by all waves together)
@@ -651,12 +691,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
         const int nx = v.nx, ny = v.ny;
         const long long plane = (long long)nx * ny;
         YCur c = y_cursor(tile, v.t0, v.per_row);
-        y_prefetch<MODE, G>(v, c, wv, lane, pre);
+        bool first = true;  // the tile starts a walk
+        y_prefetch<MODE, G>(v, c, true, wv, lane, pre);
         for (; tile < tend; ++tile) {
+            if (!first) {
+                // rows shared with the previous tile move up by YT_CELLS
+                for (int i = YW_COLS + lane; i < B::FRESH * YW_COLS; i += 64) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int i = lane + 64 * j;
-                if (i < NR * YW_COLS) {
+                    for (int m = 0; m < NQ; ++m) W[m * QS + i] = W[m * QS + i + YT_CELLS * YW_COLS];
+                }
+                wave_sync();  // the new rows below overwrite rows other lanes just read
+            }
+#pragma unroll
+            for (int j = 0; j < B::J; ++j) {
+                const int i = (first ? 0 : B::FRESH * YW_COLS) + lane + 64 * j;
+                if (i < B::NODES && (first || j == 0)) {
                     double q[NQ];
                     node_quantities<EULER2D>(pre.U[j], P.gm1, q);
 #pragma unroll
@@ -666,37 +715,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
 #pragma unroll
             for (int q = 0; q < NC; ++q) elx[q * BLOCK + tid] = pre.lx[q];
             const YCur cn = y_advance(c, v.per_row);
-            if (tile + 1 < tend) y_prefetch<MODE, G>(v, cn, wv, lane, pre);
+            const bool next_first = cn.ty == 0;
+            if (tile + 1 < tend) y_prefetch<MODE, G>(v, cn, next_first, wv, lane, pre);
             wave_sync();
 
             const int sy = c.ty * YT_CELLS;
-            const int col = c.cg * YT_COLS + wv * YW_COLS + cc, f = sy + fl;
-            {
-                double Fh[NC];
-                int sel[2 * NC];
-                face_flux<EULER2D, ORDER>(W + fl * YW_COLS + cc, QS, YW_COLS, v.al, P.gm1, P.delta, 0.0, Fh, sel);
-#pragma unroll
-                for (int q = 0; q < NC; ++q) WF[(q * YT_FACES + fl) * YW_COLS + cc] = Fh[q];
-                if (REC && v.sel && col < nx && f <= ny) {
-                    const long long xblock = (long long)ny * (nx + 1), yblock = (long long)(ny + 1) * nx;
-                    const long long ybase = (long long)NC * 2 * xblock;
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const long long o = ybase + (long long)(2 * s) * yblock + (long long)f * nx + col;
-                        v.sel[o] = (uint8_t)sel[2 * s];
-                        v.sel[o + yblock] = (uint8_t)sel[2 * s + 1];
-                    }
-                }
+            const int col = c.cg * YT_COLS + wv * YW_COLS + cc;
+            // a walk's first tile also computes face row 0 (one call site, so the
+            // face code is instantiated once)
+#pragma unroll 1
+            for (int pass = first ? 0 : 1; pass < 2; ++pass) {
+                const int k = pass == 0 ? 0 : fl + 1;
+                if (pass == 1 || lane < YW_COLS) y_face<ORDER, REC, MODE>(v, P, W, QS, WF, k, cc, col, sy + k);
             }
             wave_sync();
 
             const int y = sy + fl;
-            if (fl < YT_CELLS && y < ny && col < nx) {
+            if (y < ny && col < nx) {
                 const long long o = (long long)y * nx + col;
                 double Ly[NC];  // natural component order
 #pragma unroll
                 for (int q = 0; q < NC; ++q)
-                    Ly[perm[q]] = -(WF[(q * YT_FACES + fl + 1) * YW_COLS + cc] - WF[(q * YT_FACES + fl) * YW_COLS + cc]) * v.idy;
+                    Ly[perm[q]] = -(WF[(q * (YT_CELLS + 1) + fl + 1) * YW_COLS + cc] -
+                                    WF[(q * (YT_CELLS + 1) + fl) * YW_COLS + cc]) * v.idy;
                 if constexpr (MODE == M_RHS) {
 #pragma unroll
                     for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = elx[q * BLOCK + tid] + Ly[q];
@@ -712,7 +753,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
                 }
             }
             wave_sync();
+            // the last face row is the next tile's first
+            if (lane < YW_COLS) {
+#pragma unroll
+                for (int q = 0; q < NC; ++q)
+                    WF[(q * (YT_CELLS + 1)) * YW_COLS + lane] = WF[(q * (YT_CELLS + 1) + YT_CELLS) * YW_COLS + lane];
+            }
+            wave_sync();
             c = cn;
+            first = next_first;
         }
         if (MODE != M_RHS) mx.flush(v.amax, v.ctrl, P.r_out, red);
     }

@@ -210,6 +210,40 @@ def test_launch_shape_invariance():
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("order", [5, 7])
+def test_multi_tile_walks(order):
+    """A grid large enough that every workgroup walks several tiles of a strip (x
+    segments and y tiles), with walks that start mid-column and cross column groups:
+    L with selections and one step match the oracle, for two persistent launch shapes
+    that cut the walks differently (bitwise equal to each other)."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.quadrants(7, 640, 403)
+    print(f"multi-tile walks, order {order}, 640 x 403", flush=True)
+    ep = E.problem_from_instance(inst, order=order, record_selection=True)
+    op = PT.oracle_problem(ep)
+    Lr, selr, tier = O.rhs(op, inst.u0, with_selection=True)
+    dt = 0.5 * O.cfl_dt(op, inst.u0, 0.3)
+    ur = O.step(op, inst.u0, dt)
+    steps = []
+    try:
+        for wg in (1, 2):
+            E.enoao_set_launch(wg)
+            plan = E.enoao_plan_create(ep)
+            u = PT.to_dev(torch, inst.u0)
+            L = torch.empty_like(u)
+            E.enoao_rhs(plan, u, L)
+            sel = E.enoao_get_selection(plan)
+            mask = PT.compare_selection(op, sel, selr, tier)
+            PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what=f"L (wg {wg})")
+            E.enoao_step(plan, u, dt)
+            steps.append(u.cpu())
+            PT.assert_close_by_component(steps[-1].numpy(), ur, mask=mask, what=f"u (wg {wg})")
+    finally:
+        E.enoao_set_launch(0)
+    assert torch.equal(steps[0], steps[1])
+
+
 def test_nonphysical_state_reported():
     torch = PT.torch_cuda()
     E = _E()
