@@ -147,15 +147,19 @@ enoao_status enoao_get_selection(enoao_plan *plan, uint8_t *host_out, size_t n, 
  * boundary conditions), each with its own CFL time step, time and step
  * count.  Every Runge-Kutta stage of every member is one persistent kernel
  * launch over the flattened list of line tiles of all members; a step is
- * captured once into a HIP graph and replayed. */
+ * captured once into a HIP graph and replayed.  (1D batches whose members all
+ * fit one workgroup's LDS run on the LDS-resident solver instead, see
+ * enoao_set_resident; results are the same.) */
 enoao_status enoao_batch_create(const enoao_problem *probs, int32_t n, void *stream, enoao_batch **out);
 enoao_status enoao_batch_destroy(enoao_batch *batch);
 
 /* Advance every member i (state u[i], a device pointer, in place) by nsteps
  * CFL steps of its own size (cfl > 0), stopping a member early once it
  * reaches t_final[i] (t_final may be NULL: no end time).  Member times and
- * step counts persist across calls until enoao_batch_reset.  Synchronises
- * stream only when status is requested via enoao_batch_query. */
+ * step counts persist across calls until enoao_batch_reset.  The call
+ * synchronises stream once at its start (member controls are read and
+ * updated on the host) and returns with the steps enqueued; member status is
+ * reported by enoao_batch_query. */
 enoao_status enoao_batch_step(enoao_batch *batch, double *const *u, int32_t nsteps, double cfl,
                               const double *t_final, void *stream);
 enoao_status enoao_batch_reset(enoao_batch *batch, void *stream);
@@ -230,11 +234,13 @@ enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_c
 
 /* LDS-resident solver for small 1D problems (advection and Euler 1D, any
  * order, no selection record).  When every member of a plan or batch fits one
- * workgroup's LDS (state, stage state and face fluxes of the whole line; about
- * 1990 nodes for Euler 1D and 6600 for advection on gfx950), enoao_solve and
- * enoao_batch_step run their time-step-controlled steps in one launch with one
- * workgroup per member: the state is read from HBM once, every step and stage
- * runs out of LDS, and the state is written back at the end of the call.  The
+ * workgroup's LDS (state, stage state and face fluxes of the whole line plus
+ * one staging chunk: about 1740 nodes for Euler 1D and 6600 for advection on
+ * gfx950), enoao_solve and enoao_batch_step run their time-step-controlled
+ * steps in launches of many steps each (up to 1024 in enoao_solve, 32 in
+ * enoao_batch_step) with one workgroup per member: the state is read from HBM
+ * at the start of a launch, every step and stage runs out of LDS, and the
+ * state is written back at its end.  The
  * arithmetic is the streaming kernels' (Sections 2 to 4 as above), so results
  * are bitwise the same either way.  enable = 1 (default) allows it for plans
  * and batches used afterwards, 0 forces the streaming kernels; other values
