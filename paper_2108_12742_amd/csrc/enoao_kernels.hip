@@ -61,6 +61,7 @@ __device__ __forceinline__ int find_inst(const Inst *inst, int n, long long tile
 // Maxima of the per-field wave speeds of a state (for alpha of the next
 // evaluation and for the CFL step), and the non-physical flag.
 template <int EQ> struct Maxima {
+    static constexpr int NV = EQ == EULER2D ? 7 : (EQ == EULER1D ? 3 : 0);  // values in use
     double v[7];
     int bad;
     __device__ void reset()
@@ -101,7 +102,7 @@ template <int EQ> struct Maxima {
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-        for (int i = 0; i < 7; ++i) {
+        for (int i = 0; i < NV; ++i) {
             double x = v[i];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
@@ -112,16 +113,15 @@ template <int EQ> struct Maxima {
         for (int o = 32; o > 0; o >>= 1) b |= __shfl_xor(b, o, 64);
         if (lane == 0) {
 #pragma unroll
-            for (int i = 0; i < 7; ++i) red[wave * 8 + i] = v[i];
+            for (int i = 0; i < NV; ++i) red[wave * 8 + i] = v[i];
             red[wave * 8 + 7] = (double)b;
         }
         __syncthreads();
-        if (threadIdx.x < 8) {
+        if (threadIdx.x < NV || threadIdx.x == 7) {
             double x = red[threadIdx.x];
             for (int w = 1; w < BLOCK / 64; ++w) x = fmax(x, red[w * 8 + threadIdx.x]);
-            if (threadIdx.x < 7) {
-                if (EQ != ADVECTION && slot >= 0)
-                    atomicMax(&amax[slot * AMAX_VALS + threadIdx.x], as_bits(x));
+            if (threadIdx.x < NV) {
+                if (slot >= 0) atomicMax(&amax[slot * AMAX_VALS + threadIdx.x], as_bits(x));
             } else if (x != 0.0) {
                 atomicOr(&ctrl->status, 1);
             }
@@ -312,12 +312,24 @@ template <int EQ, int MODE> struct View {
     double al[NC];
 };
 
+// The view of the instance holding `tile`.  prev: the instance the walk was in
+// (-1 at the start of a chunk: binary search); the tile lists are ordered by
+// instance, so after the first the walk just moves on to the next instance
+// that has tiles left.
 template <int EQ, int MODE, bool Y>
-__device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst, long long tile)
+__device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst, long long tile, int prev)
 {
     constexpr int NC = NodeTraits<EQ>::NC;
     View<EQ, MODE> v;
-    v.k = uniform(find_inst<!Y>(P.inst, n_inst, tile));
+    int k;
+    if (prev < 0) {
+        k = find_inst<!Y>(P.inst, n_inst, tile);
+    } else {
+        k = prev + 1;
+        while (k < n_inst - 1 && tile >= (Y ? P.inst[k].ytile0 + P.inst[k].ytiles : P.inst[k].xtile0 + P.inst[k].xtiles))
+            ++k;
+    }
+    v.k = uniform(k);
     const Inst &I = P.inst[v.k];
     v.t0 = uniform(Y ? I.ytile0 : I.xtile0);
     v.t1 = v.t0 + uniform(Y ? I.ytiles : I.xtiles);
@@ -457,8 +469,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
     // runs once per instance met by the workgroup's chunk (uniform over the
     // workgroup, so the maxima flush, a workgroup reduction, is reached by all
     // waves together).
+    int prev = -1;
     for (long long tile = t0; tile < t1;) {
-        const View<EQ, MODE> v = load_view<EQ, MODE, false>(P, n_inst, tile);
+        const View<EQ, MODE> v = load_view<EQ, MODE, false>(P, n_inst, tile, prev);
+        prev = v.k;
         const long long tend = v.t1 < t1 ? v.t1 : t1;
         if (!v.active) {
             tile = tend;
@@ -681,8 +695,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
 
     // one outer iteration per instance met by the workgroup's chunk (uniform
     // over the workgroup: the maxima flush is reached by all waves together)
+    int prev = -1;
     for (long long tile = t0; tile < t1;) {
-        const View<EULER2D, MODE> v = load_view<EULER2D, MODE, true>(P, n_inst, tile);
+        const View<EULER2D, MODE> v = load_view<EULER2D, MODE, true>(P, n_inst, tile, prev);
+        prev = v.k;
         const long long tend = v.t1 < t1 ? v.t1 : t1;
         if (!v.active) {
             tile = tend;
@@ -883,9 +899,10 @@ __global__ void step_control(KParams P)
 template <int EQ>
 __device__ __forceinline__ void resident_reduce(Maxima<EQ> &mx, double *red, double *cm, Ctrl &C)
 {
+    constexpr int NV = Maxima<EQ>::NV;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < NV; ++i) {
         double x = mx.v[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
@@ -896,14 +913,15 @@ __device__ __forceinline__ void resident_reduce(Maxima<EQ> &mx, double *red, dou
     for (int o = 32; o > 0; o >>= 1) b |= __shfl_xor(b, o, 64);
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 7; ++i) red[wv * 8 + i] = mx.v[i];
+        for (int i = 0; i < NV; ++i) red[wv * 8 + i] = mx.v[i];
         red[wv * 8 + 7] = (double)b;
     }
     __syncthreads();
     if (threadIdx.x < 8) {
         double x = red[threadIdx.x];
         for (int w = 1; w < RES_WAVES; ++w) x = fmax(x, red[w * 8 + threadIdx.x]);
-        if (threadIdx.x < 7) cm[threadIdx.x] = x;
+        if (threadIdx.x < NV) cm[threadIdx.x] = x;
+        else if (threadIdx.x < 7) cm[threadIdx.x] = 0.0;
         else if (x != 0.0) C.status |= 1;
     }
     __syncthreads();
