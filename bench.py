@@ -20,10 +20,10 @@ import time
 import numpy as np
 
 METRIC = "cell-updates/s + % HBM/FP64 roofline; batched vs plain; p50/p99 latency"
-KERNEL_NAMES = {  # profile kind -> kernel symbol as rocprofv3 prints it (order 5, no selection record)
+KERNEL_NAMES = {  # profile kind -> kernel symbol as rocprofv3 prints it (order 5, no record, default tiles)
     "sweep_x_s1": "enoao::sweep_x<2, 5, 1, false>", "sweep_x_s2": "enoao::sweep_x<2, 5, 2, false>",
-    "sweep_x_s3": "enoao::sweep_x<2, 5, 3, false>", "sweep_y_s1": "enoao::sweep_y<5, 1, false>",
-    "sweep_y_s2": "enoao::sweep_y<5, 2, false>", "sweep_y_s3": "enoao::sweep_y<5, 3, false>",
+    "sweep_x_s3": "enoao::sweep_x<2, 5, 3, false>", "sweep_y_s1": "enoao::sweep_y<5, 1, false, 8>",
+    "sweep_y_s2": "enoao::sweep_y<5, 2, false, 8>", "sweep_y_s3": "enoao::sweep_y<5, 3, false, 8>",
 }
 
 
@@ -86,7 +86,7 @@ def bench_batched(steps=100, warmup=2, count=512):
     probs = [E.problem_from_instance(i) for i in insts]
     u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
     states = [u.clone() for u in u0]
-    best, timing = T.tune_batch(probs, states, steps=3)
+    (best, yw), timing = T.tune_batch(probs, states, steps=3)
     batch = E.enoao_batch_create(probs)
     E.enoao_batch_set_launch(batch, best)
     E.enoao_batch_step(batch, states, warmup, 0.3)
@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (512 1D members, batched vs plain) and served (Poisson arrivals) legs")
     ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="main workload at the default launch shape (occupancy, 8-column y strips)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
@@ -289,9 +291,15 @@ def main():
     n, K, Wu = args.n, args.steps, args.warmup
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
     ep = E.problem_from_instance(inst, order=args.order)
-    plan = E.enoao_plan_create(ep)
     u0 = torch.from_numpy(inst.u0).cuda()
     u = u0.clone()
+    launch, tuner = (0, 8), None
+    if not args.no_tune:  # launch shape (workgroups per CU, y strip columns) from the autotuner
+        from paper_2108_12742_amd import tune as T
+        launch, tuner = T.tune_batch([ep], [u], steps=3)
+    plan = E.enoao_plan_create(ep)
+    E.enoao_plan_set_launch(plan, launch[0])
+    E.enoao_plan_set_tiles(plan, launch[1])
     if Wu > 0:
         E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=Wu)
     u.copy_(u0)
@@ -321,7 +329,8 @@ def main():
             fl = cells * R.sweep_flops("euler2d", args.order, kern, stage)
             by = cells * R.sweep_bytes("euler2d", kern, stage)
             entry["roofline"] = R.roofline_entry(fl, by, ms * 1e-3)
-            entry["symbol"] = KERNEL_NAMES.get(kind) if args.order == 5 else None
+            sym = KERNEL_NAMES.get(kind) if args.order == 5 else None
+            entry["symbol"] = sym.replace(", 8>", f", {launch[1]}>") if sym else None
             if best is None or ms * cnt > best[1]:
                 best = (kind, ms * cnt)
         kernels[kind] = entry
@@ -334,7 +343,9 @@ def main():
         "ms_per_step": el * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "nx": n, "ny": n, "order": args.order,
-                   "bc": "periodic", "cfl": 0.3, "seed": W.QUADRANT_BENCH_SEED, "parallelism": "single-gpu"},
+                   "bc": "periodic", "cfl": 0.3, "seed": W.QUADRANT_BENCH_SEED, "parallelism": "single-gpu",
+                   "workgroups_per_cu": launch[0], "y_strip_columns": launch[1]},
+        "tuner_ms_per_step": tuner,
         "roofline": roof,
         "cpu_baseline": None,
         "kernels": kernels,

@@ -232,6 +232,15 @@ enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved);
 enoao_status enoao_plan_set_launch(enoao_plan *plan, int32_t workgroups_per_cu);
 enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_cu);
 
+/* Tile width of the 2D y-sweep: columns per wave strip, 4 or 8 (0 = the
+ * default, 8).  A y tile is 4 strips wide and 64/w cell rows tall; wider
+ * strips load longer row segments per wave, narrower ones stage fewer halo
+ * rows per face.  The plan's or batch's tile lists are rebuilt (this
+ * synchronises stream) and its captured graph is dropped.  1D problems have
+ * no y-sweep and ignore the setting.  Results do not depend on it. */
+enoao_status enoao_plan_set_tiles(enoao_plan *plan, int32_t y_strip_columns, void *stream);
+enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, void *stream);
+
 /* LDS-resident solver for small 1D problems (advection and Euler 1D, any
  * order, no selection record).  When every member of a plan or batch fits one
  * workgroup's LDS (state, stage state and face fluxes of the whole line plus

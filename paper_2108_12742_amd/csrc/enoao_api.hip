@@ -104,6 +104,7 @@ struct Runtime {
     hipStream_t cap = nullptr;
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
     int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
+    int yw = YW_DEFAULT;  // columns per wave strip of the y-sweep tiles (4 or 8)
     // every member 1D and small enough for the LDS-resident solver (res_lds
     // dynamic LDS bytes per workgroup); controlled steps then run there
     bool resident = false;
@@ -277,8 +278,8 @@ struct Runtime {
         I.dy = eq == EULER2D ? (p.y_hi - p.y_lo) / p.ny : 1.0;
         I.adv = p.adv_speed;
         I.segs_per_row = (p.nx + XW_CELLS - 1) / XW_CELLS;
-        I.ytiles_per_row = (p.ny + YT_CELLS - 1) / YT_CELLS;
-        I.ycol_groups = (p.nx + YT_COLS - 1) / YT_COLS;
+        I.ytiles_per_row = (p.ny + yt_cells(yw) - 1) / yt_cells(yw);
+        I.ycol_groups = (p.nx + yt_cols(yw) - 1) / yt_cols(yw);
         I.xtile0 = xt;
         I.xtiles = ((long long)p.ny * I.segs_per_row + XW_SEGS - 1) / XW_SEGS;
         I.ytile0 = yt;
@@ -292,7 +293,7 @@ struct Runtime {
         const long long xt = h_hdr.xtiles_total, yt = h_hdr.ytiles_total;
         for (int m = 0; m < 4; ++m) {
             grid_x[m] = grid_for(xt, occupancy_x(eq, order, m, false));
-            grid_y[m] = eq == EULER2D ? grid_for(yt, occupancy_y(order, m, false)) : 0;
+            grid_y[m] = eq == EULER2D ? grid_for(yt, occupancy_y(order, m, false, yw)) : 0;
         }
         grid_m = grid_for(xt, occupancy_maxima(eq));
     }
@@ -307,6 +308,29 @@ struct Runtime {
             graph = nullptr;
             graph_k = 0;
         }
+    }
+
+    // new y tile width: the members' y tile lists rebuilt and uploaded, grids
+    // recomputed, the captured graph dropped
+    enoao_status set_ytiles(int w, hipStream_t s)
+    {
+        if (w == yw) return ENOAO_OK;
+        yw = w;
+        long long yt = 0;
+        for (int i = 0; i < n; ++i) {
+            Inst &I = h_inst[i];
+            I.ytiles_per_row = (I.ny + yt_cells(yw) - 1) / yt_cells(yw);
+            I.ycol_groups = (I.nx + yt_cols(yw) - 1) / yt_cols(yw);
+            I.ytile0 = yt;
+            I.ytiles = eq == EULER2D ? (long long)I.ytiles_per_row * I.ycol_groups : 0;
+            yt += I.ytiles;
+        }
+        h_hdr.ytiles_total = yt;
+        HIP_TRY(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_hdr, &h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the host copies are reused
+        set_launch(wg_per_cu);
+        return ENOAO_OK;
     }
 
     void release()
@@ -355,7 +379,7 @@ struct Runtime {
         HIP_TRY(prof_end(slot, st));
         if (eq == EULER2D) {
             HIP_TRY(prof_begin(PROF_Y1 + s - 1, st, slot));
-            HIP_TRY(launch_sweep_y(order, mode, record, params(r_in, r_out, -1), grid_y[mode], st));
+            HIP_TRY(launch_sweep_y(order, mode, record, yw, params(r_in, r_out, -1), grid_y[mode], st));
             HIP_TRY(prof_end(slot, st));
         }
         return ENOAO_OK;
@@ -364,7 +388,7 @@ struct Runtime {
     enoao_status rhs(hipStream_t s)
     {
         HIP_TRY(launch_sweep_x(eq, order, M_RHS, rec, params(0, -1, -1), grid_x[M_RHS], s));
-        if (eq == EULER2D) HIP_TRY(launch_sweep_y(order, M_RHS, rec, params(0, -1, -1), grid_y[M_RHS], s));
+        if (eq == EULER2D) HIP_TRY(launch_sweep_y(order, M_RHS, rec, yw, params(0, -1, -1), grid_y[M_RHS], s));
         return ENOAO_OK;
     }
 
@@ -571,6 +595,18 @@ enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved)
     if (workgroups_per_cu < 0 || workgroups_per_cu > 64 || reserved != 0) return ENOAO_EINVAL;
     g_wg_per_cu = workgroups_per_cu;
     return ENOAO_OK;
+}
+
+enoao_status enoao_plan_set_tiles(enoao_plan *plan, int32_t y_strip_columns, void *stream)
+{
+    if (!plan || (y_strip_columns != 0 && y_strip_columns != 4 && y_strip_columns != 8)) return ENOAO_EINVAL;
+    return plan->rt.set_ytiles(y_strip_columns ? y_strip_columns : YW_DEFAULT, (hipStream_t)stream);
+}
+
+enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, void *stream)
+{
+    if (!batch || (y_strip_columns != 0 && y_strip_columns != 4 && y_strip_columns != 8)) return ENOAO_EINVAL;
+    return batch->rt.set_ytiles(y_strip_columns ? y_strip_columns : YW_DEFAULT, (hipStream_t)stream);
 }
 
 enoao_status enoao_set_resident(int32_t enable)

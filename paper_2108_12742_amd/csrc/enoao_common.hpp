@@ -18,12 +18,12 @@ enum Bc : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
 constexpr int XW_FACES = 64;
 constexpr int XW_CELLS = XW_FACES - 1;
 constexpr int XW_SEGS = 4;
-// y-sweep tiles: YT_COLS columns x YT_CELLS cell rows per workgroup; each of
-// the 4 waves owns YT_COLS / 4 columns (YT_CELLS rows x YT_COLS / 4 columns =
-// 64 lanes, one new face per lane and tile).
-constexpr int YT_CELLS = 8;
-constexpr int YT_COLS = 32;
-static_assert(YT_CELLS * (YT_COLS / 4) == 64, "a y strip is one wave");
+// y-sweep tiles: each of the 4 waves of a workgroup owns a strip of w columns
+// (w = 4 or 8, chosen per plan or batch) and w * 64/w = 64 lanes; a tile is
+// 4w columns x 64/w cell rows.
+constexpr int YW_DEFAULT = 8;
+constexpr int yt_cells(int w) { return 64 / w; }
+constexpr int yt_cols(int w) { return 4 * w; }
 constexpr int BLOCK = 256;
 
 // per-field maxima kept per instance: three ring slots of 8 values each
@@ -61,8 +61,8 @@ struct Inst {
     double dx, dy;
     double adv;                 // advection speed
     int segs_per_row;           // ceil(nx / XW_CELLS)
-    int ytiles_per_row;         // ceil(ny / YT_CELLS) row segments per column group
-    int ycol_groups;            // ceil(nx / YT_COLS)
+    int ytiles_per_row;         // ceil(ny / yt_cells(w)) tiles per column group (w: y strip width)
+    int ycol_groups;            // ceil(nx / yt_cols(w))
     int pad;
     long long xtile0, ytile0;   // first x / y tile of this instance in the batch lists
     long long xtiles, ytiles;   // number of x / y tiles

@@ -561,19 +561,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D).  A workgroup tile is YT_COLS columns x YT_CELLS cell rows; each
-// wave owns a strip of YW_COLS columns (lane = YW_COLS * row + column) and
-// walks its tiles down the strip.  Successive tiles of a walk share node rows
+// y-sweep (2D).  A workgroup tile is 4 YW columns x 64/YW cell rows; each wave
+// owns a strip of YW columns (lane = YW * row + column) and walks its tiles
+// down the strip.  Successive tiles of a walk share node rows
 // and one face row, so a walk keeps a rolling buffer: after its first tile, a
 // tile copies the 2G-1 node rows it shares with the previous one, stages only
-// YT_CELLS new rows, reuses the previous tile's last face row, and computes
-// YT_CELLS new face rows -- one face and one staged node per lane and tile,
+// 64/YW new rows, reuses the previous tile's last face row, and computes
+// 64/YW new face rows -- one face and one staged node per lane and tile,
 // and every face of the walk is computed once.  Each wave exchanges data only
 // among its own lanes, so the tile loop has no workgroup barrier.  Momentum
 // components are exchanged on load so the x-direction formulas apply.  The
 // next tile's global operands are prefetched into registers.
-constexpr int YW_COLS = YT_COLS / (BLOCK / 64);  // columns per wave
-
 // a tile's position within its instance: tile row along y, column group
 struct YCur {
     int ty, cg;
@@ -596,38 +594,39 @@ __device__ __forceinline__ YCur y_advance(YCur c, int per_row)
 }
 
 // buffer rows of a walk: row b holds node row sy - G + b (sy = first cell row
-// of the tile); face row k (k = 0..YT_CELLS, the face below cell row sy + k)
+// of the tile); face row k (k = 0..64/YW, the face below cell row sy + k)
 // reads buffer rows k .. k + 2G - 1
-template <int G> struct YBuf {
-    static constexpr int ROWS = YT_CELLS + 2 * G;
-    static constexpr int NODES = ROWS * YW_COLS;           // staged by a walk's first tile
+template <int G, int YW> struct YBuf {
+    static constexpr int CELLS = yt_cells(YW), COLS = yt_cols(YW);
+    static constexpr int ROWS = CELLS + 2 * G;
+    static constexpr int NODES = ROWS * YW;                // staged by a walk's first tile
     static constexpr int J = (NODES + 63) / 64;            // nodes per lane then
     static constexpr int FRESH = 2 * G;                    // first row a later tile stages
 };
 
-template <int G> struct YPre {
-    double U[YBuf<G>::J][4];
+template <int G, int YW> struct YPre {
+    double U[YBuf<G, YW>::J][4];
     double lx[4];  // x-part of L (rhs) or of the stage combine at the lane's cell
 };
 
 // a lane's global operands of one y tile: the strip nodes it stages (all rows
 // for the first tile of a walk, rows FRESH.. for the others) and the x-part at
 // its cell
-template <int MODE, int G>
+template <int MODE, int G, int YW>
 __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c, bool first, int wv, int lane,
-                                           YPre<G> &pre)
+                                           YPre<G, YW> &pre)
 {
-    using B = YBuf<G>;
+    using B = YBuf<G, YW>;
     const int perm[4] = {0, 2, 1, 3};
     const int nx = v.nx, ny = v.ny;
     const long long plane = (long long)nx * ny;
-    const int sy = c.ty * YT_CELLS, cbase = c.cg * YT_COLS + wv * YW_COLS;
+    const int sy = c.ty * B::CELLS, cbase = c.cg * B::COLS + wv * YW;
     const int b0 = first ? 0 : B::FRESH;
 #pragma unroll
     for (int j = 0; j < B::J; ++j) {
-        const int i = b0 * YW_COLS + lane + 64 * j;
+        const int i = b0 * YW + lane + 64 * j;
         if (i < B::NODES && (first || j == 0)) {
-            const int r = i / YW_COLS, c0 = i % YW_COLS;
+            const int r = i / YW, c0 = i % YW;
             const int y = bc_map(sy - G + r, ny, v.bc);
             const int x = min(cbase + c0, nx - 1);
             const double *p = v.in + (long long)y * nx + x;
@@ -635,7 +634,7 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
             for (int q = 0; q < 4; ++q) pre.U[j][q] = p[perm[q] * plane];
         }
     }
-    const int fl = lane / YW_COLS, y = sy + fl, col = cbase + (lane % YW_COLS);
+    const int fl = lane / YW, y = sy + fl, col = cbase + (lane % YW);
     if (y < ny && col < nx) {
         const long long o = (long long)y * nx + col;
 #pragma unroll
@@ -644,16 +643,16 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
 }
 
 // one face of a y strip into the face buffer (and the selection record)
-template <int ORDER, bool REC, int MODE>
+template <int ORDER, bool REC, int MODE, int YW>
 __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KParams &P, const double *W, int QS,
                                        double *WF, int k, int cc, int col, int f)
 {
-    constexpr int NC = 4;
+    constexpr int NC = 4, CELLS = yt_cells(YW);
     double Fh[NC];
     int sel[2 * NC];
-    face_flux<EULER2D, ORDER>(W + k * YW_COLS + cc, QS, YW_COLS, v.al, P.gm1, P.delta, 0.0, Fh, sel);
+    face_flux<EULER2D, ORDER>(W + k * YW + cc, QS, YW, v.al, P.gm1, P.delta, 0.0, Fh, sel);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) WF[(q * (YT_CELLS + 1) + k) * YW_COLS + cc] = Fh[q];
+    for (int q = 0; q < NC; ++q) WF[(q * (CELLS + 1) + k) * YW + cc] = Fh[q];
     if (REC && v.sel && col < v.nx && f <= v.ny) {
         const long long xblock = (long long)v.ny * (v.nx + 1), yblock = (long long)(v.ny + 1) * v.nx;
         const long long ybase = (long long)NC * 2 * xblock;
@@ -666,15 +665,16 @@ __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KPara
     }
 }
 
-template <int ORDER, int MODE, bool REC>
+template <int ORDER, int MODE, bool REC, int YW>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_WAVES_PER_EU))) void sweep_y(KParams P)
 {
     constexpr int NC = 4, NQ = 12, NW = BLOCK / 64;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
-    using B = YBuf<G>;
+    using B = YBuf<G, YW>;
+    constexpr int CELLS = B::CELLS, COLS = B::COLS;
     constexpr int QS = B::NODES;  // a wave's LDS stride between quantities
     __shared__ double lds[NW * NQ * QS];
-    __shared__ double fh[NW * NC * (YT_CELLS + 1) * YW_COLS];
+    __shared__ double fh[NW * NC * (CELLS + 1) * YW];
     __shared__ double red[NW * 8];
     // epilogue operand of the tile (x-part), staged from the prefetch registers
     // so it is not held through the face arithmetic
@@ -683,15 +683,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int cc = lane % YW_COLS, fl = lane / YW_COLS;
+    const int cc = lane % YW, fl = lane / YW;
     double *W = lds + wv * NQ * QS;
-    double *WF = fh + wv * NC * (YT_CELLS + 1) * YW_COLS;
+    double *WF = fh + wv * NC * (CELLS + 1) * YW;
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->ytiles_total;
     const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
     Maxima<EULER2D> mx;
     mx.reset();
-    YPre<G> pre;
+    YPre<G, YW> pre;
 
     // one outer iteration per instance met by the workgroup's chunk (uniform
     // over the workgroup: the maxima flush is reached by all waves together)
@@ -708,19 +708,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
         const long long plane = (long long)nx * ny;
         YCur c = y_cursor(tile, v.t0, v.per_row);
         bool first = true;  // the tile starts a walk
-        y_prefetch<MODE, G>(v, c, true, wv, lane, pre);
+        y_prefetch<MODE, G, YW>(v, c, true, wv, lane, pre);
         for (; tile < tend; ++tile) {
             if (!first) {
-                // rows shared with the previous tile move up by YT_CELLS
-                for (int i = YW_COLS + lane; i < B::FRESH * YW_COLS; i += 64) {
+                // rows shared with the previous tile move up by 64/YW
+                for (int i = YW + lane; i < B::FRESH * YW; i += 64) {
 #pragma unroll
-                    for (int m = 0; m < NQ; ++m) W[m * QS + i] = W[m * QS + i + YT_CELLS * YW_COLS];
+                    for (int m = 0; m < NQ; ++m) W[m * QS + i] = W[m * QS + i + CELLS * YW];
                 }
                 wave_sync();  // the new rows below overwrite rows other lanes just read
             }
 #pragma unroll
             for (int j = 0; j < B::J; ++j) {
-                const int i = (first ? 0 : B::FRESH * YW_COLS) + lane + 64 * j;
+                const int i = (first ? 0 : B::FRESH * YW) + lane + 64 * j;
                 if (i < B::NODES && (first || j == 0)) {
                     double q[NQ];
                     node_quantities<EULER2D>(pre.U[j], P.gm1, q);
@@ -732,17 +732,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
             for (int q = 0; q < NC; ++q) elx[q * BLOCK + tid] = pre.lx[q];
             const YCur cn = y_advance(c, v.per_row);
             const bool next_first = cn.ty == 0;
-            if (tile + 1 < tend) y_prefetch<MODE, G>(v, cn, next_first, wv, lane, pre);
+            if (tile + 1 < tend) y_prefetch<MODE, G, YW>(v, cn, next_first, wv, lane, pre);
             wave_sync();
 
-            const int sy = c.ty * YT_CELLS;
-            const int col = c.cg * YT_COLS + wv * YW_COLS + cc;
+            const int sy = c.ty * CELLS;
+            const int col = c.cg * COLS + wv * YW + cc;
             // a walk's first tile also computes face row 0 (one call site, so the
             // face code is instantiated once)
 #pragma unroll 1
             for (int pass = first ? 0 : 1; pass < 2; ++pass) {
                 const int k = pass == 0 ? 0 : fl + 1;
-                if (pass == 1 || lane < YW_COLS) y_face<ORDER, REC, MODE>(v, P, W, QS, WF, k, cc, col, sy + k);
+                if (pass == 1 || lane < YW) y_face<ORDER, REC, MODE, YW>(v, P, W, QS, WF, k, cc, col, sy + k);
             }
             wave_sync();
 
@@ -752,8 +752,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
                 double Ly[NC];  // natural component order
 #pragma unroll
                 for (int q = 0; q < NC; ++q)
-                    Ly[perm[q]] = -(WF[(q * (YT_CELLS + 1) + fl + 1) * YW_COLS + cc] -
-                                    WF[(q * (YT_CELLS + 1) + fl) * YW_COLS + cc]) * v.idy;
+                    Ly[perm[q]] = -(WF[(q * (CELLS + 1) + fl + 1) * YW + cc] - WF[(q * (CELLS + 1) + fl) * YW + cc]) *
+                                  v.idy;
                 if constexpr (MODE == M_RHS) {
 #pragma unroll
                     for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = elx[q * BLOCK + tid] + Ly[q];
@@ -770,10 +770,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
             }
             wave_sync();
             // the last face row is the next tile's first
-            if (lane < YW_COLS) {
+            if (lane < YW) {
 #pragma unroll
-                for (int q = 0; q < NC; ++q)
-                    WF[(q * (YT_CELLS + 1)) * YW_COLS + lane] = WF[(q * (YT_CELLS + 1) + YT_CELLS) * YW_COLS + lane];
+                for (int q = 0; q < NC; ++q) WF[(q * (CELLS + 1)) * YW + lane] = WF[(q * (CELLS + 1) + CELLS) * YW + lane];
             }
             wave_sync();
             c = cn;
@@ -1084,19 +1083,23 @@ static KFn pick_x(int eq, int order, int mode, bool rec)
     if (eq == EULER1D) return pick_x_rec<EULER1D>(order, mode, rec);
     return pick_x_rec<EULER2D>(order, mode, rec);
 }
-template <int ORDER, bool REC> static KFn pick_y_mode(int mode)
+template <int ORDER, bool REC, int YW> static KFn pick_y_mode(int mode)
 {
     switch (mode) {
-    case M_RHS: return sweep_y<ORDER, M_RHS, REC>;
-    case M_S1: return sweep_y<ORDER, M_S1, REC>;
-    case M_S2: return sweep_y<ORDER, M_S2, REC>;
-    default: return sweep_y<ORDER, M_S3, REC>;
+    case M_RHS: return sweep_y<ORDER, M_RHS, REC, YW>;
+    case M_S1: return sweep_y<ORDER, M_S1, REC, YW>;
+    case M_S2: return sweep_y<ORDER, M_S2, REC, YW>;
+    default: return sweep_y<ORDER, M_S3, REC, YW>;
     }
 }
-static KFn pick_y(int order, int mode, bool rec)
+template <int YW> static KFn pick_y_w(int order, int mode, bool rec)
 {
-    if (order == 7) return rec ? pick_y_mode<7, true>(mode) : pick_y_mode<7, false>(mode);
-    return rec ? pick_y_mode<5, true>(mode) : pick_y_mode<5, false>(mode);
+    if (order == 7) return rec ? pick_y_mode<7, true, YW>(mode) : pick_y_mode<7, false, YW>(mode);
+    return rec ? pick_y_mode<5, true, YW>(mode) : pick_y_mode<5, false, YW>(mode);
+}
+static KFn pick_y(int order, int mode, bool rec, int yw)
+{
+    return yw == 4 ? pick_y_w<4>(order, mode, rec) : pick_y_w<8>(order, mode, rec);
 }
 static KFn pick_maxima(int eq)
 {
@@ -1126,9 +1129,9 @@ hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, const KParams &
     return launch(pick_x(eq, order, mode, rec), grid, BLOCK, p, s);
 }
 
-hipError_t launch_sweep_y(int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s)
+hipError_t launch_sweep_y(int order, int mode, bool rec, int yw, const KParams &p, int grid, hipStream_t s)
 {
-    return launch(pick_y(order, mode, rec), grid, BLOCK, p, s);
+    return launch(pick_y(order, mode, rec, yw), grid, BLOCK, p, s);
 }
 
 hipError_t launch_state_maxima(int eq, const KParams &p, int grid, hipStream_t s)
@@ -1193,7 +1196,7 @@ size_t resident_lds_limit()
 }
 
 int occupancy_x(int eq, int order, int mode, bool rec) { return occupancy(pick_x(eq, order, mode, rec)); }
-int occupancy_y(int order, int mode, bool rec) { return occupancy(pick_y(order, mode, rec)); }
+int occupancy_y(int order, int mode, bool rec, int yw) { return occupancy(pick_y(order, mode, rec, yw)); }
 int occupancy_maxima(int eq) { return occupancy(pick_maxima(eq)); }
 
 }  // namespace enoao

@@ -26,7 +26,9 @@ struct KParams {
 };
 
 hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s);
-hipError_t launch_sweep_y(int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s);
+// yw: columns per wave strip of the y tiles (4 or 8; the members' y tile lists
+// must have been built for the same width)
+hipError_t launch_sweep_y(int order, int mode, bool rec, int yw, const KParams &p, int grid, hipStream_t s);
 hipError_t launch_state_maxima(int eq, const KParams &p, int grid, hipStream_t s);
 hipError_t launch_reset_maxima(const KParams &p, int n_inst, hipStream_t s);
 hipError_t launch_step_control(int eq, const KParams &p, int n_inst, hipStream_t s);
@@ -41,7 +43,7 @@ size_t resident_lds_limit();
 
 // resident workgroups per CU of each kernel (for persistent grid sizes)
 int occupancy_x(int eq, int order, int mode, bool rec);
-int occupancy_y(int order, int mode, bool rec);
+int occupancy_y(int order, int mode, bool rec, int yw);
 int occupancy_maxima(int eq);
 
 }  // namespace enoao

@@ -102,6 +102,8 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int32), vp], st),
             "enoao_set_launch": ([ctypes.c_int32, ctypes.c_int32], st),
             "enoao_set_resident": ([ctypes.c_int32], st),
+            "enoao_plan_set_tiles": ([vp, ctypes.c_int32, vp], st),
+            "enoao_batch_set_tiles": ([vp, ctypes.c_int32, vp], st),
             "enoao_plan_set_launch": ([vp, ctypes.c_int32], st),
             "enoao_batch_set_launch": ([vp, ctypes.c_int32], st),
             "enoao_profile": ([vp, ctypes.c_int32], st),
@@ -318,6 +320,14 @@ def enoao_plan_set_launch(plan: Plan, workgroups_per_cu: int):
 
 def enoao_batch_set_launch(batch: Batch, workgroups_per_cu: int):
     _check(lib().enoao_batch_set_launch(batch.handle, int(workgroups_per_cu)), "enoao_batch_set_launch")
+
+
+def enoao_plan_set_tiles(plan: Plan, y_strip_columns: int, stream=None):
+    _check(lib().enoao_plan_set_tiles(plan.handle, int(y_strip_columns), _stream(stream)), "enoao_plan_set_tiles")
+
+
+def enoao_batch_set_tiles(batch: Batch, y_strip_columns: int, stream=None):
+    _check(lib().enoao_batch_set_tiles(batch.handle, int(y_strip_columns), _stream(stream)), "enoao_batch_set_tiles")
 
 
 class Pool:

@@ -1,11 +1,13 @@
 """Autotuner of the persistent launches.
 
-The sweeps run as persistent grids of (CUs x W) workgroups; W (workgroups, i.e.
-waves/4, resident per CU) trades latency hiding against the tail of the last
-tiles.  The tuner times a few steps of the caller's batch for each candidate W
+The sweeps run as persistent grids of (CUs x W) workgroups; W (workgroups of 4
+waves resident per CU) trades latency hiding against the tail of the last
+tiles.  In 2D the y-sweep tile width is a second knob: wave strips of 4 or 8
+columns (longer row segments per load against fewer staged halo rows).  The
+tuner times a few steps of the caller's batch for each candidate (W, width)
 and keeps the fastest per (equation, order, size bucket) in a JSON cache
 (ENOAO_TUNE_CACHE, default ~/.cache/enoao_tune.json).  Results do not depend on
-W, so tuning never changes answers.
+either knob, so tuning never changes answers.
 """
 from __future__ import annotations
 
@@ -14,7 +16,8 @@ import math
 import os
 import time
 
-CANDIDATES = (0, 1, 2, 3, 4, 6, 8)  # 0 = the occupancy the kernels' resources allow
+CANDIDATES = (0, 1, 2, 3, 4, 6, 8)  # W; 0 = the occupancy the kernels' resources allow
+Y_WIDTHS = (8, 4)                    # columns per wave strip of the y tiles (2D only)
 
 
 def cache_path():
@@ -47,29 +50,39 @@ def store(key, value):
 
 
 def tune_batch(problems, states, steps=4, candidates=CANDIDATES, cfl=0.3, use_cache=True):
-    """Best workgroups-per-CU for advancing `problems` (GPU tensors `states`, restored
-    afterwards) and the timing of every candidate (ms per step)."""
+    """Best launch shape for advancing `problems` (GPU tensors `states`, restored
+    afterwards): ((workgroups per CU, y strip columns), {"W/width": ms per step})."""
     import torch
     from . import enoao as E
     key = bucket_key(problems)
     if use_cache:
         hit = load_cache().get(key)
-        if hit is not None:
-            return hit["workgroups_per_cu"], hit["ms_per_step"]
+        if hit is not None and "y_strip_columns" in hit:
+            return (hit["workgroups_per_cu"], hit["y_strip_columns"]), hit["ms_per_step"]
+    widths = Y_WIDTHS if problems[0].equation == E.EULER2D else (Y_WIDTHS[0],)
     saved = [u.clone() for u in states]
     timing = {}
-    for w in candidates:
+
+    def run(w, yw, n):
         batch = E.enoao_batch_create(problems)
         E.enoao_batch_set_launch(batch, w)
+        E.enoao_batch_set_tiles(batch, yw)
         E.enoao_batch_step(batch, states, 1, cfl)  # warm-up: graph capture, first touch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        E.enoao_batch_step(batch, states, steps, cfl)
+        E.enoao_batch_step(batch, states, n, cfl)
         torch.cuda.synchronize()
-        timing[w] = (time.perf_counter() - t0) * 1e3 / steps
+        el = (time.perf_counter() - t0) * 1e3 / max(n, 1)
         E.enoao_batch_destroy(batch)
         for u, s in zip(states, saved):
             u.copy_(s)
+        return el
+
+    run(candidates[0], widths[0], 1)  # untimed: module loads and allocator first touches
+    for yw in widths:
+        for w in candidates:
+            timing[f"{w}/{yw}"] = run(w, yw, steps)
     best = min(timing, key=timing.get)
-    store(key, {"workgroups_per_cu": best, "ms_per_step": timing})
-    return best, timing
+    w, yw = (int(x) for x in best.split("/"))
+    store(key, {"workgroups_per_cu": w, "y_strip_columns": yw, "ms_per_step": timing})
+    return (w, yw), timing

@@ -214,8 +214,8 @@ def test_launch_shape_invariance():
 def test_multi_tile_walks(order):
     """A grid large enough that every workgroup walks several tiles of a strip (x
     segments and y tiles), with walks that start mid-column and cross column groups:
-    L with selections and one step match the oracle, for two persistent launch shapes
-    that cut the walks differently (bitwise equal to each other)."""
+    L with selections and one step match the oracle, for persistent launch shapes and
+    y tile widths that cut the walks differently (bitwise equal to each other)."""
     torch = PT.torch_cuda()
     E = _E()
     inst = W.quadrants(7, 640, 403)
@@ -227,21 +227,22 @@ def test_multi_tile_walks(order):
     ur = O.step(op, inst.u0, dt)
     steps = []
     try:
-        for wg in (1, 2):
+        for wg, yw in ((1, 8), (2, 8), (1, 4)):
             E.enoao_set_launch(wg)
             plan = E.enoao_plan_create(ep)
+            E.enoao_plan_set_tiles(plan, yw)
             u = PT.to_dev(torch, inst.u0)
             L = torch.empty_like(u)
             E.enoao_rhs(plan, u, L)
             sel = E.enoao_get_selection(plan)
             mask = PT.compare_selection(op, sel, selr, tier)
-            PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what=f"L (wg {wg})")
+            PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what=f"L (wg {wg}, y strips {yw})")
             E.enoao_step(plan, u, dt)
             steps.append(u.cpu())
-            PT.assert_close_by_component(steps[-1].numpy(), ur, mask=mask, what=f"u (wg {wg})")
+            PT.assert_close_by_component(steps[-1].numpy(), ur, mask=mask, what=f"u (wg {wg}, y strips {yw})")
     finally:
         E.enoao_set_launch(0)
-    assert torch.equal(steps[0], steps[1])
+    assert torch.equal(steps[0], steps[1]) and torch.equal(steps[0], steps[2])
 
 
 def test_nonphysical_state_reported():
