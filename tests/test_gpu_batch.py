@@ -131,3 +131,30 @@ def test_server_on_gpu_pool():
         np.testing.assert_array_equal(r.result, ref)
     st = S.latency_stats(reqs)
     assert st["count"] == len(insts)
+
+
+def test_autotuner_restores_states_and_picks_a_candidate(tmp_path, monkeypatch):
+    """The tuner times every (workgroups per CU, y strip width) candidate on the caller's
+    batch, leaves the states as they were, and its choice gives the same results."""
+    torch = PT.torch_cuda()
+    E = _E()
+    from paper_2108_12742_amd import tune as T
+    monkeypatch.setenv("ENOAO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    insts = [W.quadrants(1, 80, 70), W.quadrants(3, 50, 90)]
+    probs = [E.problem_from_instance(i) for i in insts]
+    us = [PT.to_dev(torch, i.u0) for i in insts]
+    (w, yw), timing = T.tune_batch(probs, us, steps=2, candidates=(0, 2))
+    assert set(timing) == {"0/8", "2/8", "0/4", "2/4"} and (w, yw) in {(0, 8), (2, 8), (0, 4), (2, 4)}
+    for u, i in zip(us, insts):
+        assert torch.equal(u.cpu(), torch.from_numpy(i.u0))
+    assert T.tune_batch(probs, us, steps=2, candidates=(0, 2))[0] == (w, yw)  # cached
+    outs = []
+    for shape in ((w, yw), (0, 8)):
+        b = E.enoao_batch_create(probs)
+        E.enoao_batch_set_launch(b, shape[0])
+        E.enoao_batch_set_tiles(b, shape[1])
+        vs = [PT.to_dev(torch, i.u0) for i in insts]
+        E.enoao_batch_step(b, vs, 3, 0.3)
+        outs.append([v.cpu() for v in vs])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
