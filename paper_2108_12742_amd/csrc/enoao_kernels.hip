@@ -41,6 +41,15 @@ __device__ __forceinline__ int bc_map(int k, int n, int bc)
     return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
 
+// Device-memory pointers.  The state and control pointers reach a kernel through
+// the instance table in memory, so the compiler cannot tell that they address
+// global memory and would emit flat instructions for them.  Flat loads and
+// stores count against the LDS counter too, so every wait for an LDS read would
+// also wait for the next tile's global prefetch in flight (and for the previous
+// tile's stores).  Typed as global they compile to global instructions.
+#define GMEM __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GMEM T *gmem(T *p) { return (GMEM T *)p; }
+
 __device__ __forceinline__ double as_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
 
@@ -98,7 +107,7 @@ template <int EQ> struct Maxima {
         }
     }
     // workgroup reduction, then one atomic per value into the instance's slot
-    __device__ void flush(unsigned long long *amax, Ctrl *ctrl, int slot, double *red)
+    __device__ void flush(GMEM unsigned long long *amax, GMEM Ctrl *ctrl, int slot, double *red)
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -121,9 +130,11 @@ template <int EQ> struct Maxima {
             double x = red[threadIdx.x];
             for (int w = 1; w < BLOCK / 64; ++w) x = fmax(x, red[w * 8 + threadIdx.x]);
             if (threadIdx.x < NV) {
-                if (slot >= 0) atomicMax(&amax[slot * AMAX_VALS + threadIdx.x], as_bits(x));
+                if (slot >= 0)
+                    __hip_atomic_fetch_max(&amax[slot * AMAX_VALS + threadIdx.x], as_bits(x), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             } else if (x != 0.0) {
-                atomicOr(&ctrl->status, 1);
+                __hip_atomic_fetch_or(&ctrl->status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         __syncthreads();
@@ -301,13 +312,13 @@ template <int EQ, int MODE> struct View {
     long long t0, t1;      // the instance's tiles in the batch list
     int k, nx, ny, per_row, bc;
     int active;            // the instance is still stepping
-    const double *in;      // stage input
-    double *out;           // stage output
-    const double *base;    // u^n (stages 2 and 3)
-    double *lx;            // x-part of L (2D) / L (rhs)
-    uint8_t *sel;
-    unsigned long long *amax;
-    Ctrl *ctrl;
+    const GMEM double *in;    // stage input
+    GMEM double *out;         // stage output
+    const GMEM double *base;  // u^n (stages 2 and 3)
+    GMEM double *lx;          // x-part of L (2D) / L (rhs)
+    GMEM uint8_t *sel;
+    GMEM unsigned long long *amax;
+    GMEM Ctrl *ctrl;
     double idx, idy, adv, dt;
     double al[NC];
 };
@@ -337,23 +348,22 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
     v.ny = uniform(I.ny);
     v.per_row = uniform(Y ? I.ytiles_per_row : I.segs_per_row);
     v.bc = uniform(Y ? I.bcy : I.bcx);
-    Ctrl *ctrl = uniform(I.ctrl);
-    v.ctrl = ctrl;
-    v.active = uniform(ctrl->done) == 0;
-    v.dt = uniform(ctrl->dt);
-    v.in = uniform(MODE == M_S2 ? I.w1 : (MODE == M_S3 ? I.w2 : I.u));
-    v.out = uniform(MODE == M_S1 ? I.w1 : (MODE == M_S2 ? I.w2 : I.u));
-    v.base = uniform(I.u);
-    v.lx = uniform(I.lx);
-    v.sel = uniform(I.sel);
-    v.amax = uniform(I.amax);
+    v.ctrl = gmem(uniform(I.ctrl));
+    v.active = uniform(v.ctrl->done) == 0;
+    v.dt = uniform(v.ctrl->dt);
+    v.in = gmem(uniform(MODE == M_S2 ? I.w1 : (MODE == M_S3 ? I.w2 : I.u)));
+    v.out = gmem(uniform(MODE == M_S1 ? I.w1 : (MODE == M_S2 ? I.w2 : I.u)));
+    v.base = gmem(uniform(I.u));
+    v.lx = gmem(uniform(I.lx));
+    v.sel = gmem(uniform(I.sel));
+    v.amax = gmem(uniform(I.amax));
     v.idx = 1.0 / uniform(I.dx);
     v.idy = 1.0 / uniform(I.dy);
     v.adv = uniform(I.adv);
     if constexpr (EQ == ADVECTION) {
         v.al[0] = fabs(v.adv);
     } else {
-        const unsigned long long *a = v.amax + P.r_in * AMAX_VALS + (Y ? 3 : 0);
+        const GMEM unsigned long long *a = v.amax + P.r_in * AMAX_VALS + (Y ? 3 : 0);
         const double m0 = uniform(as_double(a[0])), m1 = uniform(as_double(a[1])), m2 = uniform(as_double(a[2]));
         v.al[0] = m0;
         v.al[1] = m1;
@@ -422,7 +432,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
     if (c.row >= v.ny) return;
     const int nx = v.nx, sx = c.segx * XW_CELLS;
     const long long plane = (long long)nx * v.ny;
-    const double *rowp = v.in + (long long)c.row * nx;
+    const GMEM double *rowp = v.in + (long long)c.row * nx;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int i = lane + 64 * j;
@@ -435,7 +445,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
     if constexpr (MODE == M_S2 || MODE == M_S3) {
         const int x = sx + lane;
         if (lane < XW_CELLS && x < nx) {
-            const double *b = v.base + (long long)c.row * nx + x;
+            const GMEM double *b = v.base + (long long)c.row * nx + x;
 #pragma unroll
             for (int q = 0; q < NC; ++q) pre.base[q] = b[q * plane];
         }
@@ -629,7 +639,7 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
             const int r = i / YW, c0 = i % YW;
             const int y = bc_map(sy - G + r, ny, v.bc);
             const int x = min(cbase + c0, nx - 1);
-            const double *p = v.in + (long long)y * nx + x;
+            const GMEM double *p = v.in + (long long)y * nx + x;
 #pragma unroll
             for (int q = 0; q < 4; ++q) pre.U[j][q] = p[perm[q] * plane];
         }
@@ -800,12 +810,12 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
     long long end = -1;
     int nx = 0, ny = 0, spr = 1;
     long long first = 0;
-    const double *u = nullptr;
+    const GMEM double *u = nullptr;
     double idx = 0.0, idy = 0.0;
     for (long long tile = t0; tile < t1; ++tile) {
         if (tile >= end) {
             const int k = find_inst<true>(P.inst, n_inst, tile);
-            if (cur >= 0) mx.flush(P.inst[cur].amax, P.inst[cur].ctrl, P.r_out, red);
+            if (cur >= 0) mx.flush(gmem(P.inst[cur].amax), gmem(P.inst[cur].ctrl), P.r_out, red);
             cur = k;
             const Inst &I = P.inst[k];
             first = I.xtile0;
@@ -813,7 +823,7 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
             nx = I.nx;
             ny = I.ny;
             spr = I.segs_per_row;
-            u = I.u;
+            u = gmem(I.u);
             idx = 1.0 / I.dx;
             idy = 1.0 / I.dy;
         }
@@ -827,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
             mx.add(U, P.gamma, idx, idy);
         }
     }
-    if (cur >= 0) mx.flush(P.inst[cur].amax, P.inst[cur].ctrl, P.r_out, red);
+    if (cur >= 0) mx.flush(gmem(P.inst[cur].amax), gmem(P.inst[cur].ctrl), P.r_out, red);
 }
 
 // zero all maxima slots and the status of every instance
@@ -837,7 +847,7 @@ __global__ void reset_maxima(KParams P)
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n * AMAX_SLOTS * AMAX_VALS;
          k += gridDim.x * blockDim.x) {
         const int i = k / (AMAX_SLOTS * AMAX_VALS), j = k % (AMAX_SLOTS * AMAX_VALS);
-        P.inst[i].amax[j] = 0ull;
+        gmem(P.inst[i].amax)[j] = 0ull;
     }
 }
 
@@ -999,7 +1009,7 @@ __global__ __launch_bounds__(RES_BLOCK) void resident_1d(KParams P, int nsteps)
     double *q = fx + NC * (n + 1);
     double *red = q + NQ * QS;
     double *cm = red + RES_WAVES * 8;
-    double *ug = I.u;
+    GMEM double *ug = gmem(I.u);
     for (int i = tid; i < NC * n; i += RES_BLOCK) un[i] = ug[i];
     if (tid == 0) C = *I.ctrl;
     __syncthreads();
@@ -1180,7 +1190,8 @@ hipError_t launch_resident(int eq, int order, const KParams &p, int n_inst, int 
     if (eq == EULER2D) return hipErrorInvalidValue;
     const KFn2 fn = pick_resident(eq, order);
     // dynamic LDS beyond the default limit must be allowed per kernel
-    hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     KParams copy = p;
     void *args[] = {&copy, &nsteps};
     return hipLaunchKernel((const void *)fn, dim3(n_inst), dim3(RES_BLOCK), args, lds, s);
