@@ -35,13 +35,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Floating-point contraction is off from here on (the kernels include this
+// header first): a multiply and an add are fused only where an fma() says so.
+// Every inlined copy of the same arithmetic then rounds alike, which the
+// kernels rely on: a value formed on two code paths, or in two kernels, agrees
+// bit for bit.
+#pragma clang fp contract(off)
+
 namespace enoao {
 
-// Wave-uniform early exit: when every lane of the wave has IS <= delta for the
-// highest-priority candidate on both sides of a field, that candidate is every
-// lane's choice (first principle), so the selection logic is skipped.  Each
-// lane's result is bitwise the same as on the full path (same indicators, same
-// candidate flux); only the work differs.
+// Wave-uniform shortcut: when every lane of the wave has IS <= delta for the
+// top candidate on both sides of a field, that candidate is every lane's choice
+// (first principle) and the field's value is the top candidate's conserved-
+// variable form alone; otherwise the field takes the full selection.  A lane's
+// result does not depend on the path: the full selection uses the same top
+// indicator and, when it picks the top candidate on both sides, the same value.
+// 0: always the full selection (checks that property).
 #ifndef ENOAO_EARLY_EXIT
 #define ENOAO_EARLY_EXIT 1
 #endif
@@ -90,22 +99,88 @@ __device__ __forceinline__ double select_candidate(const double (&is)[K], const 
 template <int ORDER> struct Recon {
     static constexpr int H = ReconTraits<ORDER>::H, K = ReconTraits<ORDER>::K, W = 2 * H + 1;
     // One side of one field: the chosen candidate's value at x_{j+1/2} and its
-    // index.  Candidate fluxes (table of numerical fluxes) in Newton form:
+    // index, by the two principles.  The top candidate's indicator is_top is
+    // given (it comes from the conserved-variable form below, so every path
+    // takes the same decision on it).  Candidate values (the table of
+    // numerical fluxes) in Newton form:
     //   order 5 (f_j = f[3]):  h0 = f_j, h1 = h0 + a3/2, h2 = h1 - b2/6,
     //     h3 = h2 - c1/12, h4 = h2 - c2/12, h5 = h3 - d1/20;
     //   order 7 (f_j = f[4]): the same on the shifted table, then
     //     h6 = h5 + e1/60, h7 = h5 + e2/60, h8 = h6 + g1/105,
     // (a, b, c, ... the 1st, 2nd, 3rd ... undivided differences, index = first
-    // node).  The wave skips the other indicators and the selection when every
-    // lane's top candidate has IS <= delta (then it is every lane's choice).
-    // The top candidate's flux and indicator only (the first step of run()).
+    // node).
+    __device__ __forceinline__ static double select(const double (&f)[W], double delta, double is_top, int &sel)
+    {
+        if constexpr (ORDER == 5) {
+            const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
+            const double a3 = f[4] - f[3], a4 = f[5] - f[4], a5 = f[6] - f[5];
+            const double b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3;
+            const double c0 = b1 - (a1 - a0), c1 = b2 - b1, c2 = b3 - b2, c3 = (a5 - a4) - b3;
+            const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
+            double h[6];
+            h[0] = f[3];
+            h[1] = fma(0.5, a3, h[0]);
+            h[2] = fma(-1.0 / 6.0, b2, h[1]);
+            h[3] = fma(-1.0 / 12.0, c1, h[2]);
+            h[4] = fma(-1.0 / 12.0, c2, h[2]);
+            h[5] = fma(-1.0 / 20.0, d1, h[3]);
+            const double ad1 = fabs(d1);
+            double is[6];
+            is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
+            is[1] = fmin(fabs(b2), fabs(b3));                              // S_j^{j+1}
+            is[2] = fmin(fabs(c1), fabs(c2));                              // S_{j-1}^{j+1}
+            is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
+            is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
+            is[5] = is_top;                                                // S_{j-2}^{j+2}
+            return select_candidate<6>(is, h, delta, sel);
+        } else {
+            double a[8], b[7], c[6], d[5], e[4], g[3];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = f[i + 1] - f[i];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) b[i] = a[i + 1] - a[i];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) c[i] = b[i + 1] - b[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) d[i] = c[i + 1] - c[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[i] = d[i + 1] - d[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) g[i] = e[i + 1] - e[i];
+            double h[9];
+            h[0] = f[4];
+            h[1] = fma(0.5, a[4], h[0]);
+            h[2] = fma(-1.0 / 6.0, b[3], h[1]);
+            h[3] = fma(-1.0 / 12.0, c[2], h[2]);
+            h[4] = fma(-1.0 / 12.0, c[3], h[2]);
+            h[5] = fma(-1.0 / 20.0, d[2], h[3]);
+            h[6] = fma(1.0 / 60.0, e[1], h[5]);
+            h[7] = fma(1.0 / 60.0, e[2], h[5]);
+            h[8] = fma(1.0 / 105.0, g[1], h[6]);
+            const double ad2 = fabs(d[2]), ag1 = fabs(g[1]);
+            double is[9];
+            is[0] = 0.5 * fmin(fabs(a[3]) + fabs(a[2]), fabs(a[4]) + fabs(a[5])); // S_j^j
+            is[1] = fmin(fabs(b[3]), fabs(b[4]));                                  // S_j^{j+1}
+            is[2] = fmin(fabs(c[2]), fabs(c[3]));                                  // S_{j-1}^{j+1}
+            is[3] = fmin(fabs(d[1]), ad2);                                         // S_{j-2}^{j+1}
+            is[4] = fmin(ad2, fabs(d[3]));                                         // S_{j-1}^{j+2}
+            is[5] = fmin(fabs(e[1]), fabs(e[2]));                                  // S_{j-2}^{j+2}
+            is[6] = fmin(fabs(g[0]), ag1);                                         // S_{j-3}^{j+2}
+            is[7] = fmin(ag1, fabs(g[2]));                                         // S_{j-2}^{j+3}
+            is[8] = is_top;                                                        // S_{j-3}^{j+3}
+            return select_candidate<9>(is, h, delta, sel);
+        }
+    }
+
+    // The top candidate's value and indicator from the window's own difference
+    // table (the same operations as the corresponding entries in select()).
     __device__ __forceinline__ static double top(const double (&f)[W], double &is_top)
     {
         if constexpr (ORDER == 5) {
             const double a1 = f[2] - f[1], a2 = f[3] - f[2], a3 = f[4] - f[3], a0 = f[1] - f[0];
             const double a4 = f[5] - f[4], a5 = f[6] - f[5];
-            const double b0 = a1 - a0, b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3, b4 = a5 - a4;
-            const double c0 = b1 - b0, c1 = b2 - b1, c2 = b3 - b2, c3 = b4 - b3;
+            const double b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3;
+            const double c0 = b1 - (a1 - a0), c1 = b2 - b1, c2 = b3 - b2, c3 = (a5 - a4) - b3;
             const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
             is_top = fmin(fabs(d1 - d0), fabs(d2 - d1));
             const double h1 = fma(0.5, a3, f[3]);
@@ -136,79 +211,65 @@ template <int ORDER> struct Recon {
         }
     }
 
+    // One side by the window form: the top candidate's indicator from the
+    // window; when it is within delta on every lane the selection is skipped.
     __device__ __forceinline__ static double run(const double (&f)[W], double delta, int &sel)
     {
+        double is_top;
+        const double ht = top(f, is_top);
+        if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
+            sel = K - 1;
+            return ht;
+        }
+        return select(f, delta, is_top, sel);
+    }
+};
+
+// The top candidate (S_{j-2}^{j+2}, order 7: S_{j-3}^{j+3}) in conserved
+// variables.  Its indicator and the sum of its values on the two sides are
+// linear in the window, and so is the characteristic projection, so they can be
+// formed on U and F once per node or face and projected afterwards.  Over a
+// face's 2G nodes x_0 .. x_{2H+1}:
+//   * D_p = (2H-1)-th undivided difference starting at node p:
+//       order 5: (x5 - x0) + 5 (x1 - x4) + 10 (x3 - x2)            (shifted by p)
+//       order 7: (x7 - x0) + 7 (x1 - x6) + 21 (x5 - x2) + 35 (x3 - x4)
+//     plus side (window nodes 0 .. 2H):      IS_top = min(|D_0 g+|, |D_1 g+|);
+//     minus side (mirror, nodes 2H+1 .. 1):  IS_top = min(|D_2 g-|, |D_1 g-|)
+//     (reversing a window only flips the sign of an odd difference).
+//   * plus value + minus value = S F + alpha kappa D_1 U, with the symmetric
+//     stencil S in terms of the pair sums s_k = x_{H-k} + x_{H+1+k}:
+//       order 5: S = s0 - 7/30 (s1 - s0) + 1/30 (s2 - s1),                   kappa = -1/30
+//       order 7: S = s0 - 113/420 (s1 - s0) + 13/210 (s2 - s1) - 1/140 (s3 - s2), kappa = 1/140
+//     (one-sided values 2,-13,47,27,-3 / 60 and -3,25,-101,319,214,-38,4 / 420
+//     of the Newton forms above; their mirror difference is kappa D_1).
+// Constant data give exactly zero differences and corrections.
+template <int ORDER> struct TopStencil {
+    static constexpr int H = ReconTraits<ORDER>::H;
+    static constexpr double kappa = ORDER == 5 ? -1.0 / 30.0 : 1.0 / 140.0;
+    // D starting at x[0], nodes x[0], x[ns], ...
+    __device__ __forceinline__ static double diff(const double *x, int ns)
+    {
         if constexpr (ORDER == 5) {
-            const double a0 = f[1] - f[0], a1 = f[2] - f[1], a2 = f[3] - f[2];
-            const double a3 = f[4] - f[3], a4 = f[5] - f[4], a5 = f[6] - f[5];
-            const double b0 = a1 - a0, b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3, b4 = a5 - a4;
-            const double c0 = b1 - b0, c1 = b2 - b1, c2 = b3 - b2, c3 = b4 - b3;
-            const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
-            const double e0 = d1 - d0, e1 = d2 - d1;
-            const double is_top = fmin(fabs(e0), fabs(e1));  // S_{j-2}^{j+2}
-            double h[6];
-            h[0] = f[3];
-            h[1] = fma(0.5, a3, h[0]);
-            h[2] = fma(-1.0 / 6.0, b2, h[1]);
-            h[3] = fma(-1.0 / 12.0, c1, h[2]);
-            h[5] = fma(-1.0 / 20.0, d1, h[3]);
-            if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
-                sel = 5;
-                return h[5];
-            }
-            h[4] = fma(-1.0 / 12.0, c2, h[2]);
-            const double ad1 = fabs(d1);
-            double is[6];
-            is[0] = 0.5 * fmin(fabs(a2) + fabs(a1), fabs(a3) + fabs(a4)); // S_j^j (averaged form)
-            is[1] = fmin(fabs(b2), fabs(b3));                              // S_j^{j+1}
-            is[2] = fmin(fabs(c1), fabs(c2));                              // S_{j-1}^{j+1}
-            is[3] = fmin(fabs(d0), ad1);                                   // S_{j-2}^{j+1}
-            is[4] = fmin(ad1, fabs(d2));                                   // S_{j-1}^{j+2}
-            is[5] = is_top;
-            return select_candidate<6>(is, h, delta, sel);
+            const double r = fma(5.0, x[ns] - x[4 * ns], x[5 * ns] - x[0]);
+            return fma(10.0, x[3 * ns] - x[2 * ns], r);
         } else {
-            double a[8], b[7], c[6], d[5], e[4], g[3], q[2];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = f[i + 1] - f[i];
-#pragma unroll
-            for (int i = 0; i < 7; ++i) b[i] = a[i + 1] - a[i];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) c[i] = b[i + 1] - b[i];
-#pragma unroll
-            for (int i = 0; i < 5; ++i) d[i] = c[i + 1] - c[i];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) e[i] = d[i + 1] - d[i];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) g[i] = e[i + 1] - e[i];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) q[i] = g[i + 1] - g[i];
-            const double is_top = fmin(fabs(q[0]), fabs(q[1]));  // S_{j-3}^{j+3}
-            double h[9];
-            h[0] = f[4];
-            h[1] = fma(0.5, a[4], h[0]);
-            h[2] = fma(-1.0 / 6.0, b[3], h[1]);
-            h[3] = fma(-1.0 / 12.0, c[2], h[2]);
-            h[5] = fma(-1.0 / 20.0, d[2], h[3]);
-            h[6] = fma(1.0 / 60.0, e[1], h[5]);
-            h[8] = fma(1.0 / 105.0, g[1], h[6]);
-            if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
-                sel = 8;
-                return h[8];
-            }
-            h[4] = fma(-1.0 / 12.0, c[3], h[2]);
-            h[7] = fma(1.0 / 60.0, e[2], h[5]);
-            const double ad2 = fabs(d[2]), ag1 = fabs(g[1]);
-            double is[9];
-            is[0] = 0.5 * fmin(fabs(a[3]) + fabs(a[2]), fabs(a[4]) + fabs(a[5])); // S_j^j
-            is[1] = fmin(fabs(b[3]), fabs(b[4]));                                  // S_j^{j+1}
-            is[2] = fmin(fabs(c[2]), fabs(c[3]));                                  // S_{j-1}^{j+1}
-            is[3] = fmin(fabs(d[1]), ad2);                                         // S_{j-2}^{j+1}
-            is[4] = fmin(ad2, fabs(d[3]));                                         // S_{j-1}^{j+2}
-            is[5] = fmin(fabs(e[1]), fabs(e[2]));                                  // S_{j-2}^{j+2}
-            is[6] = fmin(fabs(g[0]), ag1);                                         // S_{j-3}^{j+2}
-            is[7] = fmin(ag1, fabs(g[2]));                                         // S_{j-2}^{j+3}
-            is[8] = is_top;
-            return select_candidate<9>(is, h, delta, sel);
+            double r = fma(7.0, x[ns] - x[6 * ns], x[7 * ns] - x[0]);
+            r = fma(21.0, x[5 * ns] - x[2 * ns], r);
+            return fma(35.0, x[3 * ns] - x[4 * ns], r);
+        }
+    }
+    // S over a face's nodes, x[0] = node 0
+    __device__ __forceinline__ static double sym(const double *x, int ns)
+    {
+        const double s0 = x[H * ns] + x[(H + 1) * ns], s1 = x[(H - 1) * ns] + x[(H + 2) * ns];
+        const double s2 = x[(H - 2) * ns] + x[(H + 3) * ns];
+        if constexpr (ORDER == 5) {
+            return fma(1.0 / 30.0, s2 - s1, fma(-7.0 / 30.0, s1 - s0, s0));
+        } else {
+            const double s3 = x[(H - 3) * ns] + x[(H + 4) * ns];
+            double r = fma(-113.0 / 420.0, s1 - s0, s0);
+            r = fma(13.0 / 210.0, s2 - s1, r);
+            return fma(-1.0 / 140.0, s3 - s2, r);
         }
     }
 };
@@ -250,7 +311,7 @@ __device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>
         const double rho = U[0], m = U[1], E = U[2];
         const double ir = rcp_nr(rho);
         const double u = m * ir;
-        const double p = gm1 * (E - 0.5 * rho * (u * u));
+        const double p = gm1 * fma(-0.5 * rho, u * u, E);
         q[0] = rho; q[1] = m; q[2] = E;
         q[3] = m; q[4] = fma(m, u, p); q[5] = (E + p) * u;
         q[6] = sqrt(rho); q[7] = u; q[8] = (E + p) * ir;
@@ -259,7 +320,7 @@ __device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>
         const double rho = U[0], m = U[1], n = U[2], E = U[3];
         const double ir = rcp_nr(rho);
         const double u = m * ir, v = n * ir;
-        const double p = gm1 * (E - 0.5 * rho * fma(u, u, v * v));
+        const double p = gm1 * fma(-0.5 * rho, fma(u, u, v * v), E);
         q[0] = rho; q[1] = m; q[2] = n; q[3] = E;
         q[4] = m; q[5] = fma(m, u, p); q[6] = m * v; q[7] = (E + p) * u;
         q[8] = sqrt(rho); q[9] = u; q[10] = v; q[11] = (E + p) * ir;
@@ -305,18 +366,18 @@ __device__ __forceinline__ void project(const RoeState &r, const double (&x)[NC]
     if constexpr (NC == 4) {
         const double t = fma(r.u, x[1], fma(r.v, x[2], -x[3]));
         const double A = fma(r.b2, x[0], -r.b1 * t);
-        const double B = fma(r.u, x[0], -x[1]) * r.ic;
-        w[0] = A + B;
+        const double Bc = fma(r.u, x[0], -x[1]);  // B c
+        w[0] = fma(Bc, r.ic, A);
         w[1] = x[0] - A;
         w[2] = fma(-r.v, x[0], x[2]);
-        w[3] = A - B;
+        w[3] = fma(-Bc, r.ic, A);
     } else {
         const double t = fma(r.u, x[1], -x[2]);
         const double A = fma(r.b2, x[0], -r.b1 * t);
-        const double B = fma(r.u, x[0], -x[1]) * r.ic;
-        w[0] = A + B;
+        const double Bc = fma(r.u, x[0], -x[1]);  // B c
+        w[0] = fma(Bc, r.ic, A);
         w[1] = x[0] - A;
-        w[2] = A - B;
+        w[2] = fma(-Bc, r.ic, A);
     }
 }
 

@@ -26,9 +26,6 @@
 #ifndef ENOAO_NODE_SCHED
 #define ENOAO_NODE_SCHED 1     // stencil nodes between scheduling fences (0: none; bounds register use)
 #endif
-#ifndef ENOAO_JOINT_EXIT
-#define ENOAO_JOINT_EXIT 1     // one wave-uniform top-candidate shortcut per field pass
-#endif
 
 namespace enoao {
 
@@ -49,6 +46,17 @@ __device__ __forceinline__ int bc_map(int k, int n, int bc)
 // tile's stores).  Typed as global they compile to global instructions.
 #define GMEM __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ GMEM T *gmem(T *p) { return (GMEM T *)p; }
+
+// wave-uniform copy of a value (scalar registers)
+template <typename T> __device__ __forceinline__ T uniform(T x)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit multiple");
+    union { T v; int w[sizeof(T) / 4]; } a;
+    a.v = x;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) a.w[i] = __builtin_amdgcn_readfirstlane(a.w[i]);
+    return a.v;
+}
 
 __device__ __forceinline__ double as_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 __device__ __forceinline__ unsigned long long as_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
@@ -86,7 +94,7 @@ template <int EQ> struct Maxima {
             bad |= !(U[0] == U[0]);
         } else if constexpr (EQ == EULER1D) {
             const double rho = U[0], ir = rcp_nr(rho), u = U[1] * ir;
-            const double p = (gamma - 1.0) * (U[2] - 0.5 * rho * (u * u));
+            const double p = (gamma - 1.0) * fma(-0.5 * rho, u * u, U[2]);
             const double c = sqrt(gamma * p * ir);
             bad |= !(rho > 0.0 && p > 0.0);
             v[0] = fmax(v[0], fabs(u - c));
@@ -94,7 +102,7 @@ template <int EQ> struct Maxima {
             v[2] = fmax(v[2], fabs(u + c));
         } else {
             const double rho = U[0], ir = rcp_nr(rho), u = U[1] * ir, w = U[2] * ir;
-            const double p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + w * w));
+            const double p = (gamma - 1.0) * fma(-0.5 * rho, fma(u, u, w * w), U[3]);
             const double c = sqrt(gamma * p * ir);
             bad |= !(rho > 0.0 && p > 0.0);
             v[0] = fmax(v[0], fabs(u - c));
@@ -146,19 +154,168 @@ template <int EQ> struct Maxima {
 // One face: window node t (t = 0 .. 2G-1) of face j+1/2 is node j-H+t; the
 // plus side reads nodes j-H .. j+H, the minus side the mirror j+1+H .. j+1-H.
 
-// Characteristic fields F0 (and F1 >= 0) of an Euler face: project U and F of
-// every stencil node (the compiler drops the rows not used by these fields),
-// split, reconstruct both sides.  Taking the fields in two passes halves the
-// live window registers.
-template <int NC, int ORDER, int F0, int F1>
-__device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const RoeState &r, const double *al,
-                                           double delta, double (&wh)[NC], int (&sel)[2 * NC])
+// Top candidate of every field of an Euler face in conserved-variable form
+// (TopStencil): the projected differences D_0, D_1, D_2 of U and F and the
+// projected symmetric stencil of F give both sides' top indicators and the sum
+// of both sides' top values, on the window scale 2 field_scale (the windows
+// below are g = P F +/- alpha P U with the scaled projection P).
+template <int NC> struct TopForm {
+    double is[NC][2];  // IS_top of the plus and minus side
+    double hs[NC];     // plus + minus top value
+};
+
+// Staged differences (DSTAGED): d0 points at D_0 of quantity 0 of the face,
+// quantities (U then F) dqs apart, positions dns apart.  Otherwise they are
+// formed here from the window nodes.
+template <int NC, int ORDER, bool DSTAGED>
+__device__ __forceinline__ void top_form(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
+                                         const RoeState &r, const double *al, double delta, TopForm<NC> &tf)
 {
-    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1;
+    using T = TopStencil<ORDER>;
+    constexpr int G = ReconTraits<ORDER>::H + 1;
+    double dv[3][2][NC], sf[NC];
+    if constexpr (DSTAGED) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) dv[p][v][c] = d0[(v * NC + c) * dqs + p * dns];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sf[c] = T::sym(w0 + (NC + c) * qs, ns);
+    } else {
+        // one quantity's window at a time (bounds the live registers)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double xw[2 * G];
+#pragma unroll
+                for (int t = 0; t < 2 * G; ++t) xw[t] = w0[(v * NC + c) * qs + t * ns];
+#pragma unroll
+                for (int p = 0; p < 3; ++p) dv[p][v][c] = T::diff(xw + p, 1);
+                if (v == 1) sf[c] = T::sym(xw, 1);
+                if (ENOAO_NODE_SCHED > 0 && c % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    double pd[3][2][NC], psf[NC];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) project<NC>(r, dv[p][v], pd[p][v]);
+    project<NC>(r, sf, psf);
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        const double a = al[s];
+        tf.is[s][0] = fmin(fabs(fma(a, pd[0][0][s], pd[0][1][s])), fabs(fma(a, pd[1][0][s], pd[1][1][s])));
+        tf.is[s][1] = fmin(fabs(fma(-a, pd[2][0][s], pd[2][1][s])), fabs(fma(-a, pd[1][0][s], pd[1][1][s])));
+        tf.hs[s] = fma(a * T::kappa, pd[1][0][s], psf[s]);
+    }
+}
+
+// every lane of the wave has IS_top <= delta on both sides of field s
+template <int NC>
+__device__ __forceinline__ bool top_wave_ok(const TopForm<NC> &tf, int s, double delta)
+{
+    const double sd = 2.0 * field_scale<NC>(s) * delta;
+    return ENOAO_EARLY_EXIT && wave_all(tf.is[s][0] <= sd && tf.is[s][1] <= sd);
+}
+
+// Full selection of the characteristic fields F0 (and F1 >= 0) of an Euler
+// face: project U and F of every stencil node (the compiler drops the rows not
+// used by these fields), split, select on both sides.  A field whose top
+// candidate is within delta on every lane (bit s of okmask) keeps the top
+// value; a lane whose selection takes the top candidate on both sides takes
+// the same value.  The top form is formed again here, after the windows and
+// for these fields only (the compiler drops the other rows): holding it from
+// the shortcut test through the window arithmetic would cost more registers
+// than it saves.  Taking the fields in two passes halves the live window
+// registers.
+template <int NC, int ORDER, bool DSTAGED, int F0, int F1>
+__device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
+                                           const RoeState &r, const double *al, double delta, int okmask,
+                                           double (&wh)[NC], int (&sel)[2 * NC])
+{
+    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
+    constexpr int NF = F1 >= 0 ? 2 : 1;
+    constexpr int fs[2] = {F0, F1 >= 0 ? F1 : F0};
+    constexpr int pmask = (1 << F0) | (F1 >= 0 ? 1 << F1 : 0);
+    double gp[NF][W], gm[NF][W];
+    if ((okmask & pmask) != pmask) {
+        // node t's LDS reads go out NODE_PREFETCH nodes ahead of its arithmetic
+        constexpr int D = ENOAO_NODE_PREFETCH;
+        double Uq[2 * G][NC], Fq[2 * G][NC];
+#pragma unroll
+        for (int t = 0; t < D && t < 2 * G; ++t) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Uq[t][c] = w0[c * qs + t * ns];
+                Fq[t][c] = w0[(NC + c) * qs + t * ns];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * G; ++t) {
+            if (t + D < 2 * G) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    Uq[t + D][c] = w0[c * qs + (t + D) * ns];
+                    Fq[t + D][c] = w0[(NC + c) * qs + (t + D) * ns];
+                }
+            }
+            double PU[NC], PF[NC];
+            project<NC>(r, Uq[t], PU);
+            project<NC>(r, Fq[t], PF);
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const int s = fs[i];
+                if (t < W) gp[i][t] = fma(al[s], PU[s], PF[s]);
+                if (t >= 1) gm[i][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
+            }
+            // bound the live ranges: a scheduling fence every NODE_SCHED nodes
+            if (ENOAO_NODE_SCHED > 0 && t % ENOAO_NODE_SCHED == ENOAO_NODE_SCHED - 1)
+                __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    TopForm<NC> tf;
+    top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const int s = fs[i];
+        const double sc = 2.0 * field_scale<NC>(s);
+        if (okmask & (1 << s)) {
+            wh[s] = tf.hs[s] * (1.0 / sc);
+            sel[2 * s] = sel[2 * s + 1] = K - 1;
+        } else {
+            int sp, sm;
+            const double hp = Recon<ORDER>::select(gp[i], sc * delta, tf.is[s][0], sp);
+            const double hm = Recon<ORDER>::select(gm[i], sc * delta, tf.is[s][1], sm);
+            wh[s] = (sp == K - 1 && sm == K - 1 ? tf.hs[s] : hp + hm) * (1.0 / sc);
+            sel[2 * s] = sp;
+            sel[2 * s + 1] = sm;
+        }
+    }
+}
+
+// Window form of an Euler face (the y-sweep's): every stencil node's U and F
+// are projected on the Roe basis of the face and split, and both sides of the
+// fields F0 (and F1 >= 0) are reconstructed from these windows, the top
+// candidate's indicator coming from the window's own difference table.  Joint
+// shortcut: when every window of the pass on every lane has its top candidate
+// within delta, the top candidate is every choice (first principle) and the
+// rest of the selection is skipped; results are bitwise those of the full
+// selection.  It keeps no per-node staging beyond the node quantities, which
+// leaves the y tiles' LDS budget for two workgroups per CU.
+template <int NC, int ORDER, int F0, int F1>
+__device__ __forceinline__ void field_pass_window(const double *w0, int qs, int ns, const RoeState &r,
+                                                  const double *al, double delta, double (&wh)[NC],
+                                                  int (&sel)[2 * NC])
+{
+    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
     constexpr int NF = F1 >= 0 ? 2 : 1;
     constexpr int fs[2] = {F0, F1 >= 0 ? F1 : F0};
     double gp[NF][W], gm[NF][W];
-    // node t's LDS reads go out NODE_PREFETCH nodes ahead of its arithmetic
     constexpr int D = ENOAO_NODE_PREFETCH;
     double Uq[2 * G][NC], Fq[2 * G][NC];
 #pragma unroll
@@ -187,15 +344,9 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
             if (t < W) gp[i][t] = fma(al[s], PU[s], PF[s]);
             if (t >= 1) gm[i][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
         }
-        // bound the live ranges: a scheduling fence every NODE_SCHED nodes
         if (ENOAO_NODE_SCHED > 0 && t % ENOAO_NODE_SCHED == ENOAO_NODE_SCHED - 1) __builtin_amdgcn_sched_barrier(0);
     }
-    // window = 2 * field_scale * w^(+/-).  Joint shortcut: when every window of
-    // the pass on every lane has IS <= delta for the top candidate, the top
-    // candidate is every choice (first principle) and the rest of the selection
-    // is skipped for the whole pass; the windows' work is then one straight-line
-    // block.  Results are bitwise those of the full selection.
-    if (ENOAO_JOINT_EXIT) {
+    {
         double hp[NF], hm[NF];
         bool all = true;
 #pragma unroll
@@ -206,12 +357,12 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
             hm[i] = Recon<ORDER>::top(gm[i], im);
             all = all && ip <= sd && im <= sd;
         }
-        if (wave_all(all)) {
+        if (ENOAO_EARLY_EXIT && wave_all(all)) {
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 const int s = fs[i];
                 wh[s] = (hp[i] + hm[i]) * (1.0 / (2.0 * field_scale<NC>(s)));
-                sel[2 * s] = sel[2 * s + 1] = ReconTraits<ORDER>::K - 1;
+                sel[2 * s] = sel[2 * s + 1] = K - 1;
             }
             return;
         }
@@ -229,26 +380,58 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
     }
 }
 
-template <int EQ, int ORDER>
-__device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, const double *al, double gm1,
-                                          double delta, double adv,
+// Numerical flux of one 2D Euler face by the window form.
+template <int ORDER>
+__device__ __forceinline__ void face_flux_window(const double *w0, int qs, int ns, const double *al, double gm1,
+                                                 double delta, double (&Fh)[4], int (&sel)[8])
+{
+    constexpr int G = ReconTraits<ORDER>::H + 1, QR = 8;
+    const double *nl = w0 + (G - 1) * ns, *nr = w0 + G * ns;
+    const RoeState r = roe_state(nl[QR * qs], nl[(QR + 1) * qs], nl[(QR + 2) * qs], nl[(QR + 3) * qs], nr[QR * qs],
+                                 nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
+    double wh[4];
+    field_pass_window<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, wh, sel);
+    field_pass_window<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, wh, sel);
+    back_project<4>(r, wh, Fh);
+}
+
+// Numerical flux of one face from its 2G window nodes (w0: node 0, quantity
+// stride qs, node stride ns; d0/dqs/dns: the staged top differences when
+// DSTAGED, quantities U then F, for advection u only).
+template <int EQ, int ORDER, bool DSTAGED>
+__device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
+                                          const double *al, double gm1, double delta, double adv,
                                           double (&Fh)[NodeTraits<EQ>::NC], int (&sel)[2 * NodeTraits<EQ>::NC])
 {
-    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1;
+    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
     if constexpr (EQ == ADVECTION) {
-        // f^(+/-) = (a u +/- alpha u)/2, reconstructed as 2 f^(+/-)
+        // f^(+/-) = (a u +/- alpha u)/2, reconstructed as 2 f^(+/-); the
+        // differences and the symmetric stencil of f = a u are a times those of u
+        using T = TopStencil<ORDER>;
+        double du[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) du[p] = DSTAGED ? d0[p * dns] : T::diff(w0 + p * ns, ns);
+        const double a = al[0];
+        const double isp = fmin(fabs(fma(a, du[0], adv * du[0])), fabs(fma(a, du[1], adv * du[1])));
+        const double ism = fmin(fabs(fma(-a, du[2], adv * du[2])), fabs(fma(-a, du[1], adv * du[1])));
+        const double hs = fma(a * T::kappa, du[1], adv * T::sym(w0, ns));
+        if (ENOAO_EARLY_EXIT && wave_all(isp <= 2.0 * delta && ism <= 2.0 * delta)) {
+            Fh[0] = 0.5 * hs;
+            sel[0] = sel[1] = K - 1;
+            return;
+        }
         double gp[W], gm[W];
 #pragma unroll
         for (int t = 0; t < 2 * G; ++t) {
             const double u = w0[t * ns];
             const double au = adv * u;
-            if (t < W) gp[t] = fma(al[0], u, au);
-            if (t >= 1) gm[2 * H + 1 - t] = fma(-al[0], u, au);
+            if (t < W) gp[t] = fma(a, u, au);
+            if (t >= 1) gm[2 * H + 1 - t] = fma(-a, u, au);
         }
         int sp, sm;
-        const double hp = Recon<ORDER>::run(gp, 2.0 * delta, sp);
-        const double hm = Recon<ORDER>::run(gm, 2.0 * delta, sm);
-        Fh[0] = 0.5 * (hp + hm);
+        const double hp = Recon<ORDER>::select(gp, 2.0 * delta, isp, sp);
+        const double hm = Recon<ORDER>::select(gm, 2.0 * delta, ism, sm);
+        Fh[0] = 0.5 * (sp == K - 1 && sm == K - 1 ? hs : hp + hm);
         sel[0] = sp;
         sel[1] = sm;
     } else {
@@ -262,14 +445,53 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
             r = roe_state(nl[QR * qs], nl[(QR + 1) * qs], nl[(QR + 2) * qs], nl[(QR + 3) * qs], nr[QR * qs],
                           nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
         double wh[NC];
-        if constexpr (NC == 4) {
-            field_pass<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, wh, sel);
-            field_pass<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, wh, sel);
-        } else {
-            field_pass<3, ORDER, 0, 2>(w0, qs, ns, r, al, delta, wh, sel);
-            field_pass<3, ORDER, 1, -1>(w0, qs, ns, r, al, delta, wh, sel);
+        int okmask = 0;  // fields whose top candidate is within delta on every lane
+        {
+            TopForm<NC> tf;
+            top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+                if (top_wave_ok<NC>(tf, s, delta)) okmask |= 1 << s;
+            if (okmask == (1 << NC) - 1) {
+#pragma unroll
+                for (int s = 0; s < NC; ++s) {
+                    wh[s] = tf.hs[s] * (1.0 / (2.0 * field_scale<NC>(s)));
+                    sel[2 * s] = sel[2 * s + 1] = K - 1;
+                }
+            }
+        }
+        if (okmask != (1 << NC) - 1) {
+            if constexpr (NC == 4) {
+                field_pass<4, ORDER, DSTAGED, 0, 3>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
+                field_pass<4, ORDER, DSTAGED, 1, 2>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
+            } else {
+                field_pass<3, ORDER, DSTAGED, 0, 2>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
+                field_pass<3, ORDER, DSTAGED, 1, -1>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
+            }
         }
         back_project<NC>(r, wh, Fh);
+    }
+}
+
+// Staged top differences of two consecutive nodes i and i+1: D_0 of every
+// staged quantity (U then F; advection: u) from nodes i .. i+2H, which the two
+// share (one lane reads 2H+1 nodes for both instead of 2H for each).  x: node
+// i, quantity stride qs, node stride ns; out: quantity stride oqs, node stride
+// ons.  With two == false only node i's difference is formed, from nodes
+// i .. i+2H-1 (node i+2H is not read).
+template <int EQ, int ORDER>
+__device__ __forceinline__ void stage_diff2(const double *x, int qs, int ns, double *out, int oqs, int ons, bool two)
+{
+    constexpr int ND = EQ == ADVECTION ? 1 : 2 * NodeTraits<EQ>::NC;
+    constexpr int H = ReconTraits<ORDER>::H;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        double w[2 * H + 1];
+#pragma unroll
+        for (int t = 0; t < 2 * H; ++t) w[t] = x[m * qs + t * ns];
+        w[2 * H] = two ? x[m * qs + 2 * H * ns] : 0.0;
+        out[m * oqs] = TopStencil<ORDER>::diff(w, 1);
+        if (two) out[m * oqs + ons] = TopStencil<ORDER>::diff(w + 1, 1);
     }
 }
 
@@ -291,17 +513,6 @@ __device__ __forceinline__ double rk_combine(double in, double base, double dt, 
 template <int MODE> __device__ __forceinline__ double rk_weight()
 {
     return MODE == M_S1 ? 1.0 : (MODE == M_S2 ? 0.25 : 2.0 / 3.0);
-}
-
-// wave-uniform copy of a value (scalar registers)
-template <typename T> __device__ __forceinline__ T uniform(T x)
-{
-    static_assert(sizeof(T) % 4 == 0, "32-bit multiple");
-    union { T v; int w[sizeof(T) / 4]; } a;
-    a.v = x;
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) a.w[i] = __builtin_amdgcn_readfirstlane(a.w[i]);
-    return a.v;
 }
 
 // Per-instance values of one sweep launch.  A workgroup walks a contiguous
@@ -379,10 +590,10 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 // registers while tile t is reconstructed, so the memory latency hides behind
 // the face arithmetic.
 #ifndef ENOAO_X_WAVES_PER_EU
-#define ENOAO_X_WAVES_PER_EU 1
+#define ENOAO_X_WAVES_PER_EU 2
 #endif
 #ifndef ENOAO_Y_WAVES_PER_EU
-#define ENOAO_Y_WAVES_PER_EU 1
+#define ENOAO_Y_WAVES_PER_EU 2
 #endif
 
 // a wave's segment within its instance: grid line and segment index along it
@@ -419,7 +630,11 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // a lane's global operands of one x tile: the nodes it stages (segment
-// positions lane and lane + 64) and, for a 1D stage 2 or 3, u^n at its cell
+// positions lane and lane + 64) and, for a 1D stage 2 or 3, u^n at its cell.
+// Every register is written on every path (lanes and rows past the end load a
+// clamped, in-bounds address whose value goes unused): a register that kept
+// its old value would be copied while its previous load may still be in
+// flight, and the copy's wait would stall on the prefetch just issued.
 template <int NC> struct XPre {
     double U[2][NC];
     double base[NC];
@@ -429,26 +644,22 @@ template <int EQ, int MODE, int G>
 __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int lane, XPre<NodeTraits<EQ>::NC> &pre)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NN = XW_FACES + 2 * G - 1;
-    if (c.row >= v.ny) return;
     const int nx = v.nx, sx = c.segx * XW_CELLS;
+    const int row = min(c.row, v.ny - 1);
     const long long plane = (long long)nx * v.ny;
-    const GMEM double *rowp = v.in + (long long)c.row * nx;
+    const GMEM double *rowp = v.in + (long long)row * nx;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const int i = lane + 64 * j;
-        if (i < NN) {
-            const int x = bc_map(sx - G + i, nx, v.bc);
+        const int i = min(lane + 64 * j, NN - 1);
+        const int x = bc_map(sx - G + i, nx, v.bc);
 #pragma unroll
-            for (int q = 0; q < NC; ++q) pre.U[j][q] = rowp[q * plane + x];
-        }
+        for (int q = 0; q < NC; ++q) pre.U[j][q] = rowp[q * plane + x];
     }
     if constexpr (MODE == M_S2 || MODE == M_S3) {
-        const int x = sx + lane;
-        if (lane < XW_CELLS && x < nx) {
-            const GMEM double *b = v.base + (long long)c.row * nx + x;
+        const int x = min(sx + lane, nx - 1);
+        const GMEM double *b = v.base + (long long)row * nx + x;
 #pragma unroll
-            for (int q = 0; q < NC; ++q) pre.base[q] = b[q * plane];
-        }
+        for (int q = 0; q < NC; ++q) pre.base[q] = b[q * plane];
     }
 }
 
@@ -459,8 +670,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
     constexpr int NN = XW_FACES + 2 * G - 1;  // nodes staged per segment
     constexpr int NNP = NN + 1;
+    constexpr int ND = EQ == ADVECTION ? 1 : 2 * NC;  // staged top differences per node
+    constexpr int NDN = XW_FACES + 2;                  // nodes with a staged difference
     constexpr bool FULL = (EQ != EULER2D) && (MODE != M_RHS);  // 1D stage: combine + maxima here
     __shared__ double lds[NQ * XW_SEGS * NNP];
+    __shared__ double dif[ND * XW_SEGS * NDN];
     __shared__ double fh[NC * XW_SEGS * XW_FACES];
     __shared__ double red[(BLOCK / 64) * 8];
 
@@ -473,6 +687,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
     mx.reset();
     XPre<NC> pre;
     double *L = lds + wseg * NNP;
+    double *Dl = dif + wseg * NDN;
 
     // Each wave owns its segment's LDS (nodes and face fluxes), so within the
     // tile loop the waves synchronise only with themselves.  The outer loop
@@ -518,12 +733,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
             const XCur cn = x_advance(c, v.per_row);
             if (tile + 1 < tend) x_prefetch<EQ, MODE, G>(v, cn, lane, pre);
             wave_sync();
+            // top differences of the nodes that start one (faces 0..63 read
+            // 0..65), two consecutive nodes per lane
+            static_assert(NDN % 2 == 0 && NDN / 2 <= 64, "one pair of nodes per lane");
+            if (ok && lane < NDN / 2)
+                stage_diff2<EQ, ORDER>(L + 2 * lane, XW_SEGS * NNP, 1, Dl + 2 * lane, XW_SEGS * NDN, 1, true);
+            wave_sync();
 
             const int f = sx + lane;  // face index along the line
             if (ok) {
                 double Fh[NC];
                 int sel[2 * NC];
-                face_flux<EQ, ORDER>(L + lane, XW_SEGS * NNP, 1, v.al, P.gm1, P.delta, v.adv, Fh, sel);
+                face_flux<EQ, ORDER, true>(L + lane, XW_SEGS * NNP, 1, Dl + lane, XW_SEGS * NDN, 1, v.al, P.gm1,
+                                           P.delta, v.adv, Fh, sel);
 #pragma unroll
                 for (int q = 0; q < NC; ++q) fh[(q * XW_SEGS + wseg) * XW_FACES + lane] = Fh[q];
                 if (REC && v.sel && f <= nx) {
@@ -621,7 +843,8 @@ template <int G, int YW> struct YPre {
 
 // a lane's global operands of one y tile: the strip nodes it stages (all rows
 // for the first tile of a walk, rows FRESH.. for the others) and the x-part at
-// its cell
+// its cell (lanes past the grid's edge read a clamped, in-bounds address whose
+// value goes unused).
 template <int MODE, int G, int YW>
 __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c, bool first, int wv, int lane,
                                            YPre<G, YW> &pre)
@@ -644,12 +867,10 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
             for (int q = 0; q < 4; ++q) pre.U[j][q] = p[perm[q] * plane];
         }
     }
-    const int fl = lane / YW, y = sy + fl, col = cbase + (lane % YW);
-    if (y < ny && col < nx) {
-        const long long o = (long long)y * nx + col;
+    const int fl = lane / YW, y = min(sy + fl, ny - 1), col = min(cbase + (lane % YW), nx - 1);
+    const long long o = (long long)y * nx + col;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
-    }
+    for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
 }
 
 // one face of a y strip into the face buffer (and the selection record)
@@ -660,7 +881,7 @@ __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KPara
     constexpr int NC = 4, CELLS = yt_cells(YW);
     double Fh[NC];
     int sel[2 * NC];
-    face_flux<EULER2D, ORDER>(W + k * YW + cc, QS, YW, v.al, P.gm1, P.delta, 0.0, Fh, sel);
+    face_flux_window<ORDER>(W + k * YW + cc, QS, YW, v.al, P.gm1, P.delta, Fh, sel);
 #pragma unroll
     for (int q = 0; q < NC; ++q) WF[(q * (CELLS + 1) + k) * YW + cc] = Fh[q];
     if (REC && v.sel && col < v.nx && f <= v.ny) {
@@ -968,7 +1189,7 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
         if (f <= n) {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EQ, ORDER>(q + tid, QS, 1, al, P.gm1, P.delta, I.adv, Fh, sel);
+            face_flux<EQ, ORDER, false>(q + tid, QS, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fx[c * (n + 1) + f] = Fh[c];
         }
