@@ -227,15 +227,12 @@ __device__ __forceinline__ bool top_wave_ok(const TopForm<NC> &tf, int s, double
 // used by these fields), split, select on both sides.  A field whose top
 // candidate is within delta on every lane (bit s of okmask) keeps the top
 // value; a lane whose selection takes the top candidate on both sides takes
-// the same value.  The top form is formed again here, after the windows and
-// for these fields only (the compiler drops the other rows): holding it from
-// the shortcut test through the window arithmetic would cost more registers
-// than it saves.  Taking the fields in two passes halves the live window
-// registers.
-template <int NC, int ORDER, bool DSTAGED, int F0, int F1>
-__device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
-                                           const RoeState &r, const double *al, double delta, int okmask,
-                                           double (&wh)[NC], int (&sel)[2 * NC])
+// the same value, tf (the face's top form, formed once).  Taking the fields in
+// two passes halves the live window registers.
+template <int NC, int ORDER, int F0, int F1>
+__device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const RoeState &r, const double *al,
+                                           double delta, int okmask, const TopForm<NC> &tf, double (&wh)[NC],
+                                           int (&sel)[2 * NC])
 {
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
     constexpr int NF = F1 >= 0 ? 2 : 1;
@@ -278,8 +275,6 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    TopForm<NC> tf;
-    top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         const int s = fs[i];
@@ -446,28 +441,23 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
                           nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
         double wh[NC];
         int okmask = 0;  // fields whose top candidate is within delta on every lane
-        {
-            TopForm<NC> tf;
-            top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
+        TopForm<NC> tf;
+        top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
 #pragma unroll
-            for (int s = 0; s < NC; ++s)
-                if (top_wave_ok<NC>(tf, s, delta)) okmask |= 1 << s;
-            if (okmask == (1 << NC) - 1) {
+        for (int s = 0; s < NC; ++s)
+            if (top_wave_ok<NC>(tf, s, delta)) okmask |= 1 << s;
+        if (okmask == (1 << NC) - 1) {
 #pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    wh[s] = tf.hs[s] * (1.0 / (2.0 * field_scale<NC>(s)));
-                    sel[2 * s] = sel[2 * s + 1] = K - 1;
-                }
+            for (int s = 0; s < NC; ++s) {
+                wh[s] = tf.hs[s] * (1.0 / (2.0 * field_scale<NC>(s)));
+                sel[2 * s] = sel[2 * s + 1] = K - 1;
             }
-        }
-        if (okmask != (1 << NC) - 1) {
-            if constexpr (NC == 4) {
-                field_pass<4, ORDER, DSTAGED, 0, 3>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
-                field_pass<4, ORDER, DSTAGED, 1, 2>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
-            } else {
-                field_pass<3, ORDER, DSTAGED, 0, 2>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
-                field_pass<3, ORDER, DSTAGED, 1, -1>(w0, qs, ns, d0, dqs, dns, r, al, delta, okmask, wh, sel);
-            }
+        } else if constexpr (NC == 4) {
+            field_pass<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+            field_pass<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+        } else {
+            field_pass<3, ORDER, 0, 2>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+            field_pass<3, ORDER, 1, -1>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
         }
         back_project<NC>(r, wh, Fh);
     }
@@ -588,9 +578,11 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 // x-sweep.  Each wave: one segment of a grid line (64 faces, 63 cells).
 // Tiles are software-pipelined: the global operands of tile t+1 are loaded into
 // registers while tile t is reconstructed, so the memory latency hides behind
-// the face arithmetic.
+// the face arithmetic.  Waves per SIMD the register allocation must allow
+// (measured: three for the x-sweep, whose LDS fits three workgroups per CU;
+// two for the y-sweep, whose LDS fits two).
 #ifndef ENOAO_X_WAVES_PER_EU
-#define ENOAO_X_WAVES_PER_EU 2
+#define ENOAO_X_WAVES_PER_EU 3
 #endif
 #ifndef ENOAO_Y_WAVES_PER_EU
 #define ENOAO_Y_WAVES_PER_EU 2
