@@ -256,6 +256,19 @@ enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, 
  * return ENOAO_EINVAL.  enoao_step (host-given step) and pools always stream. */
 enoao_status enoao_set_resident(int32_t enable);
 
+/* Wave-uniform shortcut of the face kernels (Section 3.2, first principle):
+ * when every face of a wave has the top candidate's indicator within delta on
+ * both sides of a characteristic field, that field skips the other candidates'
+ * indicators and the selection, and its value is the top candidate's, formed
+ * directly (the x-sweeps and the LDS-resident solver: from the conserved-
+ * variable differences of that candidate; the y-sweep: from its window).
+ * Whenever the full selection picks the top candidate on both sides it uses
+ * the same top indicator and value, so results do not depend on the shortcut.
+ * enable = 1 (default) or 0 (every face takes the full selection; slower, for
+ * checking that property); it applies to plans, batches and pools created
+ * afterwards.  Other values return ENOAO_EINVAL. */
+enoao_status enoao_set_shortcut(int32_t enable);
+
 const char *enoao_status_string(enoao_status status);
 
 #ifdef __cplusplus

@@ -20,6 +20,7 @@ namespace {
 
 int g_wg_per_cu = 0;  // 0: occupancy of each kernel
 int g_resident = 1;   // small 1D members: LDS-resident solver for controlled steps
+int g_shortcut = 1;   // wave-uniform top-candidate shortcut of the face kernels
 
 // kernel kinds of the per-kernel timing (enoao_profile_read order)
 enum { PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_RESIDENT, PROF_KINDS };
@@ -110,6 +111,7 @@ struct Runtime {
     bool resident = false;
     size_t res_lds = 0;
     bool use_resident() const { return resident && g_resident != 0; }
+    int kflags = g_shortcut ? 0 : KF_FULL_SELECTION;  // taken when the plan or batch is created
     // optional per-kernel timing: hipEvents recorded around every launch, on the
     // stream the kernel is launched on (eager launches, no graph)
     bool profiling = false;
@@ -161,6 +163,7 @@ struct Runtime {
         p.r_in = r_in;
         p.r_out = r_out;
         p.r_zero = r_zero;
+        p.flags = kflags;
         return p;
     }
 
@@ -613,6 +616,13 @@ enoao_status enoao_set_resident(int32_t enable)
 {
     if (enable != 0 && enable != 1) return ENOAO_EINVAL;
     g_resident = enable;
+    return ENOAO_OK;
+}
+
+enoao_status enoao_set_shortcut(int32_t enable)
+{
+    if (enable != 0 && enable != 1) return ENOAO_EINVAL;
+    g_shortcut = enable;
     return ENOAO_OK;
 }
 

@@ -46,14 +46,12 @@ namespace enoao {
 
 // Wave-uniform shortcut: when every lane of the wave has IS <= delta for the
 // top candidate on both sides of a field, that candidate is every lane's choice
-// (first principle) and the field's value is the top candidate's conserved-
-// variable form alone; otherwise the field takes the full selection.  A lane's
-// result does not depend on the path: the full selection uses the same top
-// indicator and, when it picks the top candidate on both sides, the same value.
-// 0: always the full selection (checks that property).
-#ifndef ENOAO_EARLY_EXIT
-#define ENOAO_EARLY_EXIT 1
-#endif
+// (first principle) and the field's value is the top candidate's alone;
+// otherwise the field takes the full selection.  A lane's result does not
+// depend on the path: the full selection uses the same top indicator and, when
+// it picks the top candidate on both sides, the same value.  The kernels take
+// a flag that turns the shortcut off (every face takes the full selection), so
+// that property can be checked.
 
 // true when the predicate holds on every active lane of the wave (one ballot)
 __device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
@@ -212,12 +210,13 @@ template <int ORDER> struct Recon {
     }
 
     // One side by the window form: the top candidate's indicator from the
-    // window; when it is within delta on every lane the selection is skipped.
-    __device__ __forceinline__ static double run(const double (&f)[W], double delta, int &sel)
+    // window; when it is within delta on every lane (and the shortcut is on)
+    // the selection is skipped.
+    __device__ __forceinline__ static double run(const double (&f)[W], double delta, bool shortcut, int &sel)
     {
         double is_top;
         const double ht = top(f, is_top);
-        if (ENOAO_EARLY_EXIT && wave_all(is_top <= delta)) {
+        if (wave_all(is_top <= delta) & shortcut) {
             sel = K - 1;
             return ht;
         }

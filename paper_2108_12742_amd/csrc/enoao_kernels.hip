@@ -216,10 +216,10 @@ __device__ __forceinline__ void top_form(const double *w0, int qs, int ns, const
 
 // every lane of the wave has IS_top <= delta on both sides of field s
 template <int NC>
-__device__ __forceinline__ bool top_wave_ok(const TopForm<NC> &tf, int s, double delta)
+__device__ __forceinline__ bool top_wave_ok(const TopForm<NC> &tf, int s, double delta, bool shortcut)
 {
     const double sd = 2.0 * field_scale<NC>(s) * delta;
-    return ENOAO_EARLY_EXIT && wave_all(tf.is[s][0] <= sd && tf.is[s][1] <= sd);
+    return wave_all(tf.is[s][0] <= sd && tf.is[s][1] <= sd) & shortcut;
 }
 
 // Full selection of the characteristic fields F0 (and F1 >= 0) of an Euler
@@ -304,7 +304,7 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
 // leaves the y tiles' LDS budget for two workgroups per CU.
 template <int NC, int ORDER, int F0, int F1>
 __device__ __forceinline__ void field_pass_window(const double *w0, int qs, int ns, const RoeState &r,
-                                                  const double *al, double delta, double (&wh)[NC],
+                                                  const double *al, double delta, bool shortcut, double (&wh)[NC],
                                                   int (&sel)[2 * NC])
 {
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
@@ -352,7 +352,7 @@ __device__ __forceinline__ void field_pass_window(const double *w0, int qs, int 
             hm[i] = Recon<ORDER>::top(gm[i], im);
             all = all && ip <= sd && im <= sd;
         }
-        if (ENOAO_EARLY_EXIT && wave_all(all)) {
+        if (wave_all(all) & shortcut) {
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 const int s = fs[i];
@@ -367,8 +367,8 @@ __device__ __forceinline__ void field_pass_window(const double *w0, int qs, int 
         const int s = fs[i];
         const double sc = 2.0 * field_scale<NC>(s);
         int sp, sm;
-        const double hp = Recon<ORDER>::run(gp[i], sc * delta, sp);
-        const double hm = Recon<ORDER>::run(gm[i], sc * delta, sm);
+        const double hp = Recon<ORDER>::run(gp[i], sc * delta, shortcut, sp);
+        const double hm = Recon<ORDER>::run(gm[i], sc * delta, shortcut, sm);
         wh[s] = (hp + hm) * (1.0 / sc);
         sel[2 * s] = sp;
         sel[2 * s + 1] = sm;
@@ -378,24 +378,25 @@ __device__ __forceinline__ void field_pass_window(const double *w0, int qs, int 
 // Numerical flux of one 2D Euler face by the window form.
 template <int ORDER>
 __device__ __forceinline__ void face_flux_window(const double *w0, int qs, int ns, const double *al, double gm1,
-                                                 double delta, double (&Fh)[4], int (&sel)[8])
+                                                 double delta, bool shortcut, double (&Fh)[4], int (&sel)[8])
 {
     constexpr int G = ReconTraits<ORDER>::H + 1, QR = 8;
     const double *nl = w0 + (G - 1) * ns, *nr = w0 + G * ns;
     const RoeState r = roe_state(nl[QR * qs], nl[(QR + 1) * qs], nl[(QR + 2) * qs], nl[(QR + 3) * qs], nr[QR * qs],
                                  nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
     double wh[4];
-    field_pass_window<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, wh, sel);
-    field_pass_window<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, wh, sel);
+    field_pass_window<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, shortcut, wh, sel);
+    field_pass_window<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, shortcut, wh, sel);
     back_project<4>(r, wh, Fh);
 }
 
 // Numerical flux of one face from its 2G window nodes (w0: node 0, quantity
 // stride qs, node stride ns; d0/dqs/dns: the staged top differences when
-// DSTAGED, quantities U then F, for advection u only).
+// DSTAGED, quantities U then F, for advection u only).  shortcut = false: every
+// field takes the full selection (the result is the same).
 template <int EQ, int ORDER, bool DSTAGED>
 __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
-                                          const double *al, double gm1, double delta, double adv,
+                                          const double *al, double gm1, double delta, double adv, bool shortcut,
                                           double (&Fh)[NodeTraits<EQ>::NC], int (&sel)[2 * NodeTraits<EQ>::NC])
 {
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
@@ -410,7 +411,7 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
         const double isp = fmin(fabs(fma(a, du[0], adv * du[0])), fabs(fma(a, du[1], adv * du[1])));
         const double ism = fmin(fabs(fma(-a, du[2], adv * du[2])), fabs(fma(-a, du[1], adv * du[1])));
         const double hs = fma(a * T::kappa, du[1], adv * T::sym(w0, ns));
-        if (ENOAO_EARLY_EXIT && wave_all(isp <= 2.0 * delta && ism <= 2.0 * delta)) {
+        if (wave_all(isp <= 2.0 * delta && ism <= 2.0 * delta) & shortcut) {
             Fh[0] = 0.5 * hs;
             sel[0] = sel[1] = K - 1;
             return;
@@ -445,7 +446,7 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
         top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
 #pragma unroll
         for (int s = 0; s < NC; ++s)
-            if (top_wave_ok<NC>(tf, s, delta)) okmask |= 1 << s;
+            if (top_wave_ok<NC>(tf, s, delta, shortcut)) okmask |= 1 << s;
         if (okmask == (1 << NC) - 1) {
 #pragma unroll
             for (int s = 0; s < NC; ++s) {
@@ -579,10 +580,13 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 // Tiles are software-pipelined: the global operands of tile t+1 are loaded into
 // registers while tile t is reconstructed, so the memory latency hides behind
 // the face arithmetic.  Waves per SIMD the register allocation must allow
-// (measured: three for the x-sweep, whose LDS fits three workgroups per CU;
-// two for the y-sweep, whose LDS fits two).
+// (measured: three for the x-sweep, whose LDS fits three workgroups per CU,
+// except the 2D stages 2 and 3; two for the y-sweep, whose LDS fits two).
 #ifndef ENOAO_X_WAVES_PER_EU
 #define ENOAO_X_WAVES_PER_EU 3
+#endif
+#ifndef ENOAO_X23_WAVES_PER_EU
+#define ENOAO_X23_WAVES_PER_EU 2  // 2D stages 2 and 3, which hold u^n as well (three waves spill there)
 #endif
 #ifndef ENOAO_Y_WAVES_PER_EU
 #define ENOAO_Y_WAVES_PER_EU 2
@@ -656,7 +660,8 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
 }
 
 template <int EQ, int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(EQ == EULER2D && (MODE == M_S2 || MODE == M_S3) ? ENOAO_X23_WAVES_PER_EU
+                                                                                : ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
@@ -737,7 +742,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_X_W
                 double Fh[NC];
                 int sel[2 * NC];
                 face_flux<EQ, ORDER, true>(L + lane, XW_SEGS * NNP, 1, Dl + lane, XW_SEGS * NDN, 1, v.al, P.gm1,
-                                           P.delta, v.adv, Fh, sel);
+                                           P.delta, v.adv, (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
                 for (int q = 0; q < NC; ++q) fh[(q * XW_SEGS + wseg) * XW_FACES + lane] = Fh[q];
                 if (REC && v.sel && f <= nx) {
@@ -873,7 +878,8 @@ __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KPara
     constexpr int NC = 4, CELLS = yt_cells(YW);
     double Fh[NC];
     int sel[2 * NC];
-    face_flux_window<ORDER>(W + k * YW + cc, QS, YW, v.al, P.gm1, P.delta, Fh, sel);
+    face_flux_window<ORDER>(W + k * YW + cc, QS, YW, v.al, P.gm1, P.delta, (P.flags & KF_FULL_SELECTION) == 0, Fh,
+                            sel);
 #pragma unroll
     for (int q = 0; q < NC; ++q) WF[(q * (CELLS + 1) + k) * YW + cc] = Fh[q];
     if (REC && v.sel && col < v.nx && f <= v.ny) {
@@ -1181,7 +1187,8 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
         if (f <= n) {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EQ, ORDER, false>(q + tid, QS, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv, Fh, sel);
+            face_flux<EQ, ORDER, false>(q + tid, QS, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv,
+                                        (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fx[c * (n + 1) + f] = Fh[c];
         }

@@ -22,8 +22,12 @@ struct KParams {
     int r_in;    // maxima slot holding alpha of the stage input
     int r_out;   // slot receiving the maxima of the stage output (-1: none)
     int r_zero;  // slot cleared by the first kernel of the stage (-1: none)
-    int pad;
+    int flags;   // KF_* below
 };
+
+// every face takes the full selection (no wave-uniform shortcut); results are
+// the same either way, which this flag lets a caller check
+constexpr int KF_FULL_SELECTION = 1;
 
 hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s);
 // yw: columns per wave strip of the y tiles (4 or 8; the members' y tile lists

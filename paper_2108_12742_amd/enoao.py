@@ -102,6 +102,7 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int32), vp], st),
             "enoao_set_launch": ([ctypes.c_int32, ctypes.c_int32], st),
             "enoao_set_resident": ([ctypes.c_int32], st),
+            "enoao_set_shortcut": ([ctypes.c_int32], st),
             "enoao_plan_set_tiles": ([vp, ctypes.c_int32, vp], st),
             "enoao_batch_set_tiles": ([vp, ctypes.c_int32, vp], st),
             "enoao_plan_set_launch": ([vp, ctypes.c_int32], st),
@@ -308,6 +309,10 @@ def enoao_batch_profile_read(batch: Batch, stream=None):
 
 def enoao_set_resident(enable: bool):
     _check(lib().enoao_set_resident(1 if enable else 0), "enoao_set_resident")
+
+
+def enoao_set_shortcut(enable: bool):
+    _check(lib().enoao_set_shortcut(1 if enable else 0), "enoao_set_shortcut")
 
 
 def enoao_set_launch(workgroups_per_cu: int):

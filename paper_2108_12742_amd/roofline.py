@@ -4,10 +4,16 @@ Units: a "face" is one face of one sweep direction with all its characteristic
 fields and both split sides; a "cell" is one node updated by one kernel launch.
 Counts are the essential FP64 operations of the method as laid out in the
 kernels (add, sub, mul, div, sqrt, min/max, compare = 1 flop; a fused
-multiply-add = 2; fabs and negation free), counting one candidate flux per side
-(the selected one) and every indicator (branch-free selection).  Bytes are the
-compulsory HBM traffic of a launch: each input array read once, each output
-written once (halo re-reads excluded).
+multiply-add = 2; fabs and negation free).  Two layouts of the same arithmetic:
+  * window form (y-sweep): every stencil node projected and split, every
+    indicator and one candidate flux per side (branch-free selection);
+  * top form (x-sweep and the LDS-resident solver): the top candidate's two
+    indicators and the sum of its one-sided values from conserved-variable
+    differences and a symmetric stencil, seven projected vectors per face.  The
+    full selection that waves with a field off the top candidate add is
+    data-dependent and not counted (the count is a lower bound there).
+Bytes are the compulsory HBM traffic of a launch: each input array read once,
+each output written once (halo re-reads excluded).
 
 Peaks (MI355X, published): HBM3E 8.0 TB/s; FP64 vector 78.6 TFLOP/s
 (256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz).
@@ -43,6 +49,33 @@ def face_flops(equation: str, order: int) -> int:
     return node + roe + projection + split + recon + back + diff
 
 
+# (2H-1)-th difference of one quantity at one node (order 5: 3 subtractions and
+# 2 multiply-adds; order 7: 4 and 3) and the symmetric stencil of one quantity
+# (pair sums, consecutive differences and multiply-adds: order 5 3+2+2, order 7 4+3+3)
+TOP_DIFF = {5: 3 + 2 * 2, 7: 4 + 3 * 2}
+TOP_SYM = {5: 3 + 2 + 2 * 2, 7: 4 + 3 + 3 * 2}
+
+
+def face_flops_top(equation: str, order: int) -> int:
+    """Top form of one face (common path): node quantities and the staged
+    differences of its node, the symmetric stencil of F, the Roe state, seven
+    projections (D_0, D_1, D_2 of U and F, S F), per field both sides' indicators
+    (two fma, a min and a compare each) and the value sum (a multiply and an fma,
+    then the window scaling), the back-projection and the flux difference."""
+    d, sym = TOP_DIFF[order], TOP_SYM[order]
+    if equation == "advection":
+        # differences and stencil of u; per side two a*D products (mul + fma), min,
+        # compare; value sum (mul, mul, fma) and the 1/2; flux difference
+        return d + sym + 2 * (2 * 3 + 2) + 4 + 1 + 2
+    nc = 3 if equation == "euler1d" else 4
+    node = 15 if nc == 4 else 12
+    roe = 23 if nc == 4 else 19
+    proj_vec = 15 if nc == 4 else 11
+    fields = nc * (2 * (2 * 2 + 1 + 1) + (1 + 2 + 1))
+    back = 16 if nc == 4 else 12
+    return node + 2 * nc * d + nc * sym + roe + 7 * proj_vec + fields + back + 2 * nc
+
+
 def combine_flops(nc: int, stage: int) -> int:
     """Shu-Osher stage combine per cell: in + dt L (one fma per component), and for
     stages 2 and 3 the weighted sum with u^n (a multiply and an fma more)."""
@@ -75,9 +108,10 @@ def sweep_bytes(equation: str, kernel: str, stage: int) -> int:
 
 
 def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
-    """Algorithmic flops per cell of one launch."""
+    """Algorithmic flops per cell of one launch (x-sweeps: top form; y-sweep:
+    window form)."""
     nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
-    f = face_flops(equation, order)
+    f = face_flops_top(equation, order) if kernel == "x" else face_flops(equation, order)
     if stage == 0:
         return f
     if equation == "euler2d":
@@ -86,8 +120,8 @@ def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
 
 
 def cell_update_flops(equation: str, order: int) -> int:
-    dims = 2 if equation == "euler2d" else 1
-    return 3 * dims * face_flops(equation, order) + sum(stage_cell_flops(equation, s) for s in (1, 2, 3))
+    faces = face_flops_top(equation, order) + (face_flops(equation, order) if equation == "euler2d" else 0)
+    return 3 * faces + sum(stage_cell_flops(equation, s) for s in (1, 2, 3))
 
 
 def cell_update_bytes(equation: str) -> int:
