@@ -26,6 +26,10 @@
 //     S_{j-1}^{j+1} = S_j^{j+1} - 1/6 (f_{j+1} - 2 f_j + f_{j-1})), so all
 //     candidates cost one multiply-add each and the chosen one is selected
 //     with the index, without a table in memory;
+//   * the top candidate also has a conserved-variable form (TopStencil): its
+//     indicators and the sum of its two one-sided values are linear in the
+//     window, so differences and a symmetric stencil of U and F are formed
+//     first and projected on the characteristic fields afterwards;
 //   * a window may be scaled by a power of two before reconstruction (the
 //     factor 1/2 of the splitting is applied after it); scaling by 2^k is
 //     exact, so indicators, comparisons and selections are unchanged when delta

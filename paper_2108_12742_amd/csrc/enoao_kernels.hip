@@ -12,6 +12,9 @@
 //        does the RK combine and the maxima.
 // Kernels are persistent: a grid of (CUs x occupancy) workgroups walks a
 // contiguous chunk of the flattened tile list of all instances of a batch.
+// The x-sweeps (and the LDS-resident solver) take each field's top candidate in
+// conserved-variable form and run the full selection only for the fields of a
+// wave that need it; the y-sweep reconstructs from projected windows.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
