@@ -260,8 +260,8 @@ enoao_status enoao_set_resident(int32_t enable);
  * when every face of a wave has the top candidate's indicator within delta on
  * both sides of a characteristic field, that field skips the other candidates'
  * indicators and the selection, and its value is the top candidate's, formed
- * directly (the x-sweeps and the LDS-resident solver: from the conserved-
- * variable differences of that candidate; the y-sweep: from its window).
+ * directly from the conserved-variable differences and symmetric stencil of
+ * that candidate.
  * Whenever the full selection picks the top candidate on both sides it uses
  * the same top indicator and value, so results do not depend on the shortcut.
  * enable = 1 (default) or 0 (every face takes the full selection; slower, for

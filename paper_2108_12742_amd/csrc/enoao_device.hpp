@@ -173,59 +173,6 @@ template <int ORDER> struct Recon {
             return select_candidate<9>(is, h, delta, sel);
         }
     }
-
-    // The top candidate's value and indicator from the window's own difference
-    // table (the same operations as the corresponding entries in select()).
-    __device__ __forceinline__ static double top(const double (&f)[W], double &is_top)
-    {
-        if constexpr (ORDER == 5) {
-            const double a1 = f[2] - f[1], a2 = f[3] - f[2], a3 = f[4] - f[3], a0 = f[1] - f[0];
-            const double a4 = f[5] - f[4], a5 = f[6] - f[5];
-            const double b1 = a2 - a1, b2 = a3 - a2, b3 = a4 - a3;
-            const double c0 = b1 - (a1 - a0), c1 = b2 - b1, c2 = b3 - b2, c3 = (a5 - a4) - b3;
-            const double d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
-            is_top = fmin(fabs(d1 - d0), fabs(d2 - d1));
-            const double h1 = fma(0.5, a3, f[3]);
-            const double h2 = fma(-1.0 / 6.0, b2, h1);
-            const double h3 = fma(-1.0 / 12.0, c1, h2);
-            return fma(-1.0 / 20.0, d1, h3);
-        } else {
-            double a[8], b[7], c[6], d[5], e[4], g[3];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = f[i + 1] - f[i];
-#pragma unroll
-            for (int i = 0; i < 7; ++i) b[i] = a[i + 1] - a[i];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) c[i] = b[i + 1] - b[i];
-#pragma unroll
-            for (int i = 0; i < 5; ++i) d[i] = c[i + 1] - c[i];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) e[i] = d[i + 1] - d[i];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) g[i] = e[i + 1] - e[i];
-            is_top = fmin(fabs(g[1] - g[0]), fabs(g[2] - g[1]));
-            const double h1 = fma(0.5, a[4], f[4]);
-            const double h2 = fma(-1.0 / 6.0, b[3], h1);
-            const double h3 = fma(-1.0 / 12.0, c[2], h2);
-            const double h5 = fma(-1.0 / 20.0, d[2], h3);
-            const double h6 = fma(1.0 / 60.0, e[1], h5);
-            return fma(1.0 / 105.0, g[1], h6);
-        }
-    }
-
-    // One side by the window form: the top candidate's indicator from the
-    // window; when it is within delta on every lane (and the shortcut is on)
-    // the selection is skipped.
-    __device__ __forceinline__ static double run(const double (&f)[W], double delta, bool shortcut, int &sel)
-    {
-        double is_top;
-        const double ht = top(f, is_top);
-        if (wave_all(is_top <= delta) & shortcut) {
-            sel = K - 1;
-            return ht;
-        }
-        return select(f, delta, is_top, sel);
-    }
 };
 
 // The top candidate (S_{j-2}^{j+2}, order 7: S_{j-3}^{j+3}) in conserved

@@ -12,9 +12,10 @@
 //        does the RK combine and the maxima.
 // Kernels are persistent: a grid of (CUs x occupancy) workgroups walks a
 // contiguous chunk of the flattened tile list of all instances of a batch.
-// The x-sweeps (and the LDS-resident solver) take each field's top candidate in
-// conserved-variable form and run the full selection only for the fields of a
-// wave that need it; the y-sweep reconstructs from projected windows.
+// Every face takes each field's top candidate in conserved-variable form and
+// runs the full selection only for the fields of a wave that need it (the
+// x-sweeps stage the top differences per node pair in LDS; the y-sweep and the
+// LDS-resident solver form them per face, which their LDS budgets require).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -296,103 +297,6 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
     }
 }
 
-// Window form of an Euler face (the y-sweep's): every stencil node's U and F
-// are projected on the Roe basis of the face and split, and both sides of the
-// fields F0 (and F1 >= 0) are reconstructed from these windows, the top
-// candidate's indicator coming from the window's own difference table.  Joint
-// shortcut: when every window of the pass on every lane has its top candidate
-// within delta, the top candidate is every choice (first principle) and the
-// rest of the selection is skipped; results are bitwise those of the full
-// selection.  It keeps no per-node staging beyond the node quantities, which
-// leaves the y tiles' LDS budget for two workgroups per CU.
-template <int NC, int ORDER, int F0, int F1>
-__device__ __forceinline__ void field_pass_window(const double *w0, int qs, int ns, const RoeState &r,
-                                                  const double *al, double delta, bool shortcut, double (&wh)[NC],
-                                                  int (&sel)[2 * NC])
-{
-    constexpr int H = ReconTraits<ORDER>::H, G = H + 1, W = 2 * H + 1, K = ReconTraits<ORDER>::K;
-    constexpr int NF = F1 >= 0 ? 2 : 1;
-    constexpr int fs[2] = {F0, F1 >= 0 ? F1 : F0};
-    double gp[NF][W], gm[NF][W];
-    constexpr int D = ENOAO_NODE_PREFETCH;
-    double Uq[2 * G][NC], Fq[2 * G][NC];
-#pragma unroll
-    for (int t = 0; t < D && t < 2 * G; ++t) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            Uq[t][c] = w0[c * qs + t * ns];
-            Fq[t][c] = w0[(NC + c) * qs + t * ns];
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 2 * G; ++t) {
-        if (t + D < 2 * G) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                Uq[t + D][c] = w0[c * qs + (t + D) * ns];
-                Fq[t + D][c] = w0[(NC + c) * qs + (t + D) * ns];
-            }
-        }
-        double PU[NC], PF[NC];
-        project<NC>(r, Uq[t], PU);
-        project<NC>(r, Fq[t], PF);
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            const int s = fs[i];
-            if (t < W) gp[i][t] = fma(al[s], PU[s], PF[s]);
-            if (t >= 1) gm[i][2 * H + 1 - t] = fma(-al[s], PU[s], PF[s]);
-        }
-        if (ENOAO_NODE_SCHED > 0 && t % ENOAO_NODE_SCHED == ENOAO_NODE_SCHED - 1) __builtin_amdgcn_sched_barrier(0);
-    }
-    {
-        double hp[NF], hm[NF];
-        bool all = true;
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            const double sd = 2.0 * field_scale<NC>(fs[i]) * delta;
-            double ip, im;
-            hp[i] = Recon<ORDER>::top(gp[i], ip);
-            hm[i] = Recon<ORDER>::top(gm[i], im);
-            all = all && ip <= sd && im <= sd;
-        }
-        if (wave_all(all) & shortcut) {
-#pragma unroll
-            for (int i = 0; i < NF; ++i) {
-                const int s = fs[i];
-                wh[s] = (hp[i] + hm[i]) * (1.0 / (2.0 * field_scale<NC>(s)));
-                sel[2 * s] = sel[2 * s + 1] = K - 1;
-            }
-            return;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-        const int s = fs[i];
-        const double sc = 2.0 * field_scale<NC>(s);
-        int sp, sm;
-        const double hp = Recon<ORDER>::run(gp[i], sc * delta, shortcut, sp);
-        const double hm = Recon<ORDER>::run(gm[i], sc * delta, shortcut, sm);
-        wh[s] = (hp + hm) * (1.0 / sc);
-        sel[2 * s] = sp;
-        sel[2 * s + 1] = sm;
-    }
-}
-
-// Numerical flux of one 2D Euler face by the window form.
-template <int ORDER>
-__device__ __forceinline__ void face_flux_window(const double *w0, int qs, int ns, const double *al, double gm1,
-                                                 double delta, bool shortcut, double (&Fh)[4], int (&sel)[8])
-{
-    constexpr int G = ReconTraits<ORDER>::H + 1, QR = 8;
-    const double *nl = w0 + (G - 1) * ns, *nr = w0 + G * ns;
-    const RoeState r = roe_state(nl[QR * qs], nl[(QR + 1) * qs], nl[(QR + 2) * qs], nl[(QR + 3) * qs], nr[QR * qs],
-                                 nr[(QR + 1) * qs], nr[(QR + 2) * qs], nr[(QR + 3) * qs], gm1);
-    double wh[4];
-    field_pass_window<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, shortcut, wh, sel);
-    field_pass_window<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, shortcut, wh, sel);
-    back_project<4>(r, wh, Fh);
-}
-
 // Numerical flux of one face from its 2G window nodes (w0: node 0, quantity
 // stride qs, node stride ns; d0/dqs/dns: the staged top differences when
 // DSTAGED, quantities U then F, for advection u only).  shortcut = false: every
@@ -584,12 +488,13 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 // registers while tile t is reconstructed, so the memory latency hides behind
 // the face arithmetic.  Waves per SIMD the register allocation must allow
 // (measured: three for the x-sweep, whose LDS fits three workgroups per CU,
-// except the 2D stages 2 and 3; two for the y-sweep, whose LDS fits two).
+// except the 2D stages 2 and 3 and order 7, which spill at three; two for the
+// y-sweep, whose LDS fits two).
 #ifndef ENOAO_X_WAVES_PER_EU
 #define ENOAO_X_WAVES_PER_EU 3
 #endif
 #ifndef ENOAO_X23_WAVES_PER_EU
-#define ENOAO_X23_WAVES_PER_EU 2  // 2D stages 2 and 3, which hold u^n as well (three waves spill there)
+#define ENOAO_X23_WAVES_PER_EU 2  // 2D stages 2 and 3 (they hold u^n as well) and order 7
 #endif
 #ifndef ENOAO_Y_WAVES_PER_EU
 #define ENOAO_Y_WAVES_PER_EU 2
@@ -663,8 +568,9 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
 }
 
 template <int EQ, int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(EQ == EULER2D && (MODE == M_S2 || MODE == M_S3) ? ENOAO_X23_WAVES_PER_EU
-                                                                                : ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 7 || (EQ == EULER2D && (MODE == M_S2 || MODE == M_S3))
+                                                    ? ENOAO_X23_WAVES_PER_EU
+                                                    : ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
@@ -881,8 +787,8 @@ __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KPara
     constexpr int NC = 4, CELLS = yt_cells(YW);
     double Fh[NC];
     int sel[2 * NC];
-    face_flux_window<ORDER>(W + k * YW + cc, QS, YW, v.al, P.gm1, P.delta, (P.flags & KF_FULL_SELECTION) == 0, Fh,
-                            sel);
+    face_flux<EULER2D, ORDER, false>(W + k * YW + cc, QS, YW, nullptr, 0, 0, v.al, P.gm1, P.delta, 0.0,
+                                     (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
     for (int q = 0; q < NC; ++q) WF[(q * (CELLS + 1) + k) * YW + cc] = Fh[q];
     if (REC && v.sel && col < v.nx && f <= v.ny) {

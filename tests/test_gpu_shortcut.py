@@ -2,8 +2,8 @@
 top candidate is within delta on every face of a wave takes that candidate's value
 directly) must not change any result: with the shortcut switched off every face takes
 the full selection, and states and selection records agree bit for bit, for the
-x-sweep (top candidate in conserved-variable form), the y-sweep (window form), the
-LDS-resident solver and batches."""
+x-sweep (top differences staged per node), the y-sweep and the LDS-resident solver
+(formed per face) and batches."""
 import numpy as np
 import pytest
 
