@@ -5,9 +5,10 @@ fields and both split sides; a "cell" is one node updated by one kernel launch.
 Counts are the essential FP64 operations of the method as laid out in the
 kernels (add, sub, mul, div, sqrt, min/max, compare = 1 flop; a fused
 multiply-add = 2; fabs and negation free).  Two layouts of the same arithmetic:
-  * window form (y-sweep): every stencil node projected and split, every
-    indicator and one candidate flux per side (branch-free selection);
-  * top form (x-sweep and the LDS-resident solver): the top candidate's two
+  * window form: every stencil node projected and split, every indicator and
+    one candidate flux per side (branch-free selection) -- the full selection,
+    which the kernels run only for the fields of a wave that need it;
+  * top form (every sweep and the LDS-resident solver): the top candidate's two
     indicators and the sum of its one-sided values from conserved-variable
     differences and a symmetric stencil, seven projected vectors per face.  The
     full selection that waves with a field off the top candidate add is
@@ -57,11 +58,13 @@ TOP_SYM = {5: 3 + 2 + 2 * 2, 7: 4 + 3 + 3 * 2}
 
 
 def face_flops_top(equation: str, order: int) -> int:
-    """Top form of one face (common path): node quantities and the staged
-    differences of its node, the symmetric stencil of F, the Roe state, seven
-    projections (D_0, D_1, D_2 of U and F, S F), per field both sides' indicators
-    (two fma, a min and a compare each) and the value sum (a multiply and an fma,
-    then the window scaling), the back-projection and the flux difference."""
+    """Top form of one face (common path): node quantities and the top
+    differences of one node (the essential work; a kernel that forms them per
+    face from the window does three nodes' worth), the symmetric stencil of F,
+    the Roe state, seven projections (D_0, D_1, D_2 of U and F, S F), per field
+    both sides' indicators (two fma, a min and a compare each) and the value sum
+    (a multiply and an fma, then the window scaling), the back-projection and
+    the flux difference."""
     d, sym = TOP_DIFF[order], TOP_SYM[order]
     if equation == "advection":
         # differences and stencil of u; per side two a*D products (mul + fma), min,
@@ -108,10 +111,9 @@ def sweep_bytes(equation: str, kernel: str, stage: int) -> int:
 
 
 def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
-    """Algorithmic flops per cell of one launch (x-sweeps: top form; y-sweep:
-    window form)."""
+    """Algorithmic flops per cell of one launch (top form)."""
     nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
-    f = face_flops_top(equation, order) if kernel == "x" else face_flops(equation, order)
+    f = face_flops_top(equation, order)
     if stage == 0:
         return f
     if equation == "euler2d":
@@ -120,8 +122,8 @@ def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
 
 
 def cell_update_flops(equation: str, order: int) -> int:
-    faces = face_flops_top(equation, order) + (face_flops(equation, order) if equation == "euler2d" else 0)
-    return 3 * faces + sum(stage_cell_flops(equation, s) for s in (1, 2, 3))
+    dims = 2 if equation == "euler2d" else 1
+    return 3 * dims * face_flops_top(equation, order) + sum(stage_cell_flops(equation, s) for s in (1, 2, 3))
 
 
 def cell_update_bytes(equation: str) -> int:
