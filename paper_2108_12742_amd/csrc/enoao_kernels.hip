@@ -404,14 +404,8 @@ __device__ __forceinline__ double rk_combine(double in, double base, double dt, 
     else return fma(1.0 / 3.0, base, (2.0 / 3.0) * y);
 }
 
-// 2D stages: the x-sweep folds its part of L into the combine,
-//   z = rk_combine(in, base, dt, L_x),
-// and the y-sweep finishes it with its part, u_out = z + w dt L_y, w = 1, 1/4,
-// 2/3 for stages 1, 2, 3 (the same combine with L = L_x + L_y, up to rounding).
-template <int MODE> __device__ __forceinline__ double rk_weight()
-{
-    return MODE == M_S1 ? 1.0 : (MODE == M_S2 ? 0.25 : 2.0 / 3.0);
-}
+// 2D stages: the x-sweep writes its part of L, the y-sweep adds its own and
+// applies the combine to L = L_x + L_y.
 
 // Per-instance values of one sweep launch.  A workgroup walks a contiguous
 // chunk of the tile list, so it reloads them only when the walk crosses into
@@ -488,13 +482,13 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 // registers while tile t is reconstructed, so the memory latency hides behind
 // the face arithmetic.  Waves per SIMD the register allocation must allow
 // (measured: three for the x-sweep, whose LDS fits three workgroups per CU,
-// except the 2D stages 2 and 3 and order 7, which spill at three; two for the
-// y-sweep, whose LDS fits two).
+// except order 7, which spills at three; two for the y-sweep, whose LDS fits
+// two).
 #ifndef ENOAO_X_WAVES_PER_EU
 #define ENOAO_X_WAVES_PER_EU 3
 #endif
-#ifndef ENOAO_X23_WAVES_PER_EU
-#define ENOAO_X23_WAVES_PER_EU 2  // 2D stages 2 and 3 (they hold u^n as well) and order 7
+#ifndef ENOAO_X7_WAVES_PER_EU
+#define ENOAO_X7_WAVES_PER_EU 2  // order 7 (spills at three)
 #endif
 #ifndef ENOAO_Y_WAVES_PER_EU
 #define ENOAO_Y_WAVES_PER_EU 2
@@ -559,7 +553,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
 #pragma unroll
         for (int q = 0; q < NC; ++q) pre.U[j][q] = rowp[q * plane + x];
     }
-    if constexpr (MODE == M_S2 || MODE == M_S3) {
+    if constexpr ((MODE == M_S2 || MODE == M_S3) && EQ != EULER2D) {
         const int x = min(sx + lane, nx - 1);
         const GMEM double *b = v.base + (long long)row * nx + x;
 #pragma unroll
@@ -568,9 +562,8 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
 }
 
 template <int EQ, int ORDER, int MODE, bool REC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 7 || (EQ == EULER2D && (MODE == M_S2 || MODE == M_S3))
-                                                    ? ENOAO_X23_WAVES_PER_EU
-                                                    : ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 7 ? ENOAO_X7_WAVES_PER_EU
+                                                                  : ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
@@ -673,13 +666,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
 #pragma unroll
                 for (int q = 0; q < NC; ++q)
                     Lc[q] = -(fh[(q * XW_SEGS + wseg) * XW_FACES + lane + 1] - fh[(q * XW_SEGS + wseg) * XW_FACES + lane]) * v.idx;
-                if constexpr (MODE == M_RHS) {
+                if constexpr (!FULL) {  // L (rhs) or, in 2D, its x-part
 #pragma unroll
                     for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = Lc[q];
-                } else if constexpr (!FULL) {  // 2D stage: x-part of the combine
-#pragma unroll
-                    for (int q = 0; q < NC; ++q)
-                        v.lx[q * plane + o] = rk_combine<MODE>(L[q * XW_SEGS * NNP + lane + G], base[q], v.dt, Lc[q]);
                 } else {
                     double Un[NC];
 #pragma unroll
@@ -744,13 +733,14 @@ template <int G, int YW> struct YBuf {
 
 template <int G, int YW> struct YPre {
     double U[YBuf<G, YW>::J][4];
-    double lx[4];  // x-part of L (rhs) or of the stage combine at the lane's cell
+    double lx[4];    // x-part of L at the lane's cell
+    double base[4];  // u^n at the lane's cell (stages 2 and 3)
 };
 
 // a lane's global operands of one y tile: the strip nodes it stages (all rows
-// for the first tile of a walk, rows FRESH.. for the others) and the x-part at
-// its cell (lanes past the grid's edge read a clamped, in-bounds address whose
-// value goes unused).
+// for the first tile of a walk, rows FRESH.. for the others), the x-part of L
+// and, for stages 2 and 3, u^n at its cell (lanes past the grid's edge read a
+// clamped, in-bounds address whose value goes unused).
 template <int MODE, int G, int YW>
 __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c, bool first, int wv, int lane,
                                            YPre<G, YW> &pre)
@@ -777,6 +767,10 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
     const long long o = (long long)y * nx + col;
 #pragma unroll
     for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
+    if constexpr (MODE == M_S2 || MODE == M_S3) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pre.base[q] = v.base[q * plane + o];
+    }
 }
 
 // one face of a y strip into the face buffer (and the selection record)
@@ -814,9 +808,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
     __shared__ double lds[NW * NQ * QS];
     __shared__ double fh[NW * NC * (CELLS + 1) * YW];
     __shared__ double red[NW * 8];
-    // epilogue operand of the tile (x-part), staged from the prefetch registers
-    // so it is not held through the face arithmetic
+    // epilogue operands of the tile (x-part of L; u^n for stages 2 and 3),
+    // staged from the prefetch registers so they are not held through the face
+    // arithmetic
+    constexpr bool BASE = MODE == M_S2 || MODE == M_S3;
     __shared__ double elx[NC * BLOCK];
+    __shared__ double ebase[BASE ? NC * BLOCK : 1];
     const int perm[4] = {0, 2, 1, 3};
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -868,6 +865,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
             }
 #pragma unroll
             for (int q = 0; q < NC; ++q) elx[q * BLOCK + tid] = pre.lx[q];
+            if constexpr (BASE) {
+#pragma unroll
+                for (int q = 0; q < NC; ++q) ebase[q * BLOCK + tid] = pre.base[q];
+            }
             const YCur cn = y_advance(c, v.per_row);
             const bool next_first = cn.ty == 0;
             if (tile + 1 < tend) y_prefetch<MODE, G, YW>(v, cn, next_first, wv, lane, pre);
@@ -896,11 +897,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_W
 #pragma unroll
                     for (int q = 0; q < NC; ++q) v.lx[q * plane + o] = elx[q * BLOCK + tid] + Ly[q];
                 } else {
-                    const double wdt = rk_weight<MODE>() * v.dt;
+                    // stage input at the cell: buffer row fl + G (quantity perm[q]
+                    // holds natural component q)
                     double Un[NC];
 #pragma unroll
                     for (int q = 0; q < NC; ++q) {
-                        Un[q] = fma(wdt, Ly[q], elx[q * BLOCK + tid]);
+                        const double uin = W[perm[q] * QS + (fl + G) * YW + cc];
+                        const double base = BASE ? ebase[q * BLOCK + tid] : 0.0;
+                        Un[q] = rk_combine<MODE>(uin, base, v.dt, elx[q * BLOCK + tid] + Ly[q]);
                         v.out[q * plane + o] = Un[q];
                     }
                     mx.add(Un, P.gamma, v.idx, v.idy);

@@ -90,10 +90,10 @@ MAXIMA_FLOPS = {"advection": 1, "euler1d": 16, "euler2d": 28}  # per-field wave-
 
 def stage_cell_flops(equation: str, stage: int) -> int:
     """Per-cell work of a stage besides the faces, summed over the stage's kernels:
-    1D: combine + maxima in the x-sweep; 2D: the x-sweep combines with its part of L,
-    the y-sweep adds its part (one fma per component) and takes the maxima."""
+    1D: combine + maxima in the x-sweep; 2D: the y-sweep adds L_x and L_y (one add
+    per component), combines and takes the maxima."""
     nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
-    extra = 2 * nc if equation == "euler2d" else 0
+    extra = nc if equation == "euler2d" else 0
     return combine_flops(nc, stage) + MAXIMA_FLOPS[equation] + extra
 
 
@@ -101,12 +101,13 @@ def sweep_bytes(equation: str, kernel: str, stage: int) -> int:
     """Compulsory HBM bytes per cell of one launch (stage 0: evaluation of L only).
 
     1D 'x': read the stage input (+ u^n for stages 2, 3), write the stage output.
-    2D 'x': read the stage input (+ u^n for stages 2, 3), write the x-part z.
-    2D 'y': read the stage input and z, write the stage output (rhs: L)."""
+    2D 'x': read the stage input, write L_x.
+    2D 'y': read the stage input and L_x (+ u^n for stages 2, 3), write the stage
+    output (rhs: L)."""
     nc = {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
     w = 8 * nc
-    if equation == "euler2d" and kernel == "y":
-        return 3 * w
+    if equation == "euler2d":
+        return 2 * w if kernel == "x" else 3 * w + (w if stage > 1 else 0)
     return 2 * w + (w if stage > 1 else 0)
 
 
@@ -117,7 +118,7 @@ def sweep_flops(equation: str, order: int, kernel: str, stage: int) -> int:
     if stage == 0:
         return f
     if equation == "euler2d":
-        return f + (combine_flops(nc, stage) if kernel == "x" else 2 * nc + MAXIMA_FLOPS[equation])
+        return f if kernel == "x" else f + nc + combine_flops(nc, stage) + MAXIMA_FLOPS[equation]
     return f + combine_flops(nc, stage) + MAXIMA_FLOPS[equation]
 
 
