@@ -1,7 +1,8 @@
 """GPU parity on the discontinuous workloads of Sections 4.1 and 4.2: the advected
 Jiang-Shu combination profile (Gaussians, square wave, triangle, half ellipse) and the
 Lax shock tube.  Near discontinuities the lower-order candidates are selected and the
-wave-uniform early exit is rarely taken, so these runs exercise the full selection path.
+wave-uniform top-candidate shortcut is rarely taken, so these runs exercise the full
+selection path.
 
 Per step: from the oracle's state, the GPU's L (with selections) and one GPU step match
 the oracle.  Whole runs: step counts and end times match, and the GPU's error against the
