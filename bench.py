@@ -168,6 +168,43 @@ def bench_resident(steps=100, count=512, n_hi=1700):
     return res
 
 
+def bench_order7(n=2048, steps=30, warmup=2):
+    """The main 2D workload at order 7 (ENO-AO7, Section 3.3's nine candidates), with the
+    default launch shape: throughput, per-kernel mean times and each sweep's roofline."""
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import roofline as R
+    from paper_2108_12742_amd import workloads as W
+    inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
+    plan = E.enoao_plan_create(E.problem_from_instance(inst, order=7))
+    u0 = torch.from_numpy(inst.u0).cuda()
+    u = u0.clone()
+    E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=warmup)
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    E.enoao_profile(plan, True)
+    t0 = time.perf_counter()
+    _, k = E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = E.enoao_profile_read(plan)
+    E.enoao_plan_check(plan)
+    assert k == steps, (k, steps)
+    cells = n * n
+    kernels = {}
+    for kind, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        entry = {"mean_ms": round(ms, 4), "launches": cnt}
+        if kind.startswith("sweep"):
+            kern, stage = kind[6], int(kind[-1])
+            entry["roofline"] = R.roofline_entry(cells * R.sweep_flops("euler2d", 7, kern, stage),
+                                                 cells * R.sweep_bytes("euler2d", kern, stage), ms * 1e-3)
+        kernels[kind] = entry
+    return {"workload": f"euler2d-quadrants-{n}x{n}-ao7", "steps": steps, "value": cells * steps / el,
+            "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps, "kernels": kernels}
+
+
 def bench_discontinuous(order=5):
     """Discontinuous workloads of the paper at its meshes: the combination profile
     (advection, N = 400, t = 20) and the Lax tube (1D Euler, N = 200, t = 0.26), each a
@@ -372,6 +409,8 @@ def main():
         out["batched"] = bench_batched()
         print("[bench] batched leg done; LDS-resident small members ...", file=sys.stderr, flush=True)
         out["batched_small"] = bench_resident()
+        print("[bench] order 7 ...", file=sys.stderr, flush=True)
+        out["order7"] = bench_order7(n=n)
         print("[bench] discontinuous workloads ...", file=sys.stderr, flush=True)
         out["discontinuous"] = bench_discontinuous()
         print("[bench] served leg ...", file=sys.stderr, flush=True)

@@ -233,7 +233,7 @@ enoao_status enoao_plan_set_launch(enoao_plan *plan, int32_t workgroups_per_cu);
 enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_cu);
 
 /* Tile width of the 2D y-sweep: columns per wave strip, 4 or 8 (0 = the
- * default, 8).  A y tile is 4 strips wide and 64/w cell rows tall; wider
+ * default: 8 for order 5, 4 for order 7).  A y tile is 4 strips wide and 64/w cell rows tall; wider
  * strips load longer row segments per wave, narrower ones stage fewer halo
  * rows per face.  The plan's or batch's tile lists are rebuilt (this
  * synchronises stream) and its captured graph is dropped.  1D problems have

@@ -105,7 +105,7 @@ struct Runtime {
     hipStream_t cap = nullptr;
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
     int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
-    int yw = YW_DEFAULT;  // columns per wave strip of the y-sweep tiles (4 or 8)
+    int yw = 8;  // columns per wave strip of the y-sweep tiles (4 or 8); set from the order at creation
     // every member 1D and small enough for the LDS-resident solver (res_lds
     // dynamic LDS bytes per workgroup); controlled steps then run there
     bool resident = false;
@@ -185,6 +185,7 @@ struct Runtime {
         }
         eq = ps[0].equation;
         order = ps[0].order;
+        yw = yw_default(order);
         nc = ncomp_of(eq);
         n = count;
         n_cap = count;
@@ -603,13 +604,13 @@ enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved)
 enoao_status enoao_plan_set_tiles(enoao_plan *plan, int32_t y_strip_columns, void *stream)
 {
     if (!plan || (y_strip_columns != 0 && y_strip_columns != 4 && y_strip_columns != 8)) return ENOAO_EINVAL;
-    return plan->rt.set_ytiles(y_strip_columns ? y_strip_columns : YW_DEFAULT, (hipStream_t)stream);
+    return plan->rt.set_ytiles(y_strip_columns ? y_strip_columns : yw_default(plan->rt.order), (hipStream_t)stream);
 }
 
 enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, void *stream)
 {
     if (!batch || (y_strip_columns != 0 && y_strip_columns != 4 && y_strip_columns != 8)) return ENOAO_EINVAL;
-    return batch->rt.set_ytiles(y_strip_columns ? y_strip_columns : YW_DEFAULT, (hipStream_t)stream);
+    return batch->rt.set_ytiles(y_strip_columns ? y_strip_columns : yw_default(batch->rt.order), (hipStream_t)stream);
 }
 
 enoao_status enoao_set_resident(int32_t enable)
@@ -951,6 +952,7 @@ enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, s
     };
     r.eq = like->equation;
     r.order = like->order;
+    r.yw = yw_default(r.order);
     r.nc = ncomp_of(r.eq);
     r.gamma = like->gamma;
     r.delta = like->delta;

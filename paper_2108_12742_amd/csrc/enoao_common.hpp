@@ -21,7 +21,10 @@ constexpr int XW_SEGS = 4;
 // y-sweep tiles: each of the 4 waves of a workgroup owns a strip of w columns
 // (w = 4 or 8, chosen per plan or batch) and w * 64/w = 64 lanes; a tile is
 // 4w columns x 64/w cell rows.
-constexpr int YW_DEFAULT = 8;
+// Default strip width per order (measured on the 2048^2 Euler workloads: 8 for
+// order 5; 4 for order 7, whose wider strips stage more halo rows per face
+// than its one wave per SIMD can hide).
+constexpr int yw_default(int order) { return order == 7 ? 4 : 8; }
 constexpr int yt_cells(int w) { return 64 / w; }
 constexpr int yt_cols(int w) { return 4 * w; }
 constexpr int BLOCK = 256;

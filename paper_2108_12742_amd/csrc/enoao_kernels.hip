@@ -483,7 +483,8 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 // the face arithmetic.  Waves per SIMD the register allocation must allow
 // (measured: three for the x-sweep, whose LDS fits three workgroups per CU,
 // except order 7, which spills at three; two for the y-sweep, whose LDS fits
-// two).
+// two, except order 7, which spills to scratch at two and runs faster at one
+// with its whole working set in registers).
 #ifndef ENOAO_X_WAVES_PER_EU
 #define ENOAO_X_WAVES_PER_EU 3
 #endif
@@ -492,6 +493,9 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 #endif
 #ifndef ENOAO_Y_WAVES_PER_EU
 #define ENOAO_Y_WAVES_PER_EU 2
+#endif
+#ifndef ENOAO_Y7_WAVES_PER_EU
+#define ENOAO_Y7_WAVES_PER_EU 1  // order 7 (spills at two)
 #endif
 
 // a wave's segment within its instance: grid line and segment index along it
@@ -798,7 +802,8 @@ __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KPara
 }
 
 template <int ORDER, int MODE, bool REC, int YW>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ENOAO_Y_WAVES_PER_EU))) void sweep_y(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 7 ? ENOAO_Y7_WAVES_PER_EU
+                                                                  : ENOAO_Y_WAVES_PER_EU))) void sweep_y(KParams P)
 {
     constexpr int NC = 4, NQ = 12, NW = BLOCK / 64;
     constexpr int H = ReconTraits<ORDER>::H, G = H + 1;
