@@ -20,11 +20,18 @@ import time
 import numpy as np
 
 METRIC = "cell-updates/s + % HBM/FP64 roofline; batched vs plain; p50/p99 latency"
-KERNEL_NAMES = {  # profile kind -> kernel symbol as rocprofv3 prints it (order 5, no record, default tiles)
-    "sweep_x_s1": "enoao::sweep_x<2, 5, 1, false>", "sweep_x_s2": "enoao::sweep_x<2, 5, 2, false>",
-    "sweep_x_s3": "enoao::sweep_x<2, 5, 3, false>", "sweep_y_s1": "enoao::sweep_y<5, 1, false, 8>",
-    "sweep_y_s2": "enoao::sweep_y<5, 2, false, 8>", "sweep_y_s3": "enoao::sweep_y<5, 3, false, 8>",
-}
+# y-sweep strip width the library takes by default for each order (the same
+# launch as enoao_plan_set_tiles with 0)
+DEFAULT_STRIP_COLUMNS = {5: 8, 7: 4}
+
+
+def kernel_symbol(kind, order, y_strip_columns):
+    """Kernel symbol as rocprofv3 prints it for a profile kind ("sweep_x_s2", ...) of a
+    2D plan without selection record."""
+    stage = int(kind[-1])
+    if kind.startswith("sweep_x"):
+        return f"enoao::sweep_x<2, {order}, {stage}, false>"
+    return f"enoao::sweep_y<{order}, {stage}, false, {y_strip_columns}>"
 
 
 def kernel_sources_hash():
@@ -42,16 +49,17 @@ def kernel_sources_hash():
 
 def measured_traffic(symbol, workload):
     """HBM bytes per launch of `symbol` from the committed rocprofv3 byte counters
-    (profiles/traffic.json), or None when the kernels changed since they were taken."""
+    (profiles/traffic.json, per workload), or None when the kernels changed since
+    they were taken."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_sources_hash() or t.get("workload") != workload:
+    if t.get("source_hash") != kernel_sources_hash():
         return None
-    v = t.get("bytes_per_launch", {}).get(symbol)
+    v = t.get("workloads", {}).get(workload, {}).get("bytes_per_launch", {}).get(symbol)
     return None if v is None else round(v)
 
 
@@ -175,6 +183,7 @@ def bench_order7(n=2048, steps=30, warmup=2):
     from paper_2108_12742_amd import enoao as E
     from paper_2108_12742_amd import roofline as R
     from paper_2108_12742_amd import workloads as W
+    workload = f"euler2d-quadrants-{n}x{n}-ao7"
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
     plan = E.enoao_plan_create(E.problem_from_instance(inst, order=7))
     u0 = torch.from_numpy(inst.u0).cuda()
@@ -198,10 +207,12 @@ def bench_order7(n=2048, steps=30, warmup=2):
         entry = {"mean_ms": round(ms, 4), "launches": cnt}
         if kind.startswith("sweep"):
             kern, stage = kind[6], int(kind[-1])
+            entry["symbol"] = kernel_symbol(kind, 7, DEFAULT_STRIP_COLUMNS[7])
             entry["roofline"] = R.roofline_entry(cells * R.sweep_flops("euler2d", 7, kern, stage),
                                                  cells * R.sweep_bytes("euler2d", kern, stage), ms * 1e-3)
+            entry["roofline"]["traffic"] = measured_traffic(entry["symbol"], workload)
         kernels[kind] = entry
-    return {"workload": f"euler2d-quadrants-{n}x{n}-ao7", "steps": steps, "value": cells * steps / el,
+    return {"workload": workload, "steps": steps, "value": cells * steps / el,
             "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps, "kernels": kernels}
 
 
@@ -330,7 +341,7 @@ def main():
     ep = E.problem_from_instance(inst, order=args.order)
     u0 = torch.from_numpy(inst.u0).cuda()
     u = u0.clone()
-    launch, tuner = (0, 8), None
+    launch, tuner = (0, DEFAULT_STRIP_COLUMNS[args.order]), None
     if not args.no_tune:  # launch shape (workgroups per CU, y strip columns) from the autotuner
         from paper_2108_12742_amd import tune as T
         launch, tuner = T.tune_batch([ep], [u], steps=3)
@@ -366,13 +377,12 @@ def main():
             fl = cells * R.sweep_flops("euler2d", args.order, kern, stage)
             by = cells * R.sweep_bytes("euler2d", kern, stage)
             entry["roofline"] = R.roofline_entry(fl, by, ms * 1e-3)
-            sym = KERNEL_NAMES.get(kind) if args.order == 5 else None
-            entry["symbol"] = sym.replace(", 8>", f", {launch[1]}>") if sym else None
+            entry["symbol"] = kernel_symbol(kind, args.order, launch[1])
             if best is None or ms * cnt > best[1]:
                 best = (kind, ms * cnt)
         kernels[kind] = entry
     roof = dict(kernels[best[0]]["roofline"])
-    roof["kernel"] = kernels[best[0]].get("symbol") or best[0]
+    roof["kernel"] = kernels[best[0]]["symbol"]
     workload = f"euler2d-quadrants-{n}x{n}-ao{args.order}"
     roof["traffic"] = measured_traffic(roof["kernel"], workload)
     out = {
