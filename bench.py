@@ -309,15 +309,19 @@ def main():
                     help="skip the batched (512 1D members, batched vs plain) and served (Poisson arrivals) legs")
     ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--no-tune", action="store_true",
-                    help="main workload at the default launch shape (occupancy, 8-column y strips)")
+                    help="main workload at the default launch shape (occupancy; y strips of the "
+                         "order's default width, or --y-strip-columns)")
+    ap.add_argument("--y-strip-columns", type=int, default=0, choices=(0, 4, 8),
+                    help="with --no-tune: y-sweep strip width (0 = the order's default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
-              "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the kernels are measured on a single GPU "
+              "(sharding across GPUs is described in the design notes, not implemented); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -341,7 +345,7 @@ def main():
     ep = E.problem_from_instance(inst, order=args.order)
     u0 = torch.from_numpy(inst.u0).cuda()
     u = u0.clone()
-    launch, tuner = (0, DEFAULT_STRIP_COLUMNS[args.order]), None
+    launch, tuner = (0, args.y_strip_columns or DEFAULT_STRIP_COLUMNS[args.order]), None
     if not args.no_tune:  # launch shape (workgroups per CU, y strip columns) from the autotuner
         from paper_2108_12742_amd import tune as T
         launch, tuner = T.tune_batch([ep], [u], steps=3)

@@ -287,3 +287,33 @@ def test_c2_full_size_rhs():
     Lr, selr, tier = O.rhs(op, inst.u0, with_selection=True)
     mask = PT.compare_selection(op, sel, selr, tier)
     PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what="L")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("order", [5, 7])
+def test_c2_full_size_solve_step(order):
+    """The 2D Euler workload at its full size (2048^2, quadrant data, the benchmark's seed):
+    one CFL-controlled SSP-RK3 step through enoao_solve -- the captured graph of stage
+    kernels without selection record that the benchmark times, at the default launch
+    shape -- against the oracle's time loop; then the same step at another launch shape
+    (resident workgroups per CU and y strip width), bitwise equal."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.quadrants(W.QUADRANT_BENCH_SEED, 2048)
+    ep = E.problem_from_instance(inst, order=order)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, inst.u0)
+    t, n = E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=1)
+    E.enoao_plan_check(plan)
+    other = E.enoao_plan_create(ep)
+    E.enoao_plan_set_launch(other, 2)
+    E.enoao_plan_set_tiles(other, 4 if order == 5 else 8)
+    u2 = PT.to_dev(torch, inst.u0)
+    E.enoao_solve(other, u2, 1e30, cfl=0.3, max_steps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u2), "launch shape changed the result"
+    print(f"oracle step at 2048^2, order {order} ...", flush=True)
+    ur, tr, nr = O.solve(op, inst.u0, 1e30, cfl=0.3, max_steps=1)
+    assert n == nr == 1 and abs(t / tr - 1) <= 1e-14
+    PT.assert_close_by_component(u.cpu().numpy(), ur, what=f"u after one step (order {order})")
