@@ -74,13 +74,17 @@ enum { ENOAO_BC_PERIODIC = 0, ENOAO_BC_TRANSMISSIVE = 1 };
 /* flags */
 enum { ENOAO_F_RECORD_SELECTION = 1u };
 
+/* Largest nx or ny (2^31 - 1024): node indices a tile forms beyond the last
+ * node (its halo and the lanes past the end) stay within 32-bit range. */
+#define ENOAO_MAX_EXTENT 2147482624
+
 /* Caller-filled description of one problem; copied by the create calls. */
 typedef struct enoao_problem {
     uint32_t struct_size; /* sizeof(enoao_problem): ABI version check                  */
     int32_t equation;     /* ENOAO_ADVECTION | ENOAO_EULER1D | ENOAO_EULER2D            */
     int32_t order;        /* designed order: 5 or 7 (Section 3.2 candidate lists)       */
-    int32_t nx;           /* nodes along x, >= 1                                        */
-    int32_t ny;           /* nodes along y, 1 for the 1D equations                      */
+    int32_t nx;           /* nodes along x, 1 .. ENOAO_MAX_EXTENT                       */
+    int32_t ny;           /* nodes along y, 1 for the 1D equations; nx*ny <= 2^31       */
     int32_t reserved0;    /* must be 0                                                  */
     double x_lo, x_hi;    /* dx = (x_hi - x_lo)/nx                                      */
     double y_lo, y_hi;    /* dy = (y_hi - y_lo)/ny (2D only)                            */

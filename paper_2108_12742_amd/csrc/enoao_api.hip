@@ -41,6 +41,7 @@ enoao_status check_problem(const enoao_problem *p)
     if (p->equation != ADVECTION && !(p->gamma > 1.0)) return ENOAO_EINVAL;
     if (p->equation == ADVECTION && !(std::isfinite(p->adv_speed) && p->adv_speed != 0.0)) return ENOAO_EINVAL;
     if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return ENOAO_EINVAL;
+    if (p->nx > ENOAO_MAX_EXTENT || p->ny > ENOAO_MAX_EXTENT) return ENOAO_EINVAL;
     if ((long long)p->nx * p->ny > (1ll << 31)) return ENOAO_EINVAL;
     return ENOAO_OK;
 }

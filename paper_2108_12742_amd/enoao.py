@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libenoao.so")
 ADVECTION, EULER1D, EULER2D = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 F_RECORD_SELECTION = 1
+MAX_EXTENT = 2**31 - 1024  # largest nx or ny (ENOAO_MAX_EXTENT); nx * ny <= 2**31
 NCOMP = {ADVECTION: 1, EULER1D: 3, EULER2D: 4}
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONPHYSICAL = range(6)
 _EQ = {"advection": ADVECTION, "euler1d": EULER1D, "euler2d": EULER2D}
