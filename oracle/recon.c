@@ -31,7 +31,12 @@
  * the fallback IS_k against the minimum) is within TIE_EPS of the forward-error
  * scale of the indicators involved, except for exact ties between two
  * indicators realised by one and the same undivided difference (the pairs of
- * identical rows in the delta tables), which every implementation reproduces.
+ * identical rows in the delta tables), which every implementation reproduces,
+ * and except for an indicator that is zero because one of its delta rows reads
+ * only equal values: a difference of equal values is exactly zero however it is
+ * evaluated, so the comparison with delta >= 0 is exact (such zeros are common:
+ * flat regions of piecewise constant data, or the minus-side flux of advection
+ * with a > 0, which is zero at every node).
  */
 #include <math.h>
 #include <stddef.h>
@@ -100,7 +105,16 @@ static double lin(const int *c, int nt, const double *f, const double *mag, int 
 typedef struct {
     double flux, dL, dR, sL, sR, is, s;
     int side;          /* 0: IS realised by delta_L, 1: by delta_R */
+    int flat;          /* the nodes one of the delta rows reads hold equal values */
 } eval_t;
+
+/* whether f[a .. b] are all equal */
+static int all_equal(const double *f, int a, int b)
+{
+    for (int t = a + 1; t <= b; ++t)
+        if (f[t] != f[a]) return 0;
+    return 1;
+}
 
 static void eval_candidates(int order, const double *f, const double *mag, eval_t *ev)
 {
@@ -111,6 +125,7 @@ static void eval_candidates(int order, const double *f, const double *mag, eval_
         double fs;
         ev[k].flux = lin(c->fc, c->m + c->n + 1, f, mag, j - c->m, &fs) / (double)c->den;
         if (c->nd == 0) {
+            ev[k].flat = all_equal(f, j - 2, j) || all_equal(f, j, j + 2);
             /* S_j^j: delta_L = (|f_j - f_{j-1}| + |f_{j-1} - f_{j-2}|)/2, delta_R mirrored */
             ev[k].dL = (fabs(f[j] - f[j - 1]) + fabs(f[j - 1] - f[j - 2])) / 2.0;
             ev[k].dR = (fabs(f[j] - f[j + 1]) + fabs(f[j + 1] - f[j + 2])) / 2.0;
@@ -122,6 +137,7 @@ static void eval_candidates(int order, const double *f, const double *mag, eval_
                 ev[k].sR = (fabs(f[j]) + 2.0 * fabs(f[j + 1]) + fabs(f[j + 2])) / 2.0;
             }
         } else {
+            ev[k].flat = all_equal(f, j - c->m - 1, j + c->n) || all_equal(f, j - c->m, j + c->n + 1);
             ev[k].dL = fabs(lin(c->dl, c->nd, f, mag, j - c->m - 1, &ev[k].sL));
             ev[k].dR = fabs(lin(c->dr, c->nd, f, mag, j - c->m, &ev[k].sR));
         }
@@ -178,7 +194,8 @@ int ref_reconstruct(int order, const double *f, const double *mag, double delta,
     /* First principle: walk the candidates from the highest priority down and
      * take the first whose indicator does not exceed delta. */
     for (int k = K - 1; k >= 0; --k) {
-        if (fabs(ev[k].is - delta) <= TIE_EPS * ev[k].s) near = 1;
+        const int exact_zero = ev[k].is == 0.0 && ev[k].flat;
+        if (fabs(ev[k].is - delta) <= TIE_EPS * ev[k].s && !exact_zero) near = 1;
         if (ev[k].is <= delta) { chosen = k; break; }
     }
     /* Second principle: the smallest indicator; equal minima go to the

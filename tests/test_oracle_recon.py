@@ -257,3 +257,36 @@ def test_structural_tie_not_flagged():
     _, ind2 = O.candidates(5, w2)
     _, sel2, tie2 = O.reconstruct(5, w2, 1e-5)
     assert tie2 == 1
+
+
+def test_exact_zero_indicators_not_flagged():
+    """With delta = 0 the first principle compares indicators with zero.  An indicator that
+    is exactly zero because one of its delta rows reads only equal values is zero in every
+    implementation, so no flag is raised.  The oracle evaluates a row as a sum of products,
+    so equal values whose multiples round (0.3) can leave a residue where a difference
+    table gets zero: that comparison is within rounding and stays flagged, as does a zero
+    that comes from cancellation among unequal values (a fifth difference of a quartic)."""
+    for order, K in ((5, 6), (7, 9)):
+        n = 7 if order == 5 else 9
+        for w in (np.full(n, 0.25), np.zeros(n)):
+            fhat, sel, tie = O.reconstruct(order, w, 0.0)
+            assert sel == K - 1 and tie == 0 and fhat == w[0]
+        # equal values on the left row only: still an exact zero for the top candidate
+        w = np.full(n, 2.0)
+        w[-1] = 7.0
+        _, ind = O.candidates(order, w)
+        assert ind[K - 1] == 0.0
+        _, sel, tie = O.reconstruct(order, w, 0.0)
+        assert sel == K - 1 and tie == 0
+    w = np.full(7, 0.3)
+    _, ind = O.candidates(5, w)
+    assert ind[5] != 0.0
+    assert O.reconstruct(5, w, 0.0)[2] == 1
+    # quartic on small integers: every fifth difference cancels to an exact zero, but from
+    # unequal values, so the comparison with delta = 0 is flagged
+    x = np.arange(-3.0, 4.0)
+    w = x ** 4 - 2 * x ** 3 + x
+    _, ind = O.candidates(5, w)
+    assert ind[5] == 0.0
+    _, sel, tie = O.reconstruct(5, w, 0.0)
+    assert sel == 5 and tie == 1
