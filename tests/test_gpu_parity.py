@@ -317,3 +317,100 @@ def test_c2_full_size_solve_step(order):
     ur, tr, nr = O.solve(op, inst.u0, 1e30, cfl=0.3, max_steps=1)
     assert n == nr == 1 and abs(t / tr - 1) <= 1e-14
     PT.assert_close_by_component(u.cpu().numpy(), ur, what=f"u after one step (order {order})")
+
+
+def _smooth_1d(n=126):
+    """1D Euler data with no flat stretch (smooth profiles and one jump in density)."""
+    x = W.nodes(-1.0, 1.0, n)
+    rho = 1.0 + 0.3 * np.sin(np.pi * x) + 0.5 * (x > 0.2)
+    return W.conserved_1d(rho, 0.4 * np.cos(2 * np.pi * x), 1.0 + 0.2 * np.sin(3 * np.pi * x + 0.4)).reshape(3, 1, n)
+
+
+def _smooth_2d(nx=48, ny=40):
+    """2D Euler data with no flat stretch: smooth fields plus a discontinuous block,
+    periodic with period 24."""
+    t = np.arange(24) * (2.0 * np.pi / 24)
+    X, Y = np.meshgrid(t, t)
+    block = ((np.arange(24)[None, :] < 11) & (np.arange(24)[:, None] < 15)).astype(float)
+    rho = 1.0 + 0.3 * np.sin(X + 0.7) * np.cos(Y + 1.9) + 0.8 * block
+    vx = 0.4 * np.sin(Y + 0.2) + 0.2 * block
+    vy = 0.4 * np.cos(X + 2.5) - 0.3 * block
+    p = 1.0 + 0.25 * np.cos(X + Y + 1.1) + 1.5 * block
+    tab = W.conserved_2d(rho, vx, vy, p)
+    return np.tile(tab, (1, ny // 24 + 1, nx // 24 + 1))[:, :ny, :nx].copy()
+
+
+@pytest.mark.parametrize("delta", [0.0, 1.0, 1e30])
+@pytest.mark.parametrize("kind,order", [("advection", 5), ("euler1d", 5), ("euler1d", 7), ("euler2d", 5),
+                                        ("euler2d", 7)])
+def test_threshold_extremes(kind, order, delta):
+    """Selection threshold at its extremes (Section 3's two principles): delta = 0 leaves
+    the first principle to indicators that are exactly zero, so most faces take the
+    argmin of the second; delta = 1e30 always takes the top candidate (the linear
+    scheme); delta = 1 mixes both.  L with selections against the oracle (cells next to
+    flagged near ties left out), then one step where the oracle flags no tie.  The data
+    have no flat stretch: there the oracle's row sums leave rounding residues that a
+    difference table does not, and with delta = 0 every such face is a near tie."""
+    torch = PT.torch_cuda()
+    E = _E()
+    if kind == "advection":
+        inst, _ = _adv_case(131, jumps=True)
+        u0 = inst.u0
+        ep = E.problem_from_instance(inst, order=order, delta=delta, record_selection=True)
+    elif kind == "euler1d":
+        u0 = _smooth_1d()
+        ep = E.make_problem(kind, u0.shape[2], order=order, bc_x="transmissive", delta=delta,
+                            record_selection=True)
+    else:
+        u0 = _smooth_2d()
+        ep = E.make_problem(kind, u0.shape[2], u0.shape[1], order=order, delta=delta, record_selection=True)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, u0)
+    L = torch.empty_like(u)
+    E.enoao_rhs(plan, u, L)
+    sel = E.enoao_get_selection(plan)
+    Lr, selr, tier = O.rhs(op, u0, with_selection=True)
+    mask = PT.compare_selection(op, sel, selr, tier)
+    assert mask.mean() > 0.9
+    PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what=f"L (delta {delta})")
+    K = 6 if order == 5 else 9
+    if delta == 1e30:
+        assert (selr == K - 1).all() and (np.asarray(sel) == K - 1).all()
+    if delta == 0.0:
+        assert (selr != K - 1).mean() > 0.1  # the second principle decides many faces
+    if (tier != 0).any():
+        return
+    dt = 0.5 * O.cfl_dt(op, u0, 0.3)
+    E.enoao_step(plan, u, dt)
+    torch.cuda.synchronize()
+    PT.assert_close_by_component(u.cpu().numpy(), O.step(op, u0, dt), what=f"u (delta {delta})")
+
+
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("eq,shape", [("advection", (1, 1, 70)), ("euler1d", (3, 1, 70)),
+                                      ("euler2d", (4, 37, 70))])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_constant_state(eq, shape, bc, order):
+    """A uniform state (moving, for Euler) is steady: every face sees the same data and
+    computes the same flux, so L is exactly zero; one step matches the oracle."""
+    torch = PT.torch_cuda()
+    E = _E()
+    nc, ny, nx = shape
+    if eq == "advection":
+        u0 = np.full(shape, 0.7)
+    elif eq == "euler1d":
+        u0 = np.broadcast_to(W.conserved_1d(1.3, 0.4, 0.9).reshape(3, 1, 1), shape).copy()
+    else:
+        u0 = np.broadcast_to(W.conserved_2d(1.3, 0.4, -0.25, 0.9).reshape(4, 1, 1), shape).copy()
+    ep = E.make_problem(eq, nx, ny, order=order, bc_x=bc, bc_y=bc)
+    op = PT.oracle_problem(ep)
+    plan = E.enoao_plan_create(ep)
+    u = PT.to_dev(torch, u0)
+    L = torch.full_like(u, float("nan"))
+    E.enoao_rhs(plan, u, L)
+    assert torch.equal(L, torch.zeros_like(L)), "L of a uniform state must vanish"
+    dt = 0.5 * O.cfl_dt(op, u0, 0.3)
+    E.enoao_step(plan, u, dt)
+    torch.cuda.synchronize()
+    PT.assert_close_by_component(u.cpu().numpy(), O.step(op, u0, dt), what="u")
