@@ -6,6 +6,10 @@ arrival; a request that can never fit is rejected), advances every admitted
 request together with the batched kernels, and retires each one when its
 last step is done.  Request states stay in HBM between steps; admissions and
 retirements happen between step rounds, while other requests are on the GPU.
+A backend may move states between host and device asynchronously: `stage`
+starts a queued request's upload while a round computes, and `retire` may hand
+back a pending result whose download overlaps later rounds; the server finishes
+a request when its result has arrived.
 
 The scheduling is independent of the device: `Server` drives any backend with
 the `Backend` methods below.  `GpuPoolBackend` is the HIP pool of the C ABI.
@@ -30,6 +34,7 @@ class Request:
     admitted: float | None = None
     finished: float | None = None
     slot: int | None = None
+    staged: object = None      # backend handle of an upload started before admission
     result: np.ndarray | None = None
     status: int = 0            # 0 ok, non-zero: non-physical state or rejected
     error: str | None = None
@@ -52,24 +57,78 @@ class Backend:
     def admit(self, problem, u0, nsteps, cfl): ...  # slot, or None when there is no room now
     def step(self, nsteps: int): ...
     def poll(self): ...                            # (done, status, steps) per slot
-    def retire(self, slot: int, shape): ...        # final state (numpy)
+    def retire(self, slot: int, shape): ...        # final state: numpy, or a Pending
+
+    def stage(self, problem, u0):
+        """Start moving u0 towards the device; the result is passed to admit in place
+        of u0.  The default keeps u0 (admit copies it)."""
+        return u0
+
+
+class Pending:
+    """A result on its way to the host."""
+
+    def ready(self) -> bool: ...
+    def result(self) -> np.ndarray: ...
+
+
+class _Download(Pending):
+    def __init__(self, host, event):
+        self.host, self.event = host, event
+
+    def ready(self):
+        return self.event.query()
+
+    def result(self):
+        self.event.synchronize()
+        return self.host.numpy()
 
 
 class GpuPoolBackend(Backend):
-    def __init__(self, like, max_members=256, arena_bytes=8 << 30, stream=None, workgroups_per_cu=0):
+    """The HIP pool.  With overlap=True, host states move through pinned memory on a
+    copy stream of their own: inputs are uploaded while a round computes and admitted
+    from the device; results are copied out of the arena on the device and downloaded
+    while later rounds compute."""
+
+    def __init__(self, like, max_members=256, arena_bytes=8 << 30, stream=None, workgroups_per_cu=0,
+                 overlap=True):
+        import torch
         from . import enoao as E
-        self.E = E
+        self.E, self.torch = E, torch
         self.stream = stream
         self.pool = E.enoao_pool_create(like, max_members, arena_bytes, stream)
         if workgroups_per_cu:
             E.enoao_pool_set_launch(self.pool, workgroups_per_cu)
         self.max_members = max_members
         self.arena_bytes = E.enoao_pool_usage(self.pool)[1]
+        self.copy = torch.cuda.Stream() if overlap else None
+
+    def _compute(self):
+        return self.stream if self.stream is not None else self.torch.cuda.current_stream()
 
     def member_bytes(self, problem):
         return self.E.enoao_pool_member_bytes(problem)
 
+    def stage(self, problem, u0):
+        if self.copy is None or not isinstance(u0, np.ndarray):
+            return u0
+        torch = self.torch
+        host = torch.empty(u0.shape, dtype=torch.float64, pin_memory=True)
+        host.numpy()[...] = u0
+        with torch.cuda.stream(self.copy):
+            dev = torch.empty(u0.shape, dtype=torch.float64, device="cuda")
+            dev.copy_(host, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        return (dev, ev, host)
+
     def admit(self, problem, u0, nsteps, cfl):
+        if isinstance(u0, tuple):
+            dev, ev, _ = u0
+            comp = self._compute()
+            comp.wait_event(ev)
+            dev.record_stream(comp)
+            u0 = dev
         return self.E.enoao_pool_admit(self.pool, problem, u0, max_steps=nsteps, cfl=cfl, stream=self.stream)
 
     def step(self, nsteps):
@@ -80,7 +139,20 @@ class GpuPoolBackend(Backend):
         return d, f, s
 
     def retire(self, slot, shape):
-        return self.E.enoao_pool_retire(self.pool, slot, shape=shape, stream=self.stream)
+        if self.copy is None:
+            return self.E.enoao_pool_retire(self.pool, slot, shape=shape, stream=self.stream)
+        torch = self.torch
+        comp = self._compute()
+        dev = torch.empty(shape, dtype=torch.float64, device="cuda")
+        self.E.enoao_pool_retire(self.pool, slot, out=dev, stream=self.stream)
+        host = torch.empty(shape, dtype=torch.float64, pin_memory=True)
+        self.copy.wait_stream(comp)
+        with torch.cuda.stream(self.copy):
+            host.copy_(dev, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        dev.record_stream(self.copy)
+        return _Download(host, ev)
 
     def close(self):
         self.E.enoao_pool_destroy(self.pool)
@@ -91,8 +163,10 @@ class Server:
     backend: Backend
     steps_per_round: int = 1
     clock: object = time.perf_counter
+    stage_ahead: int = 4       # queued requests whose upload starts while a round computes
     queue: deque = field(default_factory=deque)
     active: dict = field(default_factory=dict)   # slot -> Request
+    pending: list = field(default_factory=list)  # (Request, Pending) results on their way
     done: list = field(default_factory=list)
     rounds: int = 0
     _next_id: int = 0
@@ -113,40 +187,67 @@ class Server:
         n = 0
         while self.queue and len(self.active) < self.backend.max_members:
             r = self.queue[0]
-            slot = self.backend.admit(r.problem, r.u0, r.nsteps, r.cfl)
+            slot = self.backend.admit(r.problem, r.u0 if r.staged is None else r.staged, r.nsteps, r.cfl)
             if slot is None:
                 break
             self.queue.popleft()
-            r.slot, r.admitted = slot, self.clock()
+            r.slot, r.admitted, r.staged = slot, self.clock(), None
             self.active[slot] = r
             n += 1
         return n
 
+    def _stage(self):
+        for r in list(self.queue)[:self.stage_ahead]:
+            if r.staged is None:
+                r.staged = self.backend.stage(r.problem, r.u0)
+
+    def _finish(self, r, result):
+        r.result = result
+        r.finished = self.clock()
+        self.done.append(r)
+
+    def collect(self, wait=False):
+        """Finish the requests whose results have arrived (all of them with wait)."""
+        left = []
+        for r, p in self.pending:
+            if wait or p.ready():
+                self._finish(r, p.result())
+            else:
+                left.append((r, p))
+        self.pending = left
+
     def round(self):
-        """Admit, advance every admitted request, retire the finished ones."""
+        """Admit, advance every admitted request, retire the finished ones.  While the
+        round computes, the next queued requests are staged and arrived results are
+        collected."""
         self.admit()
         if not self.active:
+            self.collect(wait=not self.queue)
             return 0
         self.backend.step(self.steps_per_round)
         self.rounds += 1
+        self._stage()
+        self.collect()
         done, status, steps = self.backend.poll()
         finished = 0
         for slot in list(self.active):
             if done[slot] == 1 or status[slot] != 0:
                 r = self.active.pop(slot)
-                r.result = self.backend.retire(slot, r.problem.shape)
-                r.finished = self.clock()
                 r.status = int(status[slot])
                 if r.status:
                     r.error = "non-physical state"
                 elif steps[slot] != r.nsteps:
                     r.status, r.error = -2, f"stopped after {steps[slot]} of {r.nsteps} steps"
-                self.done.append(r)
+                res = self.backend.retire(slot, r.problem.shape)
+                if isinstance(res, Pending):
+                    self.pending.append((r, res))
+                else:
+                    self._finish(r, res)
                 finished += 1
         return finished
 
     def idle(self):
-        return not self.queue and not self.active
+        return not self.queue and not self.active and not self.pending
 
     def drain(self):
         while not self.idle():

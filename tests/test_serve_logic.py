@@ -123,3 +123,55 @@ def test_slot_limit():
     srv.drain()
     assert all(r.status == 0 and r.finished is not None for r in reqs)
     assert max(len(s) for s in pool.stepped) == 2
+
+
+class _LateResult(S.Pending):
+    def __init__(self, value, clock, at):
+        self.value, self.clock, self.at = value, clock, at
+
+    def ready(self):
+        return self.clock.t >= self.at
+
+    def result(self):
+        return self.value
+
+
+class AsyncFakePool(FakePool):
+    """Stages inputs (a marker the admit checks) and hands back results that arrive two
+    rounds after retirement, as the GPU backend's overlapped transfers do."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.staged = 0
+
+    def stage(self, problem, u0):
+        self.staged += 1
+        return ("staged", u0)
+
+    def admit(self, problem, u0, nsteps, cfl):
+        if isinstance(u0, tuple):
+            u0 = u0[1]
+        return super().admit(problem, u0, nsteps, cfl)
+
+    def retire(self, slot, shape):
+        return _LateResult(super().retire(slot, shape), self.clock, self.clock.t + 2.0)
+
+
+def test_overlapped_transfers():
+    """Staged uploads are admitted in FIFO order; a request finishes when its result has
+    arrived, and drain waits for the last ones."""
+    clock = Clock()
+    pool = AsyncFakePool(max_members=2, arena_bytes=1 << 30, clock=clock)
+    srv = S.Server(pool, steps_per_round=1, clock=clock, stage_ahead=2)
+    reqs = [srv.submit(*_request(10 + k, 16), nsteps=1 + k % 3) for k in range(6)]
+    srv.drain()
+    assert srv.idle() and not srv.pending
+    assert pool.staged >= 4  # requests beyond the first two waited in the queue, staged
+    assert [r.admitted for r in reqs] == sorted(r.admitted for r in reqs)
+    for r in reqs:
+        assert r.status == 0 and r.finished is not None and r.finished >= r.admitted
+        op = r.problem.oracle()
+        u = r.u0
+        for _ in range(r.nsteps):
+            u = O.step(op, u, O.cfl_dt(op, u, 0.3))
+        np.testing.assert_array_equal(r.result, u)
