@@ -755,7 +755,8 @@ enoao_status enoao_plan_check(enoao_plan *plan, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (enoao_status e = rt.read_ctrl(s)) return e;
     if (rt.h_ctrl[0].status) {
-        HIP_TRY(hipMemsetAsync(&rt.d_ctrl[0].status, 0, sizeof(int), s));
+        static const int zero = 0;  // cleared by a copy, not a memset node, in case a caller records the stream
+        HIP_TRY(hipMemcpyAsync(&rt.d_ctrl[0].status, &zero, sizeof(int), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         return ENOAO_ENONPHYSICAL;
     }

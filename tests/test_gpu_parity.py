@@ -256,6 +256,11 @@ def test_nonphysical_state_reported():
     with pytest.raises(E.EnoaoError) as ei:
         E.enoao_solve(plan, u, 0.01, cfl=0.3)
     assert ei.value.status == E.ENONPHYSICAL
+    # the device flag stays set until a check reports it once and clears it
+    with pytest.raises(E.EnoaoError) as ei:
+        E.enoao_plan_check(plan)
+    assert ei.value.status == E.ENONPHYSICAL
+    E.enoao_plan_check(plan)
 
 
 def test_invalid_arguments():
