@@ -158,3 +158,27 @@ def test_autotuner_restores_states_and_picks_a_candidate(tmp_path, monkeypatch):
         outs.append([v.cpu() for v in vs])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+@pytest.mark.slow
+def test_c3_full_batch_sampled_members():
+    """The batched workload at its full size (512 seeded 1D Euler members, N from 128 to
+    16384, sum of N about 1.9M) in one batch at the default launch shape: every member
+    takes its 5 CFL steps without a non-physical state, and sampled members (the
+    smallest, the largest and six more) match the oracle's time loop."""
+    torch = PT.torch_cuda()
+    E = _E()
+    insts = W.batch_1d(0, 512)
+    probs = [E.problem_from_instance(i) for i in insts]
+    batch = E.enoao_batch_create(probs)
+    us = [PT.to_dev(torch, i.u0) for i in insts]
+    E.enoao_batch_step(batch, us, 5, 0.3)
+    t, steps, status = E.enoao_batch_query(batch)
+    assert (steps == 5).all() and (status == 0).all()
+    sizes = np.array([i.nx for i in insts])
+    rng = np.random.default_rng(5)
+    pick = sorted({int(sizes.argmin()), int(sizes.argmax())} | {int(k) for k in rng.choice(512, 6, replace=False)})
+    for k in pick:
+        ur, tr, nr = O.solve(PT.oracle_problem(probs[k]), insts[k].u0, 1e300, cfl=0.3, max_steps=5)
+        assert nr == 5 and abs(t[k] / tr - 1) <= 1e-14
+        PT.assert_close_by_component(us[k].cpu().numpy(), ur, rtol=1e-11, what=f"member {k} (N={sizes[k]})")
