@@ -182,3 +182,30 @@ def test_c3_full_batch_sampled_members():
         ur, tr, nr = O.solve(PT.oracle_problem(probs[k]), insts[k].u0, 1e300, cfl=0.3, max_steps=5)
         assert nr == 5 and abs(t[k] / tr - 1) <= 1e-14
         PT.assert_close_by_component(us[k].cpu().numpy(), ur, rtol=1e-11, what=f"member {k} (N={sizes[k]})")
+
+
+@pytest.mark.slow
+def test_c4_served_workload_sampled_requests():
+    """The served workload at its full size (200 seeded requests, N x N with N from 128 to
+    1024, 50 steps each) submitted at once to the server with the benchmark's pool: every
+    request succeeds; sampled requests equal their solve alone bitwise, and the smallest
+    matches the oracle's time loop."""
+    torch = PT.torch_cuda()
+    E = _E()
+    from paper_2108_12742_amd import serve as S
+    _, sizes, _ = W.arrivals(1, 200, 1.0)
+    data = [W.quadrants(W.QUADRANT_BENCH_SEED, int(n)) for n in sizes]
+    probs = [E.problem_from_instance(d) for d in data]
+    srv = S.Server(S.GpuPoolBackend(probs[0], max_members=256, arena_bytes=4 << 30), steps_per_round=1)
+    reqs = [srv.submit(p, d.u0, 50) for p, d in zip(probs, data)]
+    srv.drain()
+    assert all(r.status == 0 for r in reqs), [r.error for r in reqs if r.status]
+    small = int(np.argmin(sizes))
+    rng = np.random.default_rng(9)
+    for k in sorted({small, int(np.argmax(sizes))} | {int(k) for k in rng.choice(200, 3, replace=False)}):
+        ref, _, n = _alone(torch, E, data[k], 50)
+        assert n == 50
+        np.testing.assert_array_equal(reqs[k].result, ref)
+    ur, _, nr = O.solve(PT.oracle_problem(probs[small]), data[small].u0, 1e300, cfl=0.3, max_steps=50)
+    assert nr == 50
+    PT.assert_close_by_component(reqs[small].result, ur, rtol=1e-11, what=f"request {small} (N={sizes[small]})")
