@@ -35,12 +35,15 @@ def kernel_symbol(kind, order, y_strip_columns):
 
 
 def kernel_sources_hash():
+    """sha256 (first 16 hex) of the HIP sources and of the build script that holds the
+    compiler flags: a change to either invalidates the recorded byte counters."""
     import glob
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
     files = sorted(glob.glob(os.path.join(here, "paper_2108_12742_amd", "csrc", "*.hip"))
                    + glob.glob(os.path.join(here, "paper_2108_12742_amd", "csrc", "*.hpp")))
+    files.append(os.path.join(here, "paper_2108_12742_amd", "build.py"))
     for f in files:
         with open(f, "rb") as fh:
             h.update(fh.read())
