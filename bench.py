@@ -84,10 +84,11 @@ def cpu_baseline(n_sample=2048, steps=1):
                       f"{el:.1f} s on one host core"}
 
 
-def bench_batched(steps=100, warmup=2, count=512):
+def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
     """Batched workload: `count` 1D Euler Riemann instances, N ~ LogUniform[128, 16384],
     `steps` CFL steps each (own dt per member), in one persistent launch per stage
-    (graph-captured), against the same solves launched one plan at a time."""
+    (graph-captured), against the same solves launched one plan at a time (skipped
+    with plain=False; tune=False keeps the default launch shape)."""
     import torch
     from paper_2108_12742_amd import enoao as E
     from paper_2108_12742_amd import roofline as R
@@ -97,7 +98,7 @@ def bench_batched(steps=100, warmup=2, count=512):
     probs = [E.problem_from_instance(i) for i in insts]
     u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
     states = [u.clone() for u in u0]
-    (best, yw), timing = T.tune_batch(probs, states, steps=3)
+    (best, yw), timing = T.tune_batch(probs, states, steps=3) if tune else ((0, 8), {})
     batch = E.enoao_batch_create(probs)
     E.enoao_batch_set_launch(batch, best)
     E.enoao_batch_step(batch, states, warmup, 0.3)
@@ -115,6 +116,19 @@ def bench_batched(steps=100, warmup=2, count=512):
     el = time.perf_counter() - t0
     prof = E.enoao_batch_profile_read(batch)
     cells = sum(int(p.nx) for p in probs)
+    workload = f"euler1d-riemann-batch{count}-{cells}cells-ao5"
+    ms, kind = max(((prof[k][0], k) for k in ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3")), key=lambda x: x[0])
+    stage = int(kind[-1])
+    roof = R.roofline_entry(cells * R.sweep_flops("euler1d", 5, "x", stage), cells * R.sweep_bytes("euler1d", "x", stage),
+                            ms * 1e-3)
+    roof["kernel"] = f"enoao::sweep_x<1, 5, {stage}, false>"
+    roof["traffic"] = measured_traffic(roof["kernel"], workload)
+    out = {"workload": workload, "members": count, "cells": cells, "steps": steps,
+           "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+           "members_ok": int((status == 0).sum()), "workgroups_per_cu": best,
+           "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()}, "roofline": roof}
+    if not plain:
+        return out
     # plain: one plan per instance, solved one after another on the same stream
     plans = [E.enoao_plan_create(p) for p in probs]
     plain = [u.clone() for u in u0]
@@ -128,17 +142,9 @@ def bench_batched(steps=100, warmup=2, count=512):
     torch.cuda.synchronize()
     el_plain = time.perf_counter() - t0
     identical = all(torch.equal(a, b) for a, b in zip(states, plain))
-    ms, kind = max(((prof[k][0], k) for k in ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3")), key=lambda x: x[0])
-    stage = int(kind[-1])
-    roof = R.roofline_entry(cells * R.sweep_flops("euler1d", 5, "x", stage), cells * R.sweep_bytes("euler1d", "x", stage),
-                            ms * 1e-3)
-    roof["kernel"] = f"enoao::sweep_x<1, 5, {stage}, false>"
-    return {"workload": f"euler1d-riemann-batch{count}-{cells}cells-ao5", "members": count, "cells": cells, "steps": steps,
-            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
-            "plain_value": cells * steps / el_plain, "speedup_vs_plain": el_plain / el,
-            "identical_to_plain": identical, "members_ok": int((status == 0).sum()),
-            "workgroups_per_cu": best, "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()},
-            "roofline": roof}
+    out.update({"plain_value": cells * steps / el_plain, "speedup_vs_plain": el_plain / el,
+                "identical_to_plain": identical})
+    return out
 
 
 def bench_resident(steps=100, count=512, n_hi=1700):
@@ -316,6 +322,9 @@ def main():
                          "order's default width, or --y-strip-columns)")
     ap.add_argument("--y-strip-columns", type=int, default=0, choices=(0, 4, 8),
                     help="with --no-tune: y-sweep strip width (0 = the order's default)")
+    ap.add_argument("--only-leg", choices=("batched",), default=None,
+                    help="run only this extra leg (with --steps, --warmup and --no-tune; no comparison "
+                         "against one plan per member) and print its JSON: a short run to profile")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler pass)")
@@ -343,6 +352,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_leg == "batched":
+        print(json.dumps({"batched": bench_batched(steps=args.steps, warmup=args.warmup, tune=not args.no_tune,
+                                                   plain=False)}), flush=True)
+        return
     n, K, Wu = args.n, args.steps, args.warmup
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
     ep = E.problem_from_instance(inst, order=args.order)
