@@ -143,14 +143,18 @@ struct Runtime {
     // after a synchronisation: fold the recorded pairs into the per-kind totals
     void prof_collect()
     {
+        bool failed = false;
         for (auto &pr : ev_pairs) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev_pool[pr.second], ev_pool[pr.second + 1]) == hipSuccess) {
                 prof_ms[pr.first] += ms;
                 prof_n[pr.first] += 1;
+            } else {
+                failed = true;
             }
         }
         ev_pairs.clear();
+        if (failed) (void)hipGetLastError();  // a pair without a reading is skipped, not left as an error
     }
 
     KParams params(int r_in, int r_out, int r_zero) const
@@ -718,7 +722,9 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
         const double est = std::ceil(t_final / dt_fixed);
         k = (int)std::min(256.0, std::max(1.0, est));
     } else {
-        k = 64;
+        // CFL steps: the end time may come early (the rest of a replay then only
+        // checks its flag), unless the caller bounds the step count
+        k = max_steps > 0 && max_steps <= 256 ? (int)max_steps : 64;
     }
     // the resident solver runs a call's steps in one launch (it stops by itself at
     // t_final): fewer, longer launches
@@ -902,7 +908,7 @@ enoao_status enoao_batch_step(enoao_batch *batch, double *const *u, int32_t nste
         if (enoao_status e = rt.reset_and_maxima(s)) return e;
     }
     if (nsteps == 0) return ENOAO_OK;
-    const int k = std::min(nsteps, 32);
+    const int k = std::min(nsteps, 128);
     for (int done = 0; done < nsteps; done += k) {
         if (nsteps - done < k) {
             if (enoao_status e = rt.steps(nsteps - done, true, s)) return e;
