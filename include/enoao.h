@@ -124,7 +124,10 @@ enoao_status enoao_step(enoao_plan *plan, double *u, double dt, void *stream);
  * the start of each step.  The step that would reach t_final
  * (dt >= (t_final - t)(1 - 1e-10)) is shortened to land on it exactly.
  * Synchronises stream; *t_out / *steps_out (may be NULL) receive the final
- * time and the number of steps taken. */
+ * time and the number of steps taken.  The steps run as replays of a captured
+ * HIP graph of several steps (the whole budget when max_steps <= 256, else 64
+ * CFL steps or up to 256 fixed ones per replay); the first call with a new
+ * replay length captures its graph. */
 enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl, double dt_fixed,
                          int64_t max_steps, double *t_out, int64_t *steps_out, void *stream);
 
