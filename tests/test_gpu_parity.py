@@ -419,3 +419,55 @@ def test_constant_state(eq, shape, bc, order):
     E.enoao_step(plan, u, dt)
     torch.cuda.synchronize()
     PT.assert_close_by_component(u.cpu().numpy(), O.step(op, u0, dt), what="u")
+
+
+def test_plans_on_two_streams_concurrently():
+    """Two plans advanced at the same time from two host threads, each on a stream of
+    its own (and a batch of both on a third stream), give bitwise the results of
+    running them one after the other: every call is ordered on the stream it is given
+    and the plans share no device state."""
+    import threading
+    torch = PT.torch_cuda()
+    E = _E()
+    insts = [W.quadrants(1, 300, 260), W.quadrants(3, 257, 301)]
+    probs = [E.problem_from_instance(i) for i in insts]
+    seq = []
+    for p, i in zip(probs, insts):
+        plan = E.enoao_plan_create(p)
+        u = PT.to_dev(torch, i.u0)
+        E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=12)
+        seq.append(u.cpu())
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    plans = [E.enoao_plan_create(p, stream=s) for p, s in zip(probs, streams)]
+    for plan in plans:
+        E.enoao_plan_set_launch(plan, 1)  # one workgroup per CU each: room for both at once
+    us = [PT.to_dev(torch, i.u0) for i in insts]
+    errors = []
+
+    def run(k):
+        try:
+            E.enoao_solve(plans[k], us[k], 1e30, cfl=0.3, max_steps=12, stream=streams[k])
+        except Exception as e:  # reported by the main thread
+            errors.append((k, e))
+
+    for rep in range(2):
+        for k in range(2):
+            us[k].copy_(torch.from_numpy(insts[k].u0))
+        torch.cuda.synchronize()
+        threads = [threading.Thread(target=run, args=(k,)) for k in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=60)
+        assert not any(t.is_alive() for t in threads) and not errors, errors
+        torch.cuda.synchronize()
+        for k in range(2):
+            assert torch.equal(us[k].cpu(), seq[k]), f"plan {k}, repetition {rep}"
+    s3 = torch.cuda.Stream()
+    batch = E.enoao_batch_create(probs, stream=s3)
+    vs = [PT.to_dev(torch, i.u0) for i in insts]
+    torch.cuda.synchronize()
+    E.enoao_batch_step(batch, vs, 12, 0.3, stream=s3)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert torch.equal(vs[k].cpu(), seq[k]), f"batch member {k}"
