@@ -58,3 +58,14 @@ def test_size_limits():
     assert E.enoao_workspace_bytes(E.make_problem("euler2d", 2**16, 2**15)) > 0
     assert E.enoao_workspace_bytes(E.make_problem("euler2d", 2**16, 2**15 + 1)) == 0
     assert E.enoao_workspace_bytes(E.make_problem("euler1d", 0)) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises: there is no CPU fallback."""
+    from paper_2108_12742_amd import enoao as E
+    monkeypatch.setattr(E, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(E, "_lib", None)
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        E.lib()
+    with pytest.raises(ImportError):
+        E.enoao_workspace_bytes(E.make_problem("advection", 64))
