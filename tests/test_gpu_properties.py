@@ -106,3 +106,29 @@ def test_periodic_conservation(order):
     rel = ((after - before).abs() / mag).max().item()
     print(f"conservation order {order}: max relative change {rel:.2e}", flush=True)
     assert rel <= 1e-13
+
+
+@pytest.mark.slow
+def test_long_run_deterministic_and_conservative():
+    """400 CFL steps of the 2048^2 workload, twice from the same state: the runs are
+    bitwise identical (the per-stage maxima are combined with an order-independent
+    atomic max, and every other result has one writer), the state stays physical, and
+    the conserved sums drift only at rounding level."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = _instance()
+    ep = E.problem_from_instance(inst)
+    plan = E.enoao_plan_create(ep)
+    runs = []
+    for rep in range(2):
+        u = PT.to_dev(torch, inst.u0)
+        before = u.sum(dim=(1, 2))
+        mag = u.abs().sum(dim=(1, 2))
+        t, k = E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=400)
+        E.enoao_plan_check(plan)
+        assert k == 400
+        rel = ((u.sum(dim=(1, 2)) - before).abs() / mag).max().item()
+        print(f"run {rep}: t = {t:.6g}, max relative drift of the sums {rel:.2e}", flush=True)
+        assert rel <= 1e-11
+        runs.append((t, u))
+    assert runs[0][0] == runs[1][0] and torch.equal(runs[0][1], runs[1][1])
