@@ -201,9 +201,13 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
 def bench_resident(steps=100, count=512, n_hi=1700):
     """Small 1D members: `count` Euler Riemann instances with N ~ LogUniform[128, n_hi]
     (each fits one workgroup's LDS), `steps` CFL steps, as one batch: the LDS-resident
-    solver (one launch for all steps) against the streaming persistent sweeps."""
+    solver (one launch for all steps) against the streaming persistent sweeps.  Each
+    mode is warmed up with a run of the timed length (the streaming graph is captured
+    there); the resident kernel's duration, from a second pass with HIP events, gives
+    its roofline (FP64 VALU: the state stays in LDS for the whole call)."""
     import torch
     from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import roofline as R
     from paper_2108_12742_amd import workloads as W
     insts = W.batch_1d(1, count, n_hi=n_hi)
     probs = [E.problem_from_instance(i) for i in insts]
@@ -216,21 +220,40 @@ def bench_resident(steps=100, count=512, n_hi=1700):
         try:
             b = E.enoao_batch_create(probs)
             us = [torch.from_numpy(i.u0).cuda() for i in insts]
-            E.enoao_batch_step(b, us, 2, 0.3)  # warm-up
-            E.enoao_batch_destroy(b)
-            b = E.enoao_batch_create(probs)
-            us = [torch.from_numpy(i.u0).cuda() for i in insts]
-            torch.cuda.synchronize()
+
+            def restart():
+                E.enoao_batch_reset(b)
+                for u, i in zip(us, insts):
+                    u.copy_(torch.from_numpy(i.u0))
+                torch.cuda.synchronize()
+
+            E.enoao_batch_step(b, us, steps, 0.3)  # warm-up of the timed length
+            restart()
             t0 = time.perf_counter()
             E.enoao_batch_step(b, us, steps, 0.3)
             _, nst, status = E.enoao_batch_query(b)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
+            entry = {"value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+                     "members_ok": int((status == 0).sum())}
+            if mode == "resident":
+                final = [u.clone() for u in us]
+                restart()
+                E.enoao_batch_profile(b, True)
+                E.enoao_batch_step(b, us, steps, 0.3)
+                prof = E.enoao_batch_profile_read(b)
+                E.enoao_batch_profile(b, False)
+                ms, n = prof["resident"]
+                entry["kernel_ms"] = round(ms, 4)
+                roof = R.roofline_entry(cells * steps * R.cell_update_flops("euler1d", 5),
+                                        cells * steps * R.resident_bytes("euler1d", steps), ms * 1e-3)
+                roof["kernel"] = "enoao::resident_1d<1, 5>"
+                entry["roofline"] = roof
+                us = final
         finally:
             E.enoao_set_resident(True)
         finals.append(us)
-        res[mode] = {"value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
-                     "members_ok": int((status == 0).sum())}
+        res[mode] = entry
     res["identical"] = all(torch.equal(a, b) for a, b in zip(*finals))
     res["speedup_resident"] = res["resident"]["value"] / res["streaming"]["value"]
     return res

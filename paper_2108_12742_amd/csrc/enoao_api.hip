@@ -99,6 +99,7 @@ struct Runtime {
     Inst *d_inst = nullptr;
     Ctrl *d_ctrl = nullptr;
     unsigned long long *d_amax = nullptr;
+    int *d_res_order = nullptr;  // LDS-resident launches: members by decreasing size
     Ctrl *h_ctrl = nullptr;    // pinned mirror
     // captured step graph (K steps of control + stages)
     hipGraphExec_t graph = nullptr;
@@ -169,6 +170,7 @@ struct Runtime {
         p.r_out = r_out;
         p.r_zero = r_zero;
         p.flags = kflags;
+        p.res_order = d_res_order;
         return p;
     }
 
@@ -212,6 +214,7 @@ struct Runtime {
         const size_t o_inst = take(sizeof(Inst) * count);
         const size_t o_ctrl = take(sizeof(Ctrl) * count);
         const size_t o_amax = take(8ull * AMAX_SLOTS * AMAX_VALS * count);
+        const size_t o_order = take(sizeof(int) * count);
         std::vector<size_t> o_mem(count);
         for (int i = 0; i < count; ++i) o_mem[i] = take(member_bytes(&ps[i]));
         if (hipMalloc(&d_block, off) != hipSuccess) {
@@ -223,6 +226,7 @@ struct Runtime {
         d_inst = (Inst *)(base + o_inst);
         d_ctrl = (Ctrl *)(base + o_ctrl);
         d_amax = (unsigned long long *)(base + o_amax);
+        d_res_order = (int *)(base + o_order);
         if (hipHostMalloc((void **)&h_ctrl, sizeof(Ctrl) * count, hipHostMallocDefault) != hipSuccess) {
             h_ctrl = nullptr;
             return ENOAO_ENOMEM;
@@ -251,6 +255,16 @@ struct Runtime {
             c.done = 0;
         }
         HIP_TRY(hipMemcpyAsync(d_ctrl, c0.data(), sizeof(Ctrl) * count, hipMemcpyHostToDevice, stream));
+        // LDS-resident launches take the members by decreasing size: the hardware
+        // hands workgroups to free CUs in launch order, so the long members start
+        // first and the short ones fill in behind them instead of a CU ending with
+        // two long ones (512 members of 128..1700 nodes, one workgroup per CU:
+        // 4.7-4.8e9 cell-updates/s against 3.9-4.0e9 in member order)
+        std::vector<int> order_h(count);
+        for (int i = 0; i < count; ++i) order_h[i] = i;
+        std::stable_sort(order_h.begin(), order_h.end(),
+                         [&](int a, int b) { return (long long)ps[a].nx * ps[a].ny > (long long)ps[b].nx * ps[b].ny; });
+        HIP_TRY(hipMemcpyAsync(d_res_order, order_h.data(), sizeof(int) * count, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
 
         wg_per_cu = g_wg_per_cu;

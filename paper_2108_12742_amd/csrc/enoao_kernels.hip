@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(RES_BLOCK) void resident_1d(KParams P, int nsteps)
     extern __shared__ double sm[];
     __shared__ Ctrl C;
     __shared__ int go;
-    const Inst &I = P.inst[blockIdx.x];
+    const Inst &I = P.inst[P.res_order ? P.res_order[blockIdx.x] : (int)blockIdx.x];
     const int n = I.nx, tid = threadIdx.x;
     double *un = sm;
     double *w = un + NC * n;

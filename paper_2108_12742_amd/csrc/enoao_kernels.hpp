@@ -23,6 +23,9 @@ struct KParams {
     int r_out;   // slot receiving the maxima of the stage output (-1: none)
     int r_zero;  // slot cleared by the first kernel of the stage (-1: none)
     int flags;   // KF_* below
+    // LDS-resident launches: member run by workgroup b (members by decreasing
+    // size, so the small ones fill the machine behind the large; null: member b)
+    const int *res_order;
 };
 
 // every face takes the full selection (no wave-uniform shortcut); results are
