@@ -209,3 +209,41 @@ def test_c4_served_workload_sampled_requests():
     ur, _, nr = O.solve(PT.oracle_problem(probs[small]), data[small].u0, 1e300, cfl=0.3, max_steps=50)
     assert nr == 50
     PT.assert_close_by_component(reqs[small].result, ur, rtol=1e-11, what=f"request {small} (N={sizes[small]})")
+
+
+def test_pool_1d_order7_members():
+    """A pool of 1D Euler members at order 7 (sizes from 7 to 2000 nodes) admitted as
+    room frees up: each equals its solve alone bitwise."""
+    torch = PT.torch_cuda()
+    E = _E()
+    sizes = [2000, 7, 333, 64, 1031, 150]
+    insts = [W.riemann_1d(200 + k, n) for k, n in enumerate(sizes)]
+    probs = [E.problem_from_instance(i, order=7) for i in insts]
+    nsteps = [4, 6, 3, 5, 2, 4]
+    bytes_per = [E.enoao_pool_member_bytes(p) for p in probs]
+    pool = E.enoao_pool_create(probs[0], 3, sum(sorted(bytes_per)[-2:]) + 4096)
+    results, slots, pending = {}, {}, list(range(len(insts)))
+    rounds = 0
+    while pending or slots:
+        while pending:
+            k = pending[0]
+            s = E.enoao_pool_admit(pool, probs[k], insts[k].u0, max_steps=nsteps[k])
+            if s is None:
+                break
+            slots[s] = k
+            pending.pop(0)
+        E.enoao_pool_step(pool, 1)
+        rounds += 1
+        done, status, steps, _ = E.enoao_pool_poll(pool)
+        for s in list(slots):
+            assert status[s] == 0
+            if done[s] == 1:
+                k = slots.pop(s)
+                assert steps[s] == nsteps[k]
+                results[k] = E.enoao_pool_retire(pool, s, shape=insts[k].u0.shape)
+        assert rounds < 100
+    for k, inst in enumerate(insts):
+        plan = E.enoao_plan_create(probs[k])
+        u = PT.to_dev(torch, inst.u0)
+        E.enoao_solve(plan, u, 1e300, cfl=0.3, max_steps=nsteps[k])
+        np.testing.assert_array_equal(results[k], u.cpu().numpy())
