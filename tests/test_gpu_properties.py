@@ -163,3 +163,23 @@ def test_oblique_density_wave_against_exact_solution():
     order = np.log2(errs[40] / errs[80])
     assert errs[80] < 1e-6 and order > 4.5, (errs, order)
     assert errs[1024] < 1e-10, errs
+
+
+@pytest.mark.slow
+def test_oblique_density_wave_order7():
+    """The same wave at order 7 with dt = dx^(7/3) (so the RK3 time error stays at seventh
+    order): the GPU error against the closed form falls at close to seventh order."""
+    torch = PT.torch_cuda()
+    E = _E()
+    errs = {}
+    for n in (40, 80):
+        X, Y, u0 = _oblique_wave(n)
+        plan = E.enoao_plan_create(E.make_problem("euler2d", n, n, order=7))
+        u = PT.to_dev(torch, u0)
+        t, k = E.enoao_solve(plan, u, 0.4, dt_fixed=(2.0 / n) ** (7 / 3))
+        assert t == 0.4
+        exact = 1 + 0.2 * np.sin(np.pi * ((X - 0.4) + (Y - 0.2)))
+        errs[n] = np.abs(u[0].cpu().numpy() - exact).max()
+        print(f"n = {n}: {k} steps, max error {errs[n]:.3e}", flush=True)
+    order = np.log2(errs[40] / errs[80])
+    assert errs[80] < 1e-8 and order > 6.5, (errs, order)
