@@ -21,7 +21,8 @@
  * (face 0 and face n coincide on a periodic line).
  *
  * Return codes: 0 ok, 1 invalid argument, 5 non-physical state (rho<=0, p<=0,
- * NaN, or a non-positive Roe sound speed).
+ * NaN, or a non-positive Roe sound speed), 7 a replayed selection outside the
+ * oracle's tie set (the *_replay calls below).
  */
 #ifndef ENOAO_REF_H
 #define ENOAO_REF_H
@@ -34,7 +35,7 @@ extern "C" {
 
 enum { REF_ADVECTION = 0, REF_EULER1D = 1, REF_EULER2D = 2 };
 enum { REF_BC_PERIODIC = 0, REF_BC_TRANSMISSIVE = 1 };
-enum { REF_OK = 0, REF_EINVAL = 1, REF_ENONPHYSICAL = 5 };
+enum { REF_OK = 0, REF_EINVAL = 1, REF_ENONPHYSICAL = 5, REF_EMISMATCH = 7 };
 
 typedef struct ref_problem {
     int32_t equation;   /* REF_ADVECTION | REF_EULER1D | REF_EULER2D            */
@@ -55,6 +56,17 @@ int ref_num_candidates(int order);
 int ref_candidates(int order, const double *f, double *flux_k, double *is_k);
 int ref_reconstruct(int order, const double *f, const double *mag, double delta,
                     double *fhat, int *sel, int *tie);
+/* Replay of another evaluation's choice.  tie_set (may be NULL) receives a bit
+ * mask of the candidates an evaluation of the same indicators with rounding
+ * errors below the near-tie margin could select ({sel} when tie == 0).  With
+ * forced >= 0: if forced is in that set, it is taken (fhat, sel = forced);
+ * otherwise the oracle's own choice is returned with status REF_EMISMATCH.
+ * forced < 0: the same as ref_reconstruct. */
+int ref_reconstruct_replay(int order, const double *f, const double *mag, double delta, int forced,
+                           double *fhat, int *sel, int *tie, unsigned *tie_set);
+/* scale_k[k]: the forward-error scale of candidate k's indicator that the
+ * near-tie margin multiplies (larger of the two delta rows' sum |c| mag). */
+int ref_indicator_scales(int order, const double *f, const double *mag, double *scale_k);
 
 /* ---- Euler building blocks (Section 4: Roe average, characteristic fields) ----
  * dim = 1 (3 components) or 2 (4 components, x-direction; the y-direction uses
@@ -81,6 +93,14 @@ int64_t ref_selection_size(const ref_problem *p);
 int ref_alpha(const ref_problem *p, const double *u, double *alpha_x, double *alpha_y);
 int ref_rhs(const ref_problem *p, const double *u, double *L, uint8_t *sel, uint8_t *tie);
 int ref_step(const ref_problem *p, double *u, double dt);
+/* The same with another evaluation's selection record force[] (layout of sel;
+ * for a step three records, one per stage, each ref_selection_size entries)
+ * replayed where the oracle's tie set allows it; faces where it does not are
+ * counted in *nbad (may be NULL) and keep the oracle's choice, and the call
+ * returns REF_EMISMATCH.  force == NULL gives ref_rhs / ref_step exactly. */
+int ref_rhs_replay(const ref_problem *p, const double *u, double *L, const uint8_t *force,
+                   uint8_t *sel, uint8_t *tie, int64_t *nbad);
+int ref_step_replay(const ref_problem *p, double *u, double dt, const uint8_t *force, int64_t *nbad);
 int ref_dt(const ref_problem *p, const double *u, double cfl, double *dt);
 int ref_solve(const ref_problem *p, double *u, double t_final, double cfl, double dt_fixed,
               int64_t max_steps, double *t_out, int64_t *steps_out);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 ADVECTION, EULER1D, EULER2D = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
+MISMATCH = 7  # status of a replayed selection outside the oracle's tie set
 NCOMP = {ADVECTION: 1, EULER1D: 3, EULER2D: 4}
 
 
@@ -90,6 +91,9 @@ def lib():
         L.ref_num_candidates.argtypes = [ctypes.c_int]
         L.ref_candidates.argtypes = [ctypes.c_int, dp, dp, dp]
         L.ref_reconstruct.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp, ip, ip]
+        L.ref_reconstruct_replay.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int, dp, ip, ip,
+                                             ctypes.POINTER(ctypes.c_uint)]
+        L.ref_indicator_scales.argtypes = [ctypes.c_int, dp, dp, dp]
         L.ref_euler_flux.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
         L.ref_roe_eigen.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
         L.ref_selection_size.argtypes = [pp]
@@ -97,6 +101,9 @@ def lib():
         L.ref_alpha.argtypes = [pp, dp, dp, dp]
         L.ref_rhs.argtypes = [pp, dp, dp, u8, u8]
         L.ref_step.argtypes = [pp, dp, ctypes.c_double]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.ref_rhs_replay.argtypes = [pp, dp, dp, u8, u8, u8, i64p]
+        L.ref_step_replay.argtypes = [pp, dp, ctypes.c_double, u8, i64p]
         L.ref_dt.argtypes = [pp, dp, ctypes.c_double, dp]
         L.ref_solve.argtypes = [pp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int64, dp, ctypes.POINTER(ctypes.c_int64)]
@@ -142,6 +149,33 @@ def reconstruct(order, f, delta=1e-5, mag=None):
                                  ctypes.byref(out), ctypes.byref(sel), ctypes.byref(tie)),
            "reconstruct")
     return out.value, sel.value, tie.value
+
+
+def reconstruct_replay(order, f, forced, delta=1e-5, mag=None):
+    """(fhat, selection, near-tie flag, tie set as a list of candidates, in tie set) for one
+    side of one face, taking candidate `forced` when the oracle's tie set holds it."""
+    f = _f64(f)
+    m = None if mag is None else _f64(mag)
+    out = ctypes.c_double()
+    sel = ctypes.c_int()
+    tie = ctypes.c_int()
+    tset = ctypes.c_uint()
+    st = lib().ref_reconstruct_replay(order, _dp(f), None if m is None else _dp(m), delta, int(forced),
+                                      ctypes.byref(out), ctypes.byref(sel), ctypes.byref(tie),
+                                      ctypes.byref(tset))
+    if st not in (0, MISMATCH):
+        _check(st, "reconstruct_replay")
+    K = num_candidates(order)
+    return out.value, sel.value, tie.value, [k for k in range(K) if tset.value >> k & 1], st == 0
+
+
+def indicator_scales(order, f, mag=None):
+    """forward-error scale of every candidate's indicator (the near-tie margin's unit)"""
+    f = _f64(f)
+    m = None if mag is None else _f64(mag)
+    out = np.zeros(num_candidates(order))
+    _check(lib().ref_indicator_scales(order, _dp(f), None if m is None else _dp(m), _dp(out)), "scales")
+    return out
 
 
 def euler_flux(dim, gamma, U):
@@ -203,6 +237,48 @@ def rhs(p: Problem, u, with_selection=False):
         return L, sel, tie
     _check(lib().ref_rhs(ctypes.byref(ps), _dp(u), _dp(L), None, None), "rhs")
     return L
+
+
+def _u8(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def rhs_replay(p: Problem, u, force):
+    """L(u) with the selection record `force` (layout of rhs(with_selection=True)) replayed
+    wherever the oracle's tie set allows it.  Returns (L, selection, tie flags, number of
+    face sides whose forced choice lies outside the tie set)."""
+    u = _f64(u)
+    assert u.shape == p.shape
+    n = selection_size(p)
+    force = np.ascontiguousarray(force, dtype=np.uint8).reshape(-1)
+    assert force.size == n, (force.size, n)
+    L = np.zeros_like(u)
+    sel = np.zeros(n, np.uint8)
+    tie = np.zeros(n, np.uint8)
+    nbad = ctypes.c_int64()
+    ps = p.c_struct()
+    st = lib().ref_rhs_replay(ctypes.byref(ps), _dp(u), _dp(L), _u8(force), _u8(sel), _u8(tie),
+                              ctypes.byref(nbad))
+    if st not in (0, MISMATCH):
+        _check(st, "rhs_replay")
+    return L, sel, tie, nbad.value
+
+
+def step_replay(p: Problem, u, dt, force):
+    """One SSP-RK3 step replaying three stage records `force` (stage 1, 2, 3, each of
+    selection_size(p) entries) where the tie sets allow it.  Returns (state, number of
+    face sides outside the tie sets over the three stages)."""
+    v = _f64(u).copy()
+    assert v.shape == p.shape
+    n = selection_size(p)
+    force = np.ascontiguousarray(force, dtype=np.uint8).reshape(-1)
+    assert force.size == 3 * n, (force.size, n)
+    nbad = ctypes.c_int64()
+    ps = p.c_struct()
+    st = lib().ref_step_replay(ctypes.byref(ps), _dp(v), float(dt), _u8(force), ctypes.byref(nbad))
+    if st not in (0, MISMATCH):
+        _check(st, "step_replay")
+    return v, nbad.value
 
 
 def step(p: Problem, u, dt):

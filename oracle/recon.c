@@ -182,39 +182,96 @@ static int side_robust(const eval_t *e)
     return fabs(e->dL - e->dR) > TIE_EPS * (e->sL + e->sR);
 }
 
-int ref_reconstruct(int order, const double *f, const double *mag, double delta,
-                    double *fhat, int *sel, int *tie)
+/*
+ * The decision of one side of one face, and the set of candidates that an
+ * evaluation of the same indicators with rounding errors below TIE_EPS times
+ * their scale could select instead (the tie set; it is {chosen} when no
+ * deciding comparison is within that margin).  Walking the candidates from the
+ * highest priority down, a candidate near delta may go either way, so it joins
+ * the set and the walk goes on; the first candidate clearly within delta ends
+ * the walk; when no candidate is clearly within delta the second principle is
+ * reachable and every candidate whose indicator is within the margin of the
+ * smallest one joins the set (the smallest under perturbed values lies within
+ * the sum of the two margins of the exact smallest).  The exceptions of the
+ * near-tie flag apply alike: indicators that are exact zeros of equal values,
+ * and exact ties of one and the same difference row, decide the same way in
+ * every evaluation.
+ */
+static void decide(const eval_t *ev, int K, double delta, int *chosen_out, int *near_out, unsigned *set_out)
 {
-    eval_t ev[MAXC];
-    const int K = ref_num_candidates(order);
-    if (K == 0 || !f) return REF_EINVAL;
-    eval_candidates(order, f, mag, ev);
-
-    int chosen = -1, near = 0;
-    /* First principle: walk the candidates from the highest priority down and
-     * take the first whose indicator does not exceed delta. */
+    int chosen = -1, near = 0, settled = 0;
+    unsigned set = 0u;
+    /* First principle, as the method takes it, and its near comparisons. */
     for (int k = K - 1; k >= 0; --k) {
         const int exact_zero = ev[k].is == 0.0 && ev[k].flat;
         if (fabs(ev[k].is - delta) <= TIE_EPS * ev[k].s && !exact_zero) near = 1;
         if (ev[k].is <= delta) { chosen = k; break; }
     }
+    /* The walk of a perturbed evaluation. */
+    for (int k = K - 1; k >= 0; --k) {
+        const int exact_zero = ev[k].is == 0.0 && ev[k].flat;
+        const int close = fabs(ev[k].is - delta) <= TIE_EPS * ev[k].s && !exact_zero;
+        if (close) { set |= 1u << k; continue; }
+        if (ev[k].is <= delta) { set |= 1u << k; settled = 1; break; }
+    }
     /* Second principle: the smallest indicator; equal minima go to the
      * candidate of higher priority. */
-    if (chosen < 0) {
-        chosen = 0;
+    if (chosen < 0 || !settled) {
+        int amin = 0;
         for (int k = 1; k < K; ++k)
-            if (ev[k].is <= ev[chosen].is) chosen = k;
+            if (ev[k].is <= ev[amin].is) amin = k;
+        const int taken = chosen < 0;
+        if (!settled) set |= 1u << amin;
         for (int k = 0; k < K; ++k) {
-            if (k == chosen) continue;
-            if (fabs(ev[k].is - ev[chosen].is) > TIE_EPS * (ev[k].s + ev[chosen].s)) continue;
-            if (ev[k].is == ev[chosen].is && same_expression(ev, k, chosen) &&
-                side_robust(&ev[k]) && side_robust(&ev[chosen]))
+            if (k == amin) continue;
+            if (fabs(ev[k].is - ev[amin].is) > TIE_EPS * (ev[k].s + ev[amin].s)) continue;
+            if (ev[k].is == ev[amin].is && same_expression(ev, k, amin) &&
+                side_robust(&ev[k]) && side_robust(&ev[amin]))
                 continue;
-            near = 1;
+            if (taken) near = 1;
+            if (!settled) set |= 1u << k;
         }
+        if (taken) chosen = amin;
+    }
+    *chosen_out = chosen;
+    *near_out = near;
+    *set_out = set;
+}
+
+int ref_reconstruct(int order, const double *f, const double *mag, double delta,
+                    double *fhat, int *sel, int *tie)
+{
+    return ref_reconstruct_replay(order, f, mag, delta, -1, fhat, sel, tie, NULL);
+}
+
+int ref_reconstruct_replay(int order, const double *f, const double *mag, double delta, int forced,
+                           double *fhat, int *sel, int *tie, unsigned *tie_set)
+{
+    eval_t ev[MAXC];
+    const int K = ref_num_candidates(order);
+    if (K == 0 || !f || forced >= K) return REF_EINVAL;
+    eval_candidates(order, f, mag, ev);
+    int chosen, near;
+    unsigned set;
+    decide(ev, K, delta, &chosen, &near, &set);
+    int status = REF_OK;
+    if (forced >= 0 && forced != chosen) {
+        if (set & (1u << forced)) chosen = forced;
+        else status = REF_EMISMATCH;
     }
     if (fhat) *fhat = ev[chosen].flux;
     if (sel) *sel = chosen;
     if (tie) *tie = near;
+    if (tie_set) *tie_set = set;
+    return status;
+}
+
+int ref_indicator_scales(int order, const double *f, const double *mag, double *scale_k)
+{
+    eval_t ev[MAXC];
+    const int K = ref_num_candidates(order);
+    if (K == 0 || !f || !scale_k) return REF_EINVAL;
+    eval_candidates(order, f, mag, ev);
+    for (int k = 0; k < K; ++k) scale_k[k] = ev[k].s;
     return REF_OK;
 }

@@ -151,7 +151,7 @@ int64_t ref_selection_size(const ref_problem *p)
  */
 static int line_fluxes(const ref_problem *p, int n, int G, double *const *lin,
                        const double *alpha, double **fhat, uint8_t *sel, uint8_t *tie,
-                       int64_t face_stride, int64_t block_stride)
+                       const uint8_t *force, int64_t *nbad, int64_t face_stride, int64_t block_stride)
 {
     const int eq = p->equation, nc = ncomp_of(eq), h = p->order == 5 ? 3 : 4;
     const int W = 2 * h + 2; /* stencil nodes j-h .. j+h+1 of face j+1/2 */
@@ -171,8 +171,10 @@ static int line_fluxes(const ref_problem *p, int n, int G, double *const *lin,
             }
             double hp, hm;
             int sp, sm, tp, tm;
-            ref_reconstruct(p->order, fplus, mplus, p->delta, &hp, &sp, &tp);
-            ref_reconstruct(p->order, fminus, mminus, p->delta, &hm, &sm, &tm);
+            const int fp = force ? force[i * face_stride] : -1;
+            const int fm = force ? force[i * face_stride + block_stride] : -1;
+            if (ref_reconstruct_replay(p->order, fplus, mplus, p->delta, fp, &hp, &sp, &tp, NULL)) ++*nbad;
+            if (ref_reconstruct_replay(p->order, fminus, mminus, p->delta, fm, &hm, &sm, &tm, NULL)) ++*nbad;
             fhat[0][i] = hp + hm;
             if (sel) { sel[i * face_stride] = (uint8_t)sp; sel[i * face_stride + block_stride] = (uint8_t)sm; }
             if (tie) { tie[i * face_stride] = (uint8_t)tp; tie[i * face_stride + block_stride] = (uint8_t)tm; }
@@ -213,10 +215,11 @@ static int line_fluxes(const ref_problem *p, int n, int G, double *const *lin,
             }
             double hp, hm;
             int sp, sm, tp, tm;
-            ref_reconstruct(p->order, fplus, mplus, p->delta, &hp, &sp, &tp);
-            ref_reconstruct(p->order, fminus, mminus, p->delta, &hm, &sm, &tm);
-            what[s] = hp + hm;
             const int64_t o = (int64_t)s * 2 * block_stride + i * face_stride;
+            const int fp = force ? force[o] : -1, fm = force ? force[o + block_stride] : -1;
+            if (ref_reconstruct_replay(p->order, fplus, mplus, p->delta, fp, &hp, &sp, &tp, NULL)) ++*nbad;
+            if (ref_reconstruct_replay(p->order, fminus, mminus, p->delta, fm, &hm, &sm, &tm, NULL)) ++*nbad;
+            what[s] = hp + hm;
             if (sel) { sel[o] = (uint8_t)sp; sel[o + block_stride] = (uint8_t)sm; }
             if (tie) { tie[o] = (uint8_t)tp; tie[o + block_stride] = (uint8_t)tm; }
         }
@@ -231,6 +234,17 @@ static int line_fluxes(const ref_problem *p, int n, int G, double *const *lin,
 }
 
 int ref_rhs(const ref_problem *p, const double *u, double *L, uint8_t *sel, uint8_t *tie)
+{
+    return ref_rhs_replay(p, u, L, NULL, sel, tie, NULL);
+}
+
+/* L(u) with the selections of another evaluation replayed at near ties: at every
+ * face, field and side where force[] names a candidate other than the oracle's
+ * own choice, that candidate is taken if it lies in the oracle's tie set there
+ * (see ref_reconstruct_replay); otherwise the oracle keeps its own choice and
+ * counts the face in *nbad.  Returns REF_EMISMATCH when *nbad > 0. */
+int ref_rhs_replay(const ref_problem *p, const double *u, double *L, const uint8_t *force,
+                   uint8_t *sel, uint8_t *tie, int64_t *nbad_out)
 {
     int st = check_problem(p);
     if (st) return st;
@@ -252,6 +266,7 @@ int ref_rhs(const ref_problem *p, const double *u, double *L, uint8_t *sel, uint
     }
     const double dx = dx_of(p);
     const int64_t xblock = (int64_t)ny * (nx + 1);
+    int64_t nbad = 0;
 
     /* x-direction: every row */
     for (int iy = 0; iy < ny && !st; ++iy) {
@@ -260,7 +275,8 @@ int ref_rhs(const ref_problem *p, const double *u, double *L, uint8_t *sel, uint
             for (int c = 0; c < nc; ++c) lin[c][G + k] = u[c * plane + (size_t)iy * nx + ix];
         }
         st = line_fluxes(p, nx, G, lin, ax, fh, sel ? sel + (int64_t)iy * (nx + 1) : NULL,
-                         tie ? tie + (int64_t)iy * (nx + 1) : NULL, 1, xblock);
+                         tie ? tie + (int64_t)iy * (nx + 1) : NULL,
+                         force ? force + (int64_t)iy * (nx + 1) : NULL, &nbad, 1, xblock);
         for (int c = 0; c < nc && !st; ++c)
             for (int ix = 0; ix < nx; ++ix)
                 L[c * plane + (size_t)iy * nx + ix] = -(fh[c][ix + 1] - fh[c][ix]) / dx;
@@ -276,7 +292,8 @@ int ref_rhs(const ref_problem *p, const double *u, double *L, uint8_t *sel, uint
                 for (int c = 0; c < nc; ++c) lin[c][G + k] = u[perm[c] * plane + (size_t)iy * nx + ix];
             }
             st = line_fluxes(p, ny, G, lin, ay, fh, sel ? sel + ybase + ix : NULL,
-                             tie ? tie + ybase + ix : NULL, nx, yblock);
+                             tie ? tie + ybase + ix : NULL, force ? force + ybase + ix : NULL, &nbad,
+                             nx, yblock);
             for (int c = 0; c < nc && !st; ++c)
                 for (int iy = 0; iy < ny; ++iy) {
                     const size_t o = perm[c] * plane + (size_t)iy * nx + ix;
@@ -285,25 +302,43 @@ int ref_rhs(const ref_problem *p, const double *u, double *L, uint8_t *sel, uint
         }
     }
     free(buf);
+    if (nbad_out) *nbad_out = nbad;
+    if (!st && nbad > 0) st = REF_EMISMATCH;
     return st;
 }
 
 int ref_step(const ref_problem *p, double *u, double dt)
 {
+    return ref_step_replay(p, u, dt, NULL, NULL);
+}
+
+/* One step with the selections of another evaluation replayed at near ties:
+ * force[] holds three records of ref_selection_size(p) entries, one per stage;
+ * a mismatch outside the tie set is counted in *nbad (summed over the stages)
+ * and the step is completed with the oracle's own choice there. */
+int ref_step_replay(const ref_problem *p, double *u, double dt, const uint8_t *force, int64_t *nbad_out)
+{
     int st = check_problem(p);
     if (st) return st;
+    const int64_t rec = ref_selection_size(p);
+    int64_t nb[3] = {0, 0, 0};
     const size_t n = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
     double *u1 = (double *)malloc(sizeof(double) * n * 3);
     if (!u1) return REF_EINVAL;
     double *u2 = u1 + n, *Lb = u1 + 2 * n;
 
-    st = ref_rhs(p, u, Lb, NULL, NULL);
+    st = ref_rhs_replay(p, u, Lb, force, NULL, NULL, &nb[0]);
+    if (st == REF_EMISMATCH) st = REF_OK;
     for (size_t i = 0; i < n && !st; ++i) u1[i] = u[i] + dt * Lb[i];
-    if (!st) st = ref_rhs(p, u1, Lb, NULL, NULL);
+    if (!st) st = ref_rhs_replay(p, u1, Lb, force ? force + rec : NULL, NULL, NULL, &nb[1]);
+    if (st == REF_EMISMATCH) st = REF_OK;
     for (size_t i = 0; i < n && !st; ++i) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * Lb[i]);
-    if (!st) st = ref_rhs(p, u2, Lb, NULL, NULL);
+    if (!st) st = ref_rhs_replay(p, u2, Lb, force ? force + 2 * rec : NULL, NULL, NULL, &nb[2]);
+    if (st == REF_EMISMATCH) st = REF_OK;
     for (size_t i = 0; i < n && !st; ++i) u[i] = (1.0 / 3.0) * u[i] + (2.0 / 3.0) * (u2[i] + dt * Lb[i]);
     free(u1);
+    if (nbad_out) *nbad_out = nb[0] + nb[1] + nb[2];
+    if (!st && nb[0] + nb[1] + nb[2] > 0) st = REF_EMISMATCH;
     return st;
 }
 
