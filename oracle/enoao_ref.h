@@ -35,6 +35,7 @@ extern "C" {
 
 enum { REF_ADVECTION = 0, REF_EULER1D = 1, REF_EULER2D = 2 };
 enum { REF_BC_PERIODIC = 0, REF_BC_TRANSMISSIVE = 1 };
+enum { REF_CHAR_ROE = 0, REF_COMPONENT = 1 };
 enum { REF_OK = 0, REF_EINVAL = 1, REF_ENONPHYSICAL = 5, REF_EMISMATCH = 7 };
 
 typedef struct ref_problem {
@@ -46,6 +47,9 @@ typedef struct ref_problem {
     double  gamma;      /* ideal-gas ratio of specific heats (Euler)              */
     double  adv_speed;  /* a in u_t + a u_x = 0 (advection)                       */
     double  delta;      /* selection threshold of the reconstruction principle    */
+    int32_t recon_vars; /* Euler: REF_CHAR_ROE (characteristic fields of the Roe
+                           state, the paper's choice) | REF_COMPONENT (conserved
+                           components, one alpha = max(|u|+c) for all of them)  */
 } ref_problem;
 
 /* ---- single-face reconstruction (Section 3.2, Tables of fluxes and delta_L/delta_R) ----

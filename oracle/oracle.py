@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 ADVECTION, EULER1D, EULER2D = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
+CHAR_ROE, COMPONENT = 0, 1  # reconstruction variables of the Euler systems
 MISMATCH = 7  # status of a replayed selection outside the oracle's tie set
 NCOMP = {ADVECTION: 1, EULER1D: 3, EULER2D: 4}
 
@@ -29,6 +30,7 @@ class _Problem(ctypes.Structure):
         ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
         ("gamma", ctypes.c_double), ("adv_speed", ctypes.c_double), ("delta", ctypes.c_double),
+        ("recon_vars", ctypes.c_int32),
     ]
 
 
@@ -47,6 +49,7 @@ class Problem:
     gamma: float = 1.4
     adv_speed: float = 1.0
     delta: float = 1e-5
+    recon_vars: int = 0  # CHAR_ROE or COMPONENT
 
     @property
     def ncomp(self):
@@ -67,7 +70,7 @@ class Problem:
     def c_struct(self):
         return _Problem(self.equation, self.order, self.nx, self.ny, self.x_lo, self.x_hi,
                         self.y_lo, self.y_hi, self.bc_x, self.bc_y, self.gamma,
-                        self.adv_speed, self.delta)
+                        self.adv_speed, self.delta, self.recon_vars)
 
 
 class OracleError(RuntimeError):

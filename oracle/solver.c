@@ -29,7 +29,11 @@
  *    t_final (dt >= (t_final - t)(1 - 1e-10)) is set to t_final - t and ends
  *    the loop at t = t_final exactly;
  *  - boundary conditions act on the stencil gather: periodic wrap, or
- *    zero-gradient ("non-reflective") copying of the end node.
+ *    zero-gradient ("non-reflective") copying of the end node;
+ *  - the component-wise alternative (recon_vars = REF_COMPONENT) splits and
+ *    reconstructs each conserved component of U and F directly, with the one
+ *    alpha of the scalar splitting taken as the largest eigenvalue magnitude,
+ *    max_j (|u| + c) along the sweep, for every component.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -54,6 +58,7 @@ static int check_problem(const ref_problem *p)
     if (p->equation == REF_EULER2D && p->bc_y != REF_BC_PERIODIC && p->bc_y != REF_BC_TRANSMISSIVE)
         return REF_EINVAL;
     if (p->equation != REF_ADVECTION && !(p->gamma > 1.0)) return REF_EINVAL;
+    if (p->recon_vars != REF_CHAR_ROE && p->recon_vars != REF_COMPONENT) return REF_EINVAL;
     if (p->equation == REF_ADVECTION && !(p->adv_speed != 0.0)) return REF_EINVAL;
     if (!(p->delta >= 0.0)) return REF_EINVAL;
     return REF_OK;
@@ -180,8 +185,36 @@ static int line_fluxes(const ref_problem *p, int n, int G, double *const *lin,
             if (tie) { tie[i * face_stride] = (uint8_t)tp; tie[i * face_stride + block_stride] = (uint8_t)tm; }
             continue;
         }
-        /* Euler: Roe state of the two nodes adjacent to the face */
         const int dim = eq == REF_EULER1D ? 1 : 2;
+        if (p->recon_vars == REF_COMPONENT) {
+            /* conserved components: f^(+/-) = (F_c +/- alpha U_c)/2 with one alpha */
+            const double a = alpha[0] > alpha[nc - 1] ? alpha[0] : alpha[nc - 1];
+            double Uw[10][4], Fw[10][4];
+            for (int t = 0; t < W; ++t) {
+                for (int c = 0; c < nc; ++c) Uw[t][c] = lin[c][G + j - h + t];
+                if (ref_euler_flux(dim, p->gamma, Uw[t], Fw[t])) return REF_ENONPHYSICAL;
+            }
+            for (int c = 0; c < nc; ++c) {
+                for (int q = 0; q <= 2 * h; ++q) {
+                    const int np = q, nm = 2 * h + 1 - q;
+                    fplus[q] = 0.5 * (Fw[np][c] + a * Uw[np][c]);
+                    fminus[q] = 0.5 * (Fw[nm][c] - a * Uw[nm][c]);
+                    mplus[q] = 0.5 * (fabs(Fw[np][c]) + a * fabs(Uw[np][c]));
+                    mminus[q] = 0.5 * (fabs(Fw[nm][c]) + a * fabs(Uw[nm][c]));
+                }
+                double hp, hm;
+                int sp, sm, tp, tm;
+                const int64_t o = (int64_t)c * 2 * block_stride + i * face_stride;
+                const int fp = force ? force[o] : -1, fm = force ? force[o + block_stride] : -1;
+                if (ref_reconstruct_replay(p->order, fplus, mplus, p->delta, fp, &hp, &sp, &tp, NULL)) ++*nbad;
+                if (ref_reconstruct_replay(p->order, fminus, mminus, p->delta, fm, &hm, &sm, &tm, NULL)) ++*nbad;
+                fhat[c][i] = hp + hm;
+                if (sel) { sel[o] = (uint8_t)sp; sel[o + block_stride] = (uint8_t)sm; }
+                if (tie) { tie[o] = (uint8_t)tp; tie[o + block_stride] = (uint8_t)tm; }
+            }
+            continue;
+        }
+        /* Euler: Roe state of the two nodes adjacent to the face */
         double UL[4], UR[4], R[16], Lm[16];
         for (int c = 0; c < nc; ++c) { UL[c] = lin[c][G + j]; UR[c] = lin[c][G + j + 1]; }
         if (ref_roe_eigen(dim, p->gamma, UL, UR, R, Lm, NULL)) return REF_ENONPHYSICAL;

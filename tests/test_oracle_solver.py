@@ -466,3 +466,94 @@ def test_lax_tube_against_exact_riemann(order):
         if prev is not None:
             assert prev / l1 > 1.7, (n, prev, l1)
         prev = l1
+
+
+# ---------------------------------------------------------------- component-wise variables
+
+def test_component_linear_limit_uses_the_spectral_radius():
+    """Component-wise reconstruction with delta = 1e30 always takes the top candidate, so
+    every component is the linear upwind-biased scheme on its split flux
+    (F_c +/- alpha U_c)/2 with the one alpha = max_j (|u| + c): checked against the exact
+    S_{j-2}^{j+2} row applied to those split fluxes (mirrored for the minus side), which
+    fixes alpha (the per-field maxima would differ)."""
+    n = 60
+    inst = W.riemann_1d(6, n)
+    p = O.Problem(O.EULER1D, nx=n, x_lo=0.0, x_hi=1.0, bc_x=O.PERIODIC, delta=1e30, recon_vars=O.COMPONENT)
+    u = inst.u0[:, 0, :]
+    L = O.rhs(p, inst.u0)[:, 0, :]
+    r, m, E = u
+    vel = m / r
+    pr = 0.4 * (E - 0.5 * r * vel * vel)
+    c = np.sqrt(1.4 * pr / r)
+    a = (np.abs(vel) + c).max()
+    F = np.stack([m, m * vel + pr, (E + pr) * vel])
+    coef = [float(v) for v in X.flux_coefficients(2, 2)]
+    fp = 0.5 * (F + a * u)
+    fm = 0.5 * (F - a * u)
+    # face j+1/2: plus side from nodes j-2..j+2, minus side mirrored from nodes j+3..j-1
+    hp = sum(cf * np.roll(fp, -o, axis=1) for cf, o in zip(coef, range(-2, 3)))
+    hm = sum(cf * np.roll(fm, -(1 - o), axis=1) for cf, o in zip(coef, range(-2, 3)))
+    fh = hp + hm
+    Lref = -(fh - np.roll(fh, 1, axis=1)) / p.dx
+    np.testing.assert_allclose(L, Lref, rtol=0, atol=1e-12 * np.abs(Lref).max())
+    # the characteristic path differs on the same data
+    pc = O.Problem(O.EULER1D, nx=n, x_lo=0.0, x_hi=1.0, bc_x=O.PERIODIC, delta=1e30)
+    assert np.abs(O.rhs(pc, inst.u0)[:, 0, :] - L).max() > 1e-6 * np.abs(L).max()
+
+
+def test_component_invariants_and_order():
+    """Component-wise variables: a uniform state is steady (L exactly 0), periodic sums are
+    conserved, 2D on y-invariant data with v = 0 reduces to 1D, x <-> y transposition
+    commutes, and the density wave converges at close to fifth order."""
+    C = O.COMPONENT
+    u1 = W.conserved_1d(np.full(16, 0.7), np.full(16, -1.3), np.full(16, 2.2)).reshape(3, 1, 16)
+    assert np.abs(O.rhs(O.Problem(O.EULER1D, nx=16, recon_vars=C), u1)).max() == 0.0
+    u2 = W.conserved_2d(np.full((12, 10), 1.7), np.full((12, 10), 0.4), np.full((12, 10), -0.9),
+                        np.full((12, 10), 0.3))
+    assert np.abs(O.rhs(O.Problem(O.EULER2D, nx=10, ny=12, recon_vars=C), u2)).max() == 0.0
+    inst2 = W.quadrants(4, 24)
+    p2 = O.Problem(O.EULER2D, nx=24, ny=24, recon_vars=C)
+    v = O.step(p2, inst2.u0, 0.5 * O.cfl_dt(p2, inst2.u0, 0.3))
+    s0, s1 = inst2.u0.sum(axis=(1, 2)), v.sum(axis=(1, 2))
+    assert (np.abs(s1 - s0) <= 1e-13 * np.abs(inst2.u0).sum(axis=(1, 2))).all()
+    n, ny = 40, 7
+    inst = W.riemann_1d(5, n)
+    r, m, E = inst.u0[:, 0, :]
+    u2 = np.stack([np.tile(r, (ny, 1)), np.tile(m, (ny, 1)), np.zeros((ny, n)), np.tile(E, (ny, 1))])
+    L2 = O.rhs(O.Problem(O.EULER2D, nx=n, ny=ny, x_lo=0.0, x_hi=1.0, bc_x=O.TRANSMISSIVE, recon_vars=C), u2)
+    L1 = O.rhs(O.Problem(O.EULER1D, nx=n, x_lo=0.0, x_hi=1.0, bc_x=O.TRANSMISSIVE, recon_vars=C), inst.u0)
+    for row in range(ny):
+        np.testing.assert_array_equal(L2[[0, 1, 3], row], L1[:, 0])
+    assert np.abs(L2[2]).max() == 0.0
+    u = W.quadrants(6, 20).u0
+    p = O.Problem(O.EULER2D, nx=20, ny=20, recon_vars=C)
+    L = O.rhs(p, u)
+    Lt = O.rhs(p, np.stack([u[0].T, u[2].T, u[1].T, u[3].T]))
+    np.testing.assert_array_equal(np.stack([Lt[0].T, Lt[2].T, Lt[1].T, Lt[3].T]), L)
+    errs = []
+    for n in (40, 80):
+        x = W.nodes(-1.0, 1.0, n)
+        u0 = W.conserved_1d(1 + 0.2 * np.sin(np.pi * x), np.ones(n), np.ones(n)).reshape(3, 1, n)
+        uu, _, _ = O.solve(O.Problem(O.EULER1D, nx=n, recon_vars=C), u0, 2.0, dt_fixed=(2.0 / n) ** (5 / 3))
+        errs.append(np.abs(uu[0, 0] - u0[0, 0]).max())
+    assert errs[1] < 1e-6 and math.log(errs[0] / errs[1]) / math.log(2) > 4.5, errs
+
+
+def test_component_riemann_against_exact():
+    """Component-wise variables on seeded Riemann data without the perturbation track the
+    exact solution, and the Lax tube's density error falls under refinement."""
+    for seed in (0, 1, 2):
+        inst = W.riemann_1d(seed, 200, amp=0.0)
+        p = O.Problem(O.EULER1D, nx=200, x_lo=0.0, x_hi=1.0, bc_x=O.TRANSMISSIVE, recon_vars=O.COMPONENT)
+        u, t, _ = O.solve(p, inst.u0, 0.05, cfl=0.3)
+        ex = RX.sample(inst.meta["left"], inst.meta["right"], W.nodes(0.0, 1.0, 200), inst.meta["x0"], t)
+        assert np.isfinite(u).all()
+        assert np.abs(u[0, 0] - ex[0]).mean() < 0.05 * max(ex[0].max(), 1.0)
+    errs = []
+    for n in (100, 200):
+        inst = W.lax_tube(n)
+        p = O.Problem(O.EULER1D, nx=n, x_lo=0.0, x_hi=2.0, bc_x=O.TRANSMISSIVE, recon_vars=O.COMPONENT)
+        u, t, _ = O.solve(p, inst.u0, 0.26, cfl=0.3)
+        ex = RX.sample((0.445, 0.698, 3.528), (0.5, 0.0, 0.571), W.nodes(0.0, 2.0, n), 1.0, t)
+        errs.append(np.abs(u[0, 0] - ex[0]).mean())
+    assert errs[0] > errs[1] and errs[1] < 0.02, errs
