@@ -71,6 +71,8 @@ typedef enum enoao_status {
 
 enum { ENOAO_ADVECTION = 0, ENOAO_EULER1D = 1, ENOAO_EULER2D = 2 };
 enum { ENOAO_BC_PERIODIC = 0, ENOAO_BC_TRANSMISSIVE = 1 };
+/* variables the Euler systems are split and reconstructed in */
+enum { ENOAO_CHAR_ROE = 0, ENOAO_COMPONENT = 1 };
 /* flags */
 enum { ENOAO_F_RECORD_SELECTION = 1u };
 
@@ -85,7 +87,11 @@ typedef struct enoao_problem {
     int32_t order;        /* designed order: 5 or 7 (Section 3.2 candidate lists)       */
     int32_t nx;           /* nodes along x, 1 .. ENOAO_MAX_EXTENT                       */
     int32_t ny;           /* nodes along y, 1 for the 1D equations; nx*ny <= 2^31       */
-    int32_t reserved0;    /* must be 0                                                  */
+    int32_t recon_vars;   /* Euler systems: ENOAO_CHAR_ROE (0, default): characteristic */
+                          /*   fields of the face's Roe state, alpha per field          */
+                          /*   (Section 4); ENOAO_COMPONENT: the conserved components,  */
+                          /*   one alpha = max(|u| + c) for all (the scalar splitting   */
+                          /*   of Section 2 applied per component).  Advection: either. */
     double x_lo, x_hi;    /* dx = (x_hi - x_lo)/nx                                      */
     double y_lo, y_hi;    /* dy = (y_hi - y_lo)/ny (2D only)                            */
     int32_t bc_x, bc_y;   /* ENOAO_BC_PERIODIC | ENOAO_BC_TRANSMISSIVE (zero gradient)  */
@@ -141,13 +147,24 @@ enoao_status enoao_plan_check(enoao_plan *plan, void *stream);
  * each record is the chosen candidate 0..K-1 (K = 6 for order 5, 9 for order 7)
  * numbered S_j^j, S_j^{j+1}, S_{j-1}^{j+1}, S_{j-2}^{j+1}, S_{j-1}^{j+2},
  * S_{j-2}^{j+2}[, S_{j-3}^{j+2}, S_{j-2}^{j+3}, S_{j-3}^{j+3}], i.e. in
- * increasing priority; entries are in characteristic fields for Euler. */
+ * increasing priority; entries are in characteristic fields for Euler
+ * (conserved components with ENOAO_COMPONENT). */
 size_t enoao_selection_size(const enoao_plan *plan);
 
 /* Copies the selection records of the last evaluation of L (enoao_rhs, or the
  * third stage of the last step) to host memory host_out[n]; n must equal
  * enoao_selection_size.  Synchronises stream. */
 enoao_status enoao_get_selection(enoao_plan *plan, uint8_t *host_out, size_t n, void *stream);
+
+/* Copies the selection records of the three Runge-Kutta stages of the last
+ * step (enoao_step, or the last step of enoao_solve) to host_out[n],
+ * n = 3 * enoao_selection_size: stage 1 (input u^n), stage 2 (input u^(1)),
+ * stage 3 (input u^(2)), each in the layout above (Section 2, third-order TVD
+ * Runge-Kutta; Section 3.2 for the records).  Each stage's record is written
+ * by that stage's kernels, so the three are those of one step only after a
+ * step has run; after enoao_rhs only the first is updated.  ENOAO_EINVAL
+ * without ENOAO_F_RECORD_SELECTION or for another n.  Synchronises stream. */
+enoao_status enoao_get_step_selection(enoao_plan *plan, uint8_t *host_out, size_t n, void *stream);
 
 /* ---- batches: many independent problems advanced together ----------------
  * One batch holds n problems of one equation and order (any sizes, geometry,

@@ -32,7 +32,8 @@ enoao_status check_problem(const enoao_problem *p)
     if (!p || p->struct_size != sizeof(enoao_problem)) return ENOAO_EINVAL;
     if (!ncomp_of(p->equation)) return ENOAO_EINVAL;
     if (p->order != 5 && p->order != 7) return ENOAO_EINVAL;
-    if (p->nx < 1 || p->ny < 1 || p->reserved0 != 0 || p->reserved1 != 0) return ENOAO_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->reserved1 != 0) return ENOAO_EINVAL;
+    if (p->recon_vars != ENOAO_CHAR_ROE && p->recon_vars != ENOAO_COMPONENT) return ENOAO_EINVAL;
     if (p->equation != EULER2D && p->ny != 1) return ENOAO_EINVAL;
     if (!(p->x_hi > p->x_lo)) return ENOAO_EINVAL;
     if (p->equation == EULER2D && !(p->y_hi > p->y_lo)) return ENOAO_EINVAL;
@@ -70,7 +71,8 @@ size_t member_bytes(const enoao_problem *p)
     const size_t n = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
     const int bufs = p->equation == EULER2D ? 3 : 2;
     size_t b = bufs * (n + BUF_STAGGER) * sizeof(double);
-    if (p->flags & ENOAO_F_RECORD_SELECTION) b += (selection_count(p) + 255) / 256 * 256;
+    // three records: one per Runge-Kutta stage of a step (enoao_rhs uses the first)
+    if (p->flags & ENOAO_F_RECORD_SELECTION) b += (3 * selection_count(p) + 255) / 256 * 256;
     return b;
 }
 
@@ -89,6 +91,8 @@ struct Runtime {
     int n_cap = 0;   // members the control and reset launches cover (>= n)
     double gamma = 1.4, delta = 1e-5;
     bool rec = false;
+    bool ch = true;    // characteristic reconstruction variables (ENOAO_CHAR_ROE)
+    int last_sel = 0;  // record slot of the last evaluation of L enqueued (recording plans)
     int device = 0, cus = 256;
     std::vector<enoao_problem> probs;
     std::vector<Inst> h_inst;
@@ -158,9 +162,10 @@ struct Runtime {
         if (failed) (void)hipGetLastError();  // a pair without a reading is skipped, not left as an error
     }
 
-    KParams params(int r_in, int r_out, int r_zero) const
+    KParams params(int r_in, int r_out, int r_zero, int sel_slot = 0) const
     {
         KParams p{};
+        p.sel_slot = sel_slot;
         p.hdr = d_hdr;
         p.inst = d_inst;
         p.gamma = gamma;
@@ -189,6 +194,7 @@ struct Runtime {
             if (check_problem(&ps[i])) return ENOAO_EINVAL;
             if (ps[i].equation != ps[0].equation || ps[i].order != ps[0].order) return ENOAO_EINVAL;
             if (ps[i].gamma != ps[0].gamma || ps[i].delta != ps[0].delta) return ENOAO_EINVAL;
+            if (ps[i].recon_vars != ps[0].recon_vars) return ENOAO_EINVAL;
         }
         eq = ps[0].equation;
         order = ps[0].order;
@@ -199,6 +205,7 @@ struct Runtime {
         gamma = ps[0].gamma;
         delta = ps[0].delta;
         rec = (ps[0].flags & ENOAO_F_RECORD_SELECTION) != 0;
+        ch = ps[0].recon_vars == ENOAO_CHAR_ROE;
         probs.assign(ps, ps + count);
         HIP_TRY(hipGetDevice(&device));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
@@ -315,8 +322,8 @@ struct Runtime {
     {
         const long long xt = h_hdr.xtiles_total, yt = h_hdr.ytiles_total;
         for (int m = 0; m < 4; ++m) {
-            grid_x[m] = grid_for(xt, occupancy_x(eq, order, m, false));
-            grid_y[m] = eq == EULER2D ? grid_for(yt, occupancy_y(order, m, false, yw)) : 0;
+            grid_x[m] = grid_for(xt, occupancy_x(eq, order, m, false, ch));
+            grid_y[m] = eq == EULER2D ? grid_for(yt, occupancy_y(order, m, false, ch, yw)) : 0;
         }
         grid_m = grid_for(xt, occupancy_maxima(eq));
     }
@@ -396,22 +403,24 @@ struct Runtime {
         int slot;
         HIP_TRY(prof_begin(PROF_X1 + s - 1, st, slot));
         if (eq == EULER2D)
-            HIP_TRY(launch_sweep_x(eq, order, mode, record, params(r_in, -1, r_zero), grid_x[mode], st));
+            HIP_TRY(launch_sweep_x(eq, order, mode, record, ch, params(r_in, -1, r_zero, s - 1), grid_x[mode], st));
         else
-            HIP_TRY(launch_sweep_x(eq, order, mode, record, params(r_in, r_out, r_zero), grid_x[mode], st));
+            HIP_TRY(launch_sweep_x(eq, order, mode, record, ch, params(r_in, r_out, r_zero, s - 1), grid_x[mode], st));
         HIP_TRY(prof_end(slot, st));
         if (eq == EULER2D) {
             HIP_TRY(prof_begin(PROF_Y1 + s - 1, st, slot));
-            HIP_TRY(launch_sweep_y(order, mode, record, yw, params(r_in, r_out, -1), grid_y[mode], st));
+            HIP_TRY(launch_sweep_y(order, mode, record, ch, yw, params(r_in, r_out, -1, s - 1), grid_y[mode], st));
             HIP_TRY(prof_end(slot, st));
         }
+        if (record) last_sel = s - 1;
         return ENOAO_OK;
     }
 
     enoao_status rhs(hipStream_t s)
     {
-        HIP_TRY(launch_sweep_x(eq, order, M_RHS, rec, params(0, -1, -1), grid_x[M_RHS], s));
-        if (eq == EULER2D) HIP_TRY(launch_sweep_y(order, M_RHS, rec, yw, params(0, -1, -1), grid_y[M_RHS], s));
+        HIP_TRY(launch_sweep_x(eq, order, M_RHS, rec, ch, params(0, -1, -1), grid_x[M_RHS], s));
+        if (eq == EULER2D) HIP_TRY(launch_sweep_y(order, M_RHS, rec, ch, yw, params(0, -1, -1), grid_y[M_RHS], s));
+        last_sel = 0;
         return ENOAO_OK;
     }
 
@@ -420,7 +429,7 @@ struct Runtime {
         if (control && use_resident()) {
             int slot;
             HIP_TRY(prof_begin(PROF_RESIDENT, s, slot));
-            HIP_TRY(launch_resident(eq, order, params(0, -1, -1), n_cap, k, res_lds, s));
+            HIP_TRY(launch_resident(eq, order, ch, params(0, -1, -1), n_cap, k, res_lds, s));
             HIP_TRY(prof_end(slot, s));
             return ENOAO_OK;
         }
@@ -432,7 +441,7 @@ struct Runtime {
                 HIP_TRY(prof_end(slot, s));
             }
             for (int st = 1; st <= 3; ++st)
-                if (enoao_status e = stage(st, rec && st == 3, s)) return e;
+                if (enoao_status e = stage(st, rec, s)) return e;
         }
         return ENOAO_OK;
     }
@@ -839,6 +848,17 @@ enoao_status enoao_get_selection(enoao_plan *plan, uint8_t *host_out, size_t n, 
     if (!plan || !host_out || !plan->rt.rec) return ENOAO_EINVAL;
     if (n != selection_count(&plan->rt.probs[0])) return ENOAO_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(host_out, plan->rt.h_inst[0].sel + (size_t)plan->rt.last_sel * n, n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return ENOAO_OK;
+}
+
+enoao_status enoao_get_step_selection(enoao_plan *plan, uint8_t *host_out, size_t n, void *stream)
+{
+    if (!plan || !host_out || !plan->rt.rec) return ENOAO_EINVAL;
+    if (n != 3 * selection_count(&plan->rt.probs[0])) return ENOAO_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(host_out, plan->rt.h_inst[0].sel, n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return ENOAO_OK;
@@ -979,6 +999,7 @@ enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, s
     r.gamma = like->gamma;
     r.delta = like->delta;
     r.rec = false;
+    r.ch = like->recon_vars == ENOAO_CHAR_ROE;
     r.dynamic = true;
     r.n = 0;
     r.n_cap = max_members;
@@ -1057,7 +1078,8 @@ enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const
     if (!pool || !prob || !u0 || !slot_out || max_steps < 0 || !(cfl > 0.0) || !(t_final >= 0.0)) return ENOAO_EINVAL;
     Runtime &r = pool->rt;
     if (check_problem(prob) || (prob->flags & ENOAO_F_RECORD_SELECTION)) return ENOAO_EINVAL;
-    if (prob->equation != r.eq || prob->order != r.order || prob->gamma != r.gamma || prob->delta != r.delta)
+    if (prob->equation != r.eq || prob->order != r.order || prob->gamma != r.gamma || prob->delta != r.delta ||
+        prob->recon_vars != r.probs[0].recon_vars)
         return ENOAO_EINVAL;
     const size_t bytes = pool_member_bytes(prob);
     if (bytes > pool->arena_bytes) return ENOAO_EINVAL;  // can never fit

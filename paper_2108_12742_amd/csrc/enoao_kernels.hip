@@ -163,6 +163,37 @@ template <int EQ> struct Maxima {
 // projected symmetric stencil of F give both sides' top indicators and the sum
 // of both sides' top values, on the window scale 2 field_scale (the windows
 // below are g = P F +/- alpha P U with the scaled projection P).
+// Reconstruction variables.  CH: the characteristic fields of the face's Roe
+// state (Section 4), with the scaled projection and the field scales above;
+// otherwise the conserved components themselves (identity projection, scale 1,
+// and one alpha for all of them).
+template <int NC, bool CH>
+__device__ __forceinline__ void to_fields(const RoeState &r, const double (&x)[NC], double (&w)[NC])
+{
+    if constexpr (CH) {
+        project<NC>(r, x, w);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = x[c];
+    }
+}
+
+template <int NC, bool CH>
+__device__ __forceinline__ void from_fields(const RoeState &r, const double (&w)[NC], double (&F)[NC])
+{
+    if constexpr (CH) {
+        back_project<NC>(r, w, F);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) F[c] = w[c];
+    }
+}
+
+template <int NC, bool CH> __device__ __forceinline__ constexpr double fscale(int s)
+{
+    return CH ? field_scale<NC>(s) : 1.0;
+}
+
 template <int NC> struct TopForm {
     double is[NC][2];  // IS_top of the plus and minus side
     double hs[NC];     // plus + minus top value
@@ -171,7 +202,7 @@ template <int NC> struct TopForm {
 // Staged differences (DSTAGED): d0 points at D_0 of quantity 0 of the face,
 // quantities (U then F) dqs apart, positions dns apart.  Otherwise they are
 // formed here from the window nodes.
-template <int NC, int ORDER, bool DSTAGED>
+template <int NC, int ORDER, bool DSTAGED, bool CH>
 __device__ __forceinline__ void top_form(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
                                          const RoeState &r, const double *al, double delta, TopForm<NC> &tf)
 {
@@ -207,8 +238,8 @@ __device__ __forceinline__ void top_form(const double *w0, int qs, int ns, const
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) project<NC>(r, dv[p][v], pd[p][v]);
-    project<NC>(r, sf, psf);
+        for (int v = 0; v < 2; ++v) to_fields<NC, CH>(r, dv[p][v], pd[p][v]);
+    to_fields<NC, CH>(r, sf, psf);
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const double a = al[s];
@@ -219,10 +250,10 @@ __device__ __forceinline__ void top_form(const double *w0, int qs, int ns, const
 }
 
 // every lane of the wave has IS_top <= delta on both sides of field s
-template <int NC>
+template <int NC, bool CH>
 __device__ __forceinline__ bool top_wave_ok(const TopForm<NC> &tf, int s, double delta, bool shortcut)
 {
-    const double sd = 2.0 * field_scale<NC>(s) * delta;
+    const double sd = 2.0 * fscale<NC, CH>(s) * delta;
     return wave_all(tf.is[s][0] <= sd && tf.is[s][1] <= sd) & shortcut;
 }
 
@@ -233,7 +264,7 @@ __device__ __forceinline__ bool top_wave_ok(const TopForm<NC> &tf, int s, double
 // value; a lane whose selection takes the top candidate on both sides takes
 // the same value, tf (the face's top form, formed once).  Taking the fields in
 // two passes halves the live window registers.
-template <int NC, int ORDER, int F0, int F1>
+template <int NC, int ORDER, int F0, int F1, bool CH>
 __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, const RoeState &r, const double *al,
                                            double delta, int okmask, const TopForm<NC> &tf, double (&wh)[NC],
                                            int (&sel)[2 * NC])
@@ -265,8 +296,8 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
                 }
             }
             double PU[NC], PF[NC];
-            project<NC>(r, Uq[t], PU);
-            project<NC>(r, Fq[t], PF);
+            to_fields<NC, CH>(r, Uq[t], PU);
+            to_fields<NC, CH>(r, Fq[t], PF);
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 const int s = fs[i];
@@ -282,7 +313,7 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         const int s = fs[i];
-        const double sc = 2.0 * field_scale<NC>(s);
+        const double sc = 2.0 * fscale<NC, CH>(s);
         if (okmask & (1 << s)) {
             wh[s] = tf.hs[s] * (1.0 / sc);
             sel[2 * s] = sel[2 * s + 1] = K - 1;
@@ -301,7 +332,7 @@ __device__ __forceinline__ void field_pass(const double *w0, int qs, int ns, con
 // stride qs, node stride ns; d0/dqs/dns: the staged top differences when
 // DSTAGED, quantities U then F, for advection u only).  shortcut = false: every
 // field takes the full selection (the result is the same).
-template <int EQ, int ORDER, bool DSTAGED>
+template <int EQ, int ORDER, bool DSTAGED, bool CH>
 __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, const double *d0, int dqs, int dns,
                                           const double *al, double gm1, double delta, double adv, bool shortcut,
                                           double (&Fh)[NodeTraits<EQ>::NC], int (&sel)[2 * NodeTraits<EQ>::NC])
@@ -340,8 +371,10 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
     } else {
         constexpr int NC = NodeTraits<EQ>::NC, QR = 2 * NC;
         const double *nl = w0 + (G - 1) * ns, *nr = w0 + G * ns;
-        RoeState r;
-        if constexpr (EQ == EULER1D)
+        RoeState r{};
+        if constexpr (!CH) {
+            // conserved components: no Roe state
+        } else if constexpr (EQ == EULER1D)
             r = roe_state(nl[QR * qs], nl[(QR + 1) * qs], 0.0, nl[(QR + 2) * qs], nr[QR * qs],
                           nr[(QR + 1) * qs], 0.0, nr[(QR + 2) * qs], gm1);
         else
@@ -350,24 +383,24 @@ __device__ __forceinline__ void face_flux(const double *w0, int qs, int ns, cons
         double wh[NC];
         int okmask = 0;  // fields whose top candidate is within delta on every lane
         TopForm<NC> tf;
-        top_form<NC, ORDER, DSTAGED>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
+        top_form<NC, ORDER, DSTAGED, CH>(w0, qs, ns, d0, dqs, dns, r, al, delta, tf);
 #pragma unroll
         for (int s = 0; s < NC; ++s)
-            if (top_wave_ok<NC>(tf, s, delta, shortcut)) okmask |= 1 << s;
+            if (top_wave_ok<NC, CH>(tf, s, delta, shortcut)) okmask |= 1 << s;
         if (okmask == (1 << NC) - 1) {
 #pragma unroll
             for (int s = 0; s < NC; ++s) {
-                wh[s] = tf.hs[s] * (1.0 / (2.0 * field_scale<NC>(s)));
+                wh[s] = tf.hs[s] * (1.0 / (2.0 * fscale<NC, CH>(s)));
                 sel[2 * s] = sel[2 * s + 1] = K - 1;
             }
         } else if constexpr (NC == 4) {
-            field_pass<4, ORDER, 0, 3>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
-            field_pass<4, ORDER, 1, 2>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+            field_pass<4, ORDER, 0, 3, CH>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+            field_pass<4, ORDER, 1, 2, CH>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
         } else {
-            field_pass<3, ORDER, 0, 2>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
-            field_pass<3, ORDER, 1, -1>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+            field_pass<3, ORDER, 0, 2, CH>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
+            field_pass<3, ORDER, 1, -1, CH>(w0, qs, ns, r, al, delta, okmask, tf, wh, sel);
         }
-        back_project<NC>(r, wh, Fh);
+        from_fields<NC, CH>(r, wh, Fh);
     }
 }
 
@@ -430,7 +463,7 @@ template <int EQ, int MODE> struct View {
 // (-1 at the start of a chunk: binary search); the tile lists are ordered by
 // instance, so after the first the walk just moves on to the next instance
 // that has tiles left.
-template <int EQ, int MODE, bool Y>
+template <int EQ, int MODE, bool Y, bool CH>
 __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst, long long tile, int prev)
 {
     constexpr int NC = NodeTraits<EQ>::NC;
@@ -459,6 +492,12 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
     v.base = gmem(uniform(I.u));
     v.lx = gmem(uniform(I.lx));
     v.sel = gmem(uniform(I.sel));
+    if (v.sel && P.sel_slot > 0) {
+        // records of one evaluation: x block [NC][2][ny][nx+1], then in 2D the y block [NC][2][ny+1][nx]
+        const long long rec = (long long)NC * 2 * v.ny * (v.nx + 1) +
+                              (EQ == EULER2D ? (long long)NC * 2 * (v.ny + 1) * v.nx : 0ll);
+        v.sel += (long long)P.sel_slot * rec;
+    }
     v.amax = gmem(uniform(I.amax));
     v.idx = 1.0 / uniform(I.dx);
     v.idy = 1.0 / uniform(I.dy);
@@ -468,10 +507,17 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
     } else {
         const GMEM unsigned long long *a = v.amax + P.r_in * AMAX_VALS + (Y ? 3 : 0);
         const double m0 = uniform(as_double(a[0])), m1 = uniform(as_double(a[1])), m2 = uniform(as_double(a[2]));
-        v.al[0] = m0;
-        v.al[1] = m1;
-        if (NC == 4) v.al[2] = m1;
-        v.al[NC - 1] = m2;
+        if constexpr (CH) {
+            v.al[0] = m0;
+            v.al[1] = m1;
+            if (NC == 4) v.al[2] = m1;
+            v.al[NC - 1] = m2;
+        } else {
+            // one alpha for all components: max(|u| + c) = max(max|u - c|, max|u + c|)
+            const double a = fmax(m0, m2);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v.al[c] = a;
+        }
     }
     return v;
 }
@@ -565,7 +611,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
     }
 }
 
-template <int EQ, int ORDER, int MODE, bool REC>
+template <int EQ, int ORDER, int MODE, bool REC, bool CH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 7 ? ENOAO_X7_WAVES_PER_EU
                                                                   : ENOAO_X_WAVES_PER_EU))) void sweep_x(KParams P)
 {
@@ -599,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
     // waves together).
     int prev = -1;
     for (long long tile = t0; tile < t1;) {
-        const View<EQ, MODE> v = load_view<EQ, MODE, false>(P, n_inst, tile, prev);
+        const View<EQ, MODE> v = load_view<EQ, MODE, false, CH>(P, n_inst, tile, prev);
         prev = v.k;
         const long long tend = v.t1 < t1 ? v.t1 : t1;
         if (!v.active) {
@@ -647,7 +693,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
             if (ok) {
                 double Fh[NC];
                 int sel[2 * NC];
-                face_flux<EQ, ORDER, true>(L + lane, XW_SEGS * NNP, 1, Dl + lane, XW_SEGS * NDN, 1, v.al, P.gm1,
+                face_flux<EQ, ORDER, true, CH>(L + lane, XW_SEGS * NNP, 1, Dl + lane, XW_SEGS * NDN, 1, v.al, P.gm1,
                                            P.delta, v.adv, (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
                 for (int q = 0; q < NC; ++q) fh[(q * XW_SEGS + wseg) * XW_FACES + lane] = Fh[q];
@@ -778,14 +824,14 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
 }
 
 // one face of a y strip into the face buffer (and the selection record)
-template <int ORDER, bool REC, int MODE, int YW>
+template <int ORDER, bool REC, int MODE, int YW, bool CH>
 __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KParams &P, const double *W, int QS,
                                        double *WF, int k, int cc, int col, int f)
 {
     constexpr int NC = 4, CELLS = yt_cells(YW);
     double Fh[NC];
     int sel[2 * NC];
-    face_flux<EULER2D, ORDER, false>(W + k * YW + cc, QS, YW, nullptr, 0, 0, v.al, P.gm1, P.delta, 0.0,
+    face_flux<EULER2D, ORDER, false, CH>(W + k * YW + cc, QS, YW, nullptr, 0, 0, v.al, P.gm1, P.delta, 0.0,
                                      (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
     for (int q = 0; q < NC; ++q) WF[(q * (CELLS + 1) + k) * YW + cc] = Fh[q];
@@ -801,7 +847,7 @@ __device__ __forceinline__ void y_face(const View<EULER2D, MODE> &v, const KPara
     }
 }
 
-template <int ORDER, int MODE, bool REC, int YW>
+template <int ORDER, int MODE, bool REC, int YW, bool CH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 7 ? ENOAO_Y7_WAVES_PER_EU
                                                                   : ENOAO_Y_WAVES_PER_EU))) void sweep_y(KParams P)
 {
@@ -837,7 +883,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
     // over the workgroup: the maxima flush is reached by all waves together)
     int prev = -1;
     for (long long tile = t0; tile < t1;) {
-        const View<EULER2D, MODE> v = load_view<EULER2D, MODE, true>(P, n_inst, tile, prev);
+        const View<EULER2D, MODE> v = load_view<EULER2D, MODE, true, CH>(P, n_inst, tile, prev);
         prev = v.k;
         const long long tend = v.t1 < t1 ? v.t1 : t1;
         if (!v.active) {
@@ -886,7 +932,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
 #pragma unroll 1
             for (int pass = first ? 0 : 1; pass < 2; ++pass) {
                 const int k = pass == 0 ? 0 : fl + 1;
-                if (pass == 1 || lane < YW) y_face<ORDER, REC, MODE, YW>(v, P, W, QS, WF, k, cc, col, sy + k);
+                if (pass == 1 || lane < YW) y_face<ORDER, REC, MODE, YW, CH>(v, P, W, QS, WF, k, cc, col, sy + k);
             }
             wave_sync();
 
@@ -1073,7 +1119,7 @@ __device__ __forceinline__ void resident_reduce(Maxima<EQ> &mx, double *red, dou
     __syncthreads();
 }
 
-template <int EQ, int ORDER, int MODE>
+template <int EQ, int ORDER, int MODE, bool CH>
 __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, int n, double *un, double *w,
                                                double *fx, double *q, double *red, double *cm, Ctrl &C, double dt)
 {
@@ -1084,10 +1130,14 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
     double al[NC];
     if constexpr (EQ == ADVECTION) {
         al[0] = fabs(I.adv);
-    } else {
+    } else if constexpr (CH) {
         al[0] = cm[0];
         al[1] = cm[1];
         al[NC - 1] = cm[2];
+    } else {
+        const double a = fmax(cm[0], cm[2]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) al[c] = a;
     }
     const double *in = MODE == M_S1 ? un : w;
     for (int c0 = 0; c0 <= n; c0 += RES_BLOCK) {
@@ -1105,7 +1155,7 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
         if (f <= n) {
             double Fh[NC];
             int sel[2 * NC];
-            face_flux<EQ, ORDER, false>(q + tid, QS, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv,
+            face_flux<EQ, ORDER, false, CH>(q + tid, QS, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv,
                                         (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
             for (int c = 0; c < NC; ++c) fx[c * (n + 1) + f] = Fh[c];
@@ -1130,7 +1180,7 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
     resident_reduce<EQ>(mx, red, cm, C);
 }
 
-template <int EQ, int ORDER>
+template <int EQ, int ORDER, bool CH>
 __global__ __launch_bounds__(RES_BLOCK) void resident_1d(KParams P, int nsteps)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
@@ -1168,9 +1218,9 @@ __global__ __launch_bounds__(RES_BLOCK) void resident_1d(KParams P, int nsteps)
         __syncthreads();
         if (!go) break;  // uniform: read after the barrier by every thread
         const double dt = C.dt;
-        resident_stage<EQ, ORDER, M_S1>(P, I, n, un, w, fx, q, red, cm, C, dt);
-        resident_stage<EQ, ORDER, M_S2>(P, I, n, un, w, fx, q, red, cm, C, dt);
-        resident_stage<EQ, ORDER, M_S3>(P, I, n, un, w, fx, q, red, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S1, CH>(P, I, n, un, w, fx, q, red, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S2, CH>(P, I, n, un, w, fx, q, red, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S3, CH>(P, I, n, un, w, fx, q, red, cm, C, dt);
     }
     for (int i = tid; i < NC * n; i += RES_BLOCK) ug[i] = un[i];
     if (tid == 0) *I.ctrl = C;
@@ -1208,46 +1258,48 @@ __global__ void set_dt(KParams P, double dt)
 using KFn = void (*)(KParams);
 using KFn2 = void (*)(KParams, int);
 
-template <int EQ, int ORDER, bool REC> static KFn pick_x_mode(int mode)
+template <int EQ, int ORDER, bool REC, bool CH> static KFn pick_x_mode(int mode)
 {
     switch (mode) {
-    case M_RHS: return sweep_x<EQ, ORDER, M_RHS, REC>;
-    case M_S1: return sweep_x<EQ, ORDER, M_S1, REC>;
-    case M_S2: return sweep_x<EQ, ORDER, M_S2, REC>;
-    default: return sweep_x<EQ, ORDER, M_S3, REC>;
+    case M_RHS: return sweep_x<EQ, ORDER, M_RHS, REC, CH>;
+    case M_S1: return sweep_x<EQ, ORDER, M_S1, REC, CH>;
+    case M_S2: return sweep_x<EQ, ORDER, M_S2, REC, CH>;
+    default: return sweep_x<EQ, ORDER, M_S3, REC, CH>;
     }
 }
-template <int EQ, bool REC> static KFn pick_x_order(int order, int mode)
+template <int EQ, bool REC, bool CH> static KFn pick_x_order(int order, int mode)
 {
-    return order == 7 ? pick_x_mode<EQ, 7, REC>(mode) : pick_x_mode<EQ, 5, REC>(mode);
+    return order == 7 ? pick_x_mode<EQ, 7, REC, CH>(mode) : pick_x_mode<EQ, 5, REC, CH>(mode);
 }
-template <int EQ> static KFn pick_x_rec(int order, int mode, bool rec)
+template <int EQ, bool CH> static KFn pick_x_rec(int order, int mode, bool rec)
 {
-    return rec ? pick_x_order<EQ, true>(order, mode) : pick_x_order<EQ, false>(order, mode);
+    return rec ? pick_x_order<EQ, true, CH>(order, mode) : pick_x_order<EQ, false, CH>(order, mode);
 }
-static KFn pick_x(int eq, int order, int mode, bool rec)
+// ch: characteristic fields (advection has one variable and always takes this path)
+static KFn pick_x(int eq, int order, int mode, bool rec, bool ch)
 {
-    if (eq == ADVECTION) return pick_x_rec<ADVECTION>(order, mode, rec);
-    if (eq == EULER1D) return pick_x_rec<EULER1D>(order, mode, rec);
-    return pick_x_rec<EULER2D>(order, mode, rec);
+    if (eq == ADVECTION) return pick_x_rec<ADVECTION, true>(order, mode, rec);
+    if (eq == EULER1D) return ch ? pick_x_rec<EULER1D, true>(order, mode, rec) : pick_x_rec<EULER1D, false>(order, mode, rec);
+    return ch ? pick_x_rec<EULER2D, true>(order, mode, rec) : pick_x_rec<EULER2D, false>(order, mode, rec);
 }
-template <int ORDER, bool REC, int YW> static KFn pick_y_mode(int mode)
+template <int ORDER, bool REC, int YW, bool CH> static KFn pick_y_mode(int mode)
 {
     switch (mode) {
-    case M_RHS: return sweep_y<ORDER, M_RHS, REC, YW>;
-    case M_S1: return sweep_y<ORDER, M_S1, REC, YW>;
-    case M_S2: return sweep_y<ORDER, M_S2, REC, YW>;
-    default: return sweep_y<ORDER, M_S3, REC, YW>;
+    case M_RHS: return sweep_y<ORDER, M_RHS, REC, YW, CH>;
+    case M_S1: return sweep_y<ORDER, M_S1, REC, YW, CH>;
+    case M_S2: return sweep_y<ORDER, M_S2, REC, YW, CH>;
+    default: return sweep_y<ORDER, M_S3, REC, YW, CH>;
     }
 }
-template <int YW> static KFn pick_y_w(int order, int mode, bool rec)
+template <int YW, bool CH> static KFn pick_y_w(int order, int mode, bool rec)
 {
-    if (order == 7) return rec ? pick_y_mode<7, true, YW>(mode) : pick_y_mode<7, false, YW>(mode);
-    return rec ? pick_y_mode<5, true, YW>(mode) : pick_y_mode<5, false, YW>(mode);
+    if (order == 7) return rec ? pick_y_mode<7, true, YW, CH>(mode) : pick_y_mode<7, false, YW, CH>(mode);
+    return rec ? pick_y_mode<5, true, YW, CH>(mode) : pick_y_mode<5, false, YW, CH>(mode);
 }
-static KFn pick_y(int order, int mode, bool rec, int yw)
+static KFn pick_y(int order, int mode, bool rec, int yw, bool ch)
 {
-    return yw == 4 ? pick_y_w<4>(order, mode, rec) : pick_y_w<8>(order, mode, rec);
+    if (ch) return yw == 4 ? pick_y_w<4, true>(order, mode, rec) : pick_y_w<8, true>(order, mode, rec);
+    return yw == 4 ? pick_y_w<4, false>(order, mode, rec) : pick_y_w<8, false>(order, mode, rec);
 }
 static KFn pick_maxima(int eq)
 {
@@ -1272,14 +1324,14 @@ static int occupancy(KFn fn)
     return n;
 }
 
-hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s)
+hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, bool ch, const KParams &p, int grid, hipStream_t s)
 {
-    return launch(pick_x(eq, order, mode, rec), grid, BLOCK, p, s);
+    return launch(pick_x(eq, order, mode, rec, ch), grid, BLOCK, p, s);
 }
 
-hipError_t launch_sweep_y(int order, int mode, bool rec, int yw, const KParams &p, int grid, hipStream_t s)
+hipError_t launch_sweep_y(int order, int mode, bool rec, bool ch, int yw, const KParams &p, int grid, hipStream_t s)
 {
-    return launch(pick_y(order, mode, rec, yw), grid, BLOCK, p, s);
+    return launch(pick_y(order, mode, rec, yw, ch), grid, BLOCK, p, s);
 }
 
 hipError_t launch_state_maxima(int eq, const KParams &p, int grid, hipStream_t s)
@@ -1317,16 +1369,18 @@ hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s)
     return launch(clear_done, (n_inst + 63) / 64, 64, p, s);
 }
 
-static KFn2 pick_resident(int eq, int order)
+static KFn2 pick_resident(int eq, int order, bool ch)
 {
-    if (eq == ADVECTION) return order == 7 ? resident_1d<ADVECTION, 7> : resident_1d<ADVECTION, 5>;
-    return order == 7 ? resident_1d<EULER1D, 7> : resident_1d<EULER1D, 5>;
+    if (eq == ADVECTION) return order == 7 ? resident_1d<ADVECTION, 7, true> : resident_1d<ADVECTION, 5, true>;
+    if (ch) return order == 7 ? resident_1d<EULER1D, 7, true> : resident_1d<EULER1D, 5, true>;
+    return order == 7 ? resident_1d<EULER1D, 7, false> : resident_1d<EULER1D, 5, false>;
 }
 
-hipError_t launch_resident(int eq, int order, const KParams &p, int n_inst, int nsteps, size_t lds, hipStream_t s)
+hipError_t launch_resident(int eq, int order, bool ch, const KParams &p, int n_inst, int nsteps, size_t lds,
+                           hipStream_t s)
 {
     if (eq == EULER2D) return hipErrorInvalidValue;
-    const KFn2 fn = pick_resident(eq, order);
+    const KFn2 fn = pick_resident(eq, order, ch);
     // dynamic LDS beyond the default limit must be allowed per kernel
     const hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1344,8 +1398,11 @@ size_t resident_lds_limit()
     return v > 256 ? (size_t)v - 256 : 0;
 }
 
-int occupancy_x(int eq, int order, int mode, bool rec) { return occupancy(pick_x(eq, order, mode, rec)); }
-int occupancy_y(int order, int mode, bool rec, int yw) { return occupancy(pick_y(order, mode, rec, yw)); }
+int occupancy_x(int eq, int order, int mode, bool rec, bool ch) { return occupancy(pick_x(eq, order, mode, rec, ch)); }
+int occupancy_y(int order, int mode, bool rec, bool ch, int yw)
+{
+    return occupancy(pick_y(order, mode, rec, yw, ch));
+}
 int occupancy_maxima(int eq) { return occupancy(pick_maxima(eq)); }
 
 }  // namespace enoao

@@ -23,6 +23,7 @@ struct KParams {
     int r_out;   // slot receiving the maxima of the stage output (-1: none)
     int r_zero;  // slot cleared by the first kernel of the stage (-1: none)
     int flags;   // KF_* below
+    int sel_slot;  // selection record a recording launch writes (0..2: the stage's record)
     // LDS-resident launches: member run by workgroup b (members by decreasing
     // size, so the small ones fill the machine behind the large; null: member b)
     const int *res_order;
@@ -32,10 +33,12 @@ struct KParams {
 // the same either way, which this flag lets a caller check
 constexpr int KF_FULL_SELECTION = 1;
 
-hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, const KParams &p, int grid, hipStream_t s);
+// ch: reconstruct in the characteristic fields of the Roe state (false: in the
+// conserved components; advection ignores it)
+hipError_t launch_sweep_x(int eq, int order, int mode, bool rec, bool ch, const KParams &p, int grid, hipStream_t s);
 // yw: columns per wave strip of the y tiles (4 or 8; the members' y tile lists
 // must have been built for the same width)
-hipError_t launch_sweep_y(int order, int mode, bool rec, int yw, const KParams &p, int grid, hipStream_t s);
+hipError_t launch_sweep_y(int order, int mode, bool rec, bool ch, int yw, const KParams &p, int grid, hipStream_t s);
 hipError_t launch_state_maxima(int eq, const KParams &p, int grid, hipStream_t s);
 hipError_t launch_reset_maxima(const KParams &p, int n_inst, hipStream_t s);
 hipError_t launch_step_control(int eq, const KParams &p, int n_inst, hipStream_t s);
@@ -44,13 +47,14 @@ hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, boo
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
 // nsteps controlled steps of every member (all 1D, all fitting the LDS), one
 // workgroup per member; lds = dynamic LDS bytes per workgroup
-hipError_t launch_resident(int eq, int order, const KParams &p, int n_inst, int nsteps, size_t lds, hipStream_t s);
+hipError_t launch_resident(int eq, int order, bool ch, const KParams &p, int n_inst, int nsteps, size_t lds,
+                           hipStream_t s);
 // largest dynamic LDS a resident workgroup may use on this device (0: none)
 size_t resident_lds_limit();
 
 // resident workgroups per CU of each kernel (for persistent grid sizes)
-int occupancy_x(int eq, int order, int mode, bool rec);
-int occupancy_y(int order, int mode, bool rec, int yw);
+int occupancy_x(int eq, int order, int mode, bool rec, bool ch);
+int occupancy_y(int order, int mode, bool rec, bool ch, int yw);
 int occupancy_maxima(int eq);
 
 }  // namespace enoao

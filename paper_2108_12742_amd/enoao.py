@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libenoao.so")
 
 ADVECTION, EULER1D, EULER2D = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+CHAR_ROE, COMPONENT = 0, 1  # reconstruction variables of the Euler systems
+_RV = {"characteristic": CHAR_ROE, "component": COMPONENT}
 F_RECORD_SELECTION = 1
 MAX_EXTENT = 2**31 - 1024  # largest nx or ny (ENOAO_MAX_EXTENT); nx * ny <= 2**31
 NCOMP = {ADVECTION: 1, EULER1D: 3, EULER2D: 4}
@@ -31,7 +33,7 @@ class Problem(ctypes.Structure):
     """enoao_problem"""
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("equation", ctypes.c_int32), ("order", ctypes.c_int32),
-        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("recon_vars", ctypes.c_int32),
         ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
         ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
@@ -50,19 +52,20 @@ class Problem(ctypes.Structure):
 
 def make_problem(equation, nx, ny=1, order=5, x_lo=-1.0, x_hi=1.0, y_lo=-1.0, y_hi=1.0,
                  bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, gamma=1.4, adv_speed=1.0, delta=1e-5,
-                 record_selection=False) -> Problem:
+                 record_selection=False, recon_vars=CHAR_ROE) -> Problem:
     eq = _EQ[equation] if isinstance(equation, str) else int(equation)
+    rv = _RV[recon_vars] if isinstance(recon_vars, str) else int(recon_vars)
     bcx = _BC[bc_x] if isinstance(bc_x, str) else int(bc_x)
     bcy = _BC[bc_y] if isinstance(bc_y, str) else int(bc_y)
-    return Problem(ctypes.sizeof(Problem), eq, order, nx, ny, 0, x_lo, x_hi, y_lo, y_hi, bcx, bcy,
+    return Problem(ctypes.sizeof(Problem), eq, order, nx, ny, rv, x_lo, x_hi, y_lo, y_hi, bcx, bcy,
                    gamma, adv_speed, delta, F_RECORD_SELECTION if record_selection else 0, 0)
 
 
-def problem_from_instance(inst, order=5, delta=1e-5, record_selection=False) -> Problem:
+def problem_from_instance(inst, order=5, delta=1e-5, record_selection=False, recon_vars=CHAR_ROE) -> Problem:
     """Problem for a workloads.Instance."""
     return make_problem(inst.equation, inst.nx, inst.ny, order, inst.x_lo, inst.x_hi, inst.y_lo,
                         inst.y_hi, inst.bc_x, inst.bc_y, inst.gamma, inst.adv_speed, delta,
-                        record_selection)
+                        record_selection, recon_vars)
 
 
 class EnoaoError(RuntimeError):
@@ -94,6 +97,7 @@ def lib():
             "enoao_plan_check": ([vp, vp], st),
             "enoao_selection_size": ([vp], ctypes.c_size_t),
             "enoao_get_selection": ([vp, vp, ctypes.c_size_t, vp], st),
+            "enoao_get_step_selection": ([vp, vp, ctypes.c_size_t, vp], st),
             "enoao_batch_create": ([pp, ctypes.c_int32, vp, ctypes.POINTER(vp)], st),
             "enoao_batch_destroy": ([vp], st),
             "enoao_batch_step": ([vp, ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_double,
@@ -238,6 +242,15 @@ def enoao_get_selection(plan: Plan, stream=None) -> np.ndarray:
     out = np.zeros(n, np.uint8)
     _check(lib().enoao_get_selection(plan.handle, out.ctypes.data_as(ctypes.c_void_p), n, _stream(stream)),
            "enoao_get_selection")
+    return out
+
+
+def enoao_get_step_selection(plan: Plan, stream=None) -> np.ndarray:
+    """the three stage records of the last step, stage 1 first (3 * enoao_selection_size)"""
+    n = 3 * enoao_selection_size(plan)
+    out = np.zeros(n, np.uint8)
+    _check(lib().enoao_get_step_selection(plan.handle, out.ctypes.data_as(ctypes.c_void_p), n, _stream(stream)),
+           "enoao_get_step_selection")
     return out
 
 

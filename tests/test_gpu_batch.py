@@ -38,8 +38,9 @@ def test_batch_1d_members_match_alone_and_oracle():
         assert torch.equal(us[k].cpu(), torch.from_numpy(ref)), f"member {k} (N={sizes[k]}) differs from alone"
         assert t[k] == ta
     for k in (0, 4):
-        ur, _, _ = O.solve(PT.oracle_problem(probs[k]), insts[k].u0, 1e300, cfl=0.3, max_steps=10)
-        PT.assert_close_by_component(us[k].cpu().numpy(), ur, rtol=1e-11, what=f"member {k}")
+        ur, _, _, _, _ = PT.lockstep_solve(torch, E, probs[k], insts[k].u0, 1e300, cfl=0.3, max_steps=10,
+                                           what=f"member {k}")
+        assert np.array_equal(us[k].cpu().numpy(), ur)
 
 
 def test_batch_continues_across_calls_and_stops_at_t_final():
@@ -165,7 +166,8 @@ def test_c3_full_batch_sampled_members():
     """The batched workload at its full size (512 seeded 1D Euler members, N from 128 to
     16384, sum of N about 1.9M) in one batch at the default launch shape: every member
     takes its 5 CFL steps without a non-physical state, and sampled members (the
-    smallest, the largest and six more) match the oracle's time loop."""
+    smallest, the largest and six more) equal their solve alone, whose every step
+    matches the oracle (tests/parity.py lockstep_solve)."""
     torch = PT.torch_cuda()
     E = _E()
     insts = W.batch_1d(0, 512)
@@ -179,17 +181,18 @@ def test_c3_full_batch_sampled_members():
     rng = np.random.default_rng(5)
     pick = sorted({int(sizes.argmin()), int(sizes.argmax())} | {int(k) for k in rng.choice(512, 6, replace=False)})
     for k in pick:
-        ur, tr, nr = O.solve(PT.oracle_problem(probs[k]), insts[k].u0, 1e300, cfl=0.3, max_steps=5)
-        assert nr == 5 and abs(t[k] / tr - 1) <= 1e-14
-        PT.assert_close_by_component(us[k].cpu().numpy(), ur, rtol=1e-11, what=f"member {k} (N={sizes[k]})")
+        ur, nr, tr, _, _ = PT.lockstep_solve(torch, E, probs[k], insts[k].u0, 1e300, cfl=0.3, max_steps=5,
+                                             what=f"member {k} (N={sizes[k]})")
+        assert nr == 5 and t[k] == tr
+        assert np.array_equal(us[k].cpu().numpy(), ur), f"member {k} differs from its solve alone"
 
 
 @pytest.mark.slow
 def test_c4_served_workload_sampled_requests():
     """The served workload at its full size (200 seeded requests, N x N with N from 128 to
     1024, 50 steps each) submitted at once to the server with the benchmark's pool: every
-    request succeeds; sampled requests equal their solve alone bitwise, and the smallest
-    matches the oracle's time loop."""
+    request succeeds; sampled requests equal their solve alone bitwise, and every step
+    of the smallest matches the oracle (tests/parity.py lockstep_solve)."""
     torch = PT.torch_cuda()
     E = _E()
     from paper_2108_12742_amd import serve as S
@@ -206,9 +209,10 @@ def test_c4_served_workload_sampled_requests():
         ref, _, n = _alone(torch, E, data[k], 50)
         assert n == 50
         np.testing.assert_array_equal(reqs[k].result, ref)
-    ur, _, nr = O.solve(PT.oracle_problem(probs[small]), data[small].u0, 1e300, cfl=0.3, max_steps=50)
+    ur, nr, _, _, _ = PT.lockstep_solve(torch, E, probs[small], data[small].u0, 1e300, cfl=0.3, max_steps=50,
+                                        what=f"request {small} (N={sizes[small]})")
     assert nr == 50
-    PT.assert_close_by_component(reqs[small].result, ur, rtol=1e-11, what=f"request {small} (N={sizes[small]})")
+    np.testing.assert_array_equal(reqs[small].result, ur)
 
 
 def test_pool_1d_order7_members():

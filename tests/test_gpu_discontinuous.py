@@ -5,9 +5,10 @@ wave-uniform top-candidate shortcut is rarely taken, so these runs exercise the 
 selection path.
 
 Per step: from the oracle's state, the GPU's L (with selections) and one GPU step match
-the oracle.  Whole runs: step counts and end times match, and the GPU's error against the
-exact solution agrees with the oracle's (the two trajectories may part at rounding-level
-near-ties, so the end states are compared through their errors, not cell by cell)."""
+the oracle at every cell, with the GPU's choices replayed by the oracle at near ties.
+Whole runs: every step of the GPU's run is checked from the GPU's state before it (same
+dt, every cell at 1e-12), the one-call device loop equals the stepped run bitwise, and
+the oracle's own run takes as many steps to the same end time."""
 import numpy as np
 import pytest
 
@@ -27,6 +28,10 @@ def _E():
 
 
 def _trajectory_parity(torch, E, inst, order, nsteps, cfl=0.3):
+    """Along the oracle's trajectory: per step, L with its selection record and the
+    step with its three stage records against the oracle, which replays the GPU's picks
+    at near ties (tests/parity.py); the streaming plan without a record takes bitwise
+    the same step.  The trajectory continues from the replayed oracle state."""
     ep = E.problem_from_instance(inst, order=order, record_selection=True)
     op = PT.oracle_problem(ep)
     plan_rec = E.enoao_plan_create(ep)
@@ -38,14 +43,13 @@ def _trajectory_parity(torch, E, inst, order, nsteps, cfl=0.3):
         L = torch.empty_like(u)
         E.enoao_rhs(plan_rec, u, L)
         sel = E.enoao_get_selection(plan_rec)
-        Lr, selr, tier = O.rhs(op, ur, with_selection=True)
-        mask = PT.compare_selection(op, sel, selr, tier)
-        PT.assert_close_by_component(L.cpu().numpy(), Lr, mask=mask, what=f"L step {k}")
-        low += int((selr < O.num_candidates(order) - 1).sum())
+        PT.check_rhs(op, ur, L.cpu().numpy(), sel, what=f"L step {k}")
+        low += int((np.asarray(sel) < O.num_candidates(order) - 1).sum())
         dt = O.cfl_dt(op, ur, cfl)
+        got, recs = PT.gpu_step_recorded(torch, E, plan_rec, ur, dt)
         E.enoao_step(plan, u, dt)
-        ur = O.step(op, ur, dt)
-        PT.assert_close_by_component(u.cpu().numpy(), ur, mask=mask, what=f"u step {k}")
+        assert np.array_equal(u.cpu().numpy(), got)
+        ur = PT.check_step(op, ur, dt, got, recs, what=f"u step {k}")
     return low
 
 
@@ -58,24 +62,25 @@ def test_combination_wave_steps(order):
     assert low > 0  # lower-order candidates were taken and compared
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.slow
 @pytest.mark.parametrize("order", [5, 7])
 def test_combination_wave_ten_periods(order):
-    """N = 400 (dx = 1/200), t = 20 as in Section 4.1: 13334 CFL steps on the GPU and in
-    the oracle."""
+    """N = 400 (dx = 1/200), t = 20 as in Section 4.1: all 13334 CFL steps checked one by
+    one against the oracle (tests/parity.py lockstep_solve: same dt, every cell at 1e-12
+    with the GPU's picks replayed at near ties), the one-call device loop bitwise equal
+    to the stepped run, and the oracle's own run taking as many steps; the profile stays
+    within its bounds."""
     torch = PT.torch_cuda()
     E = _E()
     inst = W.combination_wave(400)
     ep = E.problem_from_instance(inst, order=order)
-    plan = E.enoao_plan_create(ep)
-    u = PT.to_dev(torch, inst.u0)
-    t, n = E.enoao_solve(plan, u, 20.0, cfl=0.3)
-    ur, tr, nr = O.solve(PT.oracle_problem(ep), inst.u0, 20.0, cfl=0.3)
+    print(f"combination wave to t = 20, order {order}", flush=True)
+    g, n, t, flagged, alt = PT.lockstep_solve(torch, E, ep, inst.u0, 20.0, cfl=0.3, what="combination")
+    print(f"{n} steps, {flagged} flagged face sides, {alt} other tie picks", flush=True)
+    _, tr, nr = O.solve(PT.oracle_problem(ep), inst.u0, 20.0, cfl=0.3)
     assert n == nr and t == tr == 20.0
-    g = u.cpu().numpy()[0, 0]
-    e_g = np.abs(g - inst.u0[0, 0]).mean()
-    e_r = np.abs(ur[0, 0] - inst.u0[0, 0]).mean()
-    assert abs(e_g / e_r - 1) < 1e-3, (e_g, e_r)
-    assert np.abs(g - ur[0, 0]).max() < 1e-5
+    g = g[0, 0]
     assert g.max() <= 1.0 + 1e-3 and g.min() >= -1e-3
 
 
@@ -96,14 +101,10 @@ def test_lax_tube_to_t026(order):
     E = _E()
     inst = W.lax_tube(200)
     ep = E.problem_from_instance(inst, order=order)
-    plan = E.enoao_plan_create(ep)
-    u = PT.to_dev(torch, inst.u0)
-    t, n = E.enoao_solve(plan, u, 0.26, cfl=0.3)
+    g, n, t, _, _ = PT.lockstep_solve(torch, E, ep, inst.u0, 0.26, cfl=0.3, what="Lax tube")
     ur, tr, nr = O.solve(PT.oracle_problem(ep), inst.u0, 0.26, cfl=0.3)
     assert n == nr and t == tr == 0.26
     ex = RX.sample(*LAX, W.nodes(0.0, 2.0, 200), 1.0, 0.26)
-    g = u.cpu().numpy()
     e_g = np.abs(g[0, 0] - ex[0]).mean()
     e_r = np.abs(ur[0, 0] - ex[0]).mean()
-    assert abs(e_g / e_r - 1) < 1e-6, (e_g, e_r)
-    PT.assert_close_by_component(g, ur, rtol=1e-9, what="u(t=0.26)")
+    assert abs(e_g / e_r - 1) < 1e-6 and e_g < 0.012, (e_g, e_r)

@@ -18,7 +18,8 @@ def _E():
 def _solve(torch, E, inst, order, resident, t_final=1e300, max_steps=40, cfl=0.3, profile=False):
     E.enoao_set_resident(resident)
     try:
-        plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order))
+        plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order,
+                                                           recon_vars=inst.meta.get("recon", 0)))
         if profile:
             E.enoao_profile(plan, True)
         u = PT.to_dev(torch, inst.u0)
@@ -39,6 +40,10 @@ def _case(kind, n, seed):
         inst = _case("adv", n, seed)
         inst.adv_speed = -0.8
         return inst
+    if kind == "e1-comp":
+        inst = W.riemann_1d(seed, n)
+        inst.meta["recon"] = "component"
+        return inst
     if kind == "e1-periodic":
         inst = W.riemann_1d(seed, n)
         inst.bc_x = "periodic"
@@ -47,7 +52,8 @@ def _case(kind, n, seed):
 
 
 CASES = [("adv", 1, 5), ("adv", 200, 5), ("adv-left", 513, 7), ("adv", 3000, 5), ("e1", 5, 5), ("e1", 63, 5),
-         ("e1", 512, 5), ("e1", 513, 7), ("e1-periodic", 700, 5), ("e1", 1024, 5), ("e1", 1500, 7)]
+         ("e1", 512, 5), ("e1", 513, 7), ("e1-periodic", 700, 5), ("e1", 1024, 5), ("e1", 1500, 7),
+         ("e1-comp", 900, 5), ("e1-comp", 600, 7)]
 
 
 @pytest.mark.parametrize("kind,n,order", CASES, ids=[f"{k}-{n}-ao{o}" for k, n, o in CASES])
@@ -61,10 +67,11 @@ def test_resident_bitwise_equals_streaming_and_matches_oracle(kind, n, order):
     assert prof["resident"][1] > 0, "the LDS-resident solver did not run"
     assert (tr, nr) == (ts, ns) and nr == 40
     assert torch.equal(ur, us), "resident and streaming results differ"
-    ep = E.problem_from_instance(inst, order=order)
-    uo, to, no = O.solve(PT.oracle_problem(ep), inst.u0, 1e300, cfl=0.3, max_steps=40)
-    assert no == nr and abs(to - tr) <= 1e-14 * abs(to)
-    PT.assert_close_by_component(ur.numpy(), uo, rtol=1e-11, what="u")
+    ep = E.problem_from_instance(inst, order=order, recon_vars=inst.meta.get("recon", 0))
+    # every step against the oracle; the stepped streaming run equals the resident one
+    uo, no, to, _, _ = PT.lockstep_solve(torch, E, ep, inst.u0, 1e300, cfl=0.3, max_steps=40, what=f"{kind} N={n}")
+    assert no == nr and to == tr
+    assert np.array_equal(ur.numpy(), uo)
 
 
 def test_resident_stops_at_t_final_and_resumes():
