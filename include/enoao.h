@@ -137,6 +137,27 @@ enoao_status enoao_step(enoao_plan *plan, double *u, double dt, void *stream);
 enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl, double dt_fixed,
                          int64_t max_steps, double *t_out, int64_t *steps_out, void *stream);
 
+/* Bytes of the per-device array that enoao_step_noalloc works in (64 MiB). */
+#define ENOAO_NOALLOC_SCRATCH_BYTES 67108864
+
+/* enoao_step without a plan and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid allocation): one third-order TVD Runge-Kutta step of size dt > 0
+ * of the problem *prob, in place on the caller's device state u (layout as
+ * above), enqueued on stream.  The result is bitwise that of enoao_step on a
+ * plan of *prob (the same kernel launches).
+ * Workspace: a file-scope device array of ENOAO_NOALLOC_SCRATCH_BYTES that each
+ * GPU the library runs on holds until the process ends; the call uses
+ * 1024 + B * (ncomp*nx*ny + 544) * 8 bytes of it (B = 3 buffers for Euler 2D,
+ * 2 otherwise), e.g. up to about 836 x 836 nodes for Euler 2D or 1.39 million
+ * for Euler 1D; a larger problem returns ENOAO_EINVAL, as do
+ * ENOAO_F_RECORD_SELECTION and the arguments enoao_step rejects.  Every call on
+ * a GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * A non-physical state is not reported (there is no plan to hold the flag).
+ * ENOAO_EDEVICE if the array's device address cannot be obtained. */
+enoao_status enoao_step_noalloc(const enoao_problem *prob, double *u, double dt, void *stream);
+
 /* Synchronises stream and returns ENOAO_ENONPHYSICAL if any device-side check
  * of the plan failed since the last synchronising call (then clears it). */
 enoao_status enoao_plan_check(enoao_plan *plan, void *stream);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -496,6 +497,57 @@ struct enoao_plan {
     double *ws_lx = nullptr;  // 2D: Lx workspace (inside the runtime allocation)
 };
 
+// ---------------------------------------------------------------------------
+// Allocation-free step (enoao_step_noalloc).  Its workspace -- the batch
+// header, the member descriptor, the control block, the maxima ring and the
+// stage buffers -- lives in one file-scope device array per GPU.  Host code
+// never uses the array's name as an address: the device address is taken once
+// per device with hipGetSymbolAddress and kept in noalloc_ptr.
+namespace {
+
+__device__ __align__(256) unsigned char scratch[ENOAO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mutex;
+void *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this device's scratch array (nullptr on failure)
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        noalloc_ptr[device] = ptr;
+    }
+    return noalloc_ptr[device];
+}
+
+// scratch layout: header, descriptor, control, maxima ring, then the stage buffers
+constexpr size_t NA_HDR = 0, NA_INST = 256, NA_CTRL = 512, NA_AMAX = 768, NA_MEM = 1024;
+static_assert(sizeof(BatchHdr) <= 256 && sizeof(Inst) <= 256 && sizeof(Ctrl) <= 256 &&
+                  AMAX_SLOTS * AMAX_VALS * 8 <= 256, "scratch header slots");
+
+size_t noalloc_bytes(const enoao_problem *p)
+{
+    const size_t cells = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
+    return NA_MEM + (p->equation == EULER2D ? 3 : 2) * (cells + BUF_STAGGER) * sizeof(double);
+}
+
+// writes the descriptor, header and control block of the one member (kernel
+// arguments by value: no host-to-device copy of pageable memory)
+__global__ void noalloc_init(BatchHdr h, Inst I, Ctrl c, BatchHdr *dh, Inst *di, Ctrl *dc)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *dh = h;
+        *di = I;
+        *dc = c;
+    }
+}
+
+}  // namespace
+
 struct enoao_batch {
     Runtime rt;
     std::vector<const double *> bound;  // member states currently in the descriptors
@@ -775,6 +827,57 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
     if (steps_out) *steps_out = h.steps;
     if (st == ENOAO_OK && h.status) st = ENOAO_ENONPHYSICAL;
     return st;
+}
+
+enoao_status enoao_step_noalloc(const enoao_problem *prob, double *u, double dt, void *stream)
+{
+    if (!prob || !u || !(dt > 0.0) || !std::isfinite(dt)) return ENOAO_EINVAL;
+    if (check_problem(prob) || (prob->flags & ENOAO_F_RECORD_SELECTION)) return ENOAO_EINVAL;
+    if (noalloc_bytes(prob) > (size_t)ENOAO_NOALLOC_SCRATCH_BYTES) return ENOAO_EINVAL;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    char *base = (char *)noalloc_scratch(device);
+    if (!base) return ENOAO_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+
+    // a one-member runtime over the scratch array (nothing in it allocates)
+    Runtime rt;
+    rt.eq = prob->equation;
+    rt.order = prob->order;
+    rt.yw = yw_default(rt.order);
+    rt.nc = ncomp_of(rt.eq);
+    rt.n = rt.n_cap = 1;
+    rt.gamma = prob->gamma;
+    rt.delta = prob->delta;
+    rt.rec = false;
+    rt.ch = prob->recon_vars == ENOAO_CHAR_ROE;
+    rt.device = device;
+    HIP_TRY(hipDeviceGetAttribute(&rt.cus, hipDeviceAttributeMultiprocessorCount, device));
+    rt.d_hdr = (BatchHdr *)(base + NA_HDR);
+    rt.d_inst = (Inst *)(base + NA_INST);
+    rt.d_ctrl = (Ctrl *)(base + NA_CTRL);
+    rt.d_amax = (unsigned long long *)(base + NA_AMAX);
+    rt.d_res_order = nullptr;
+    double *m = (double *)(base + NA_MEM);
+    const size_t cells = (size_t)rt.nc * prob->nx * prob->ny;
+    Inst I;
+    long long xt = 0, yt = 0;
+    rt.fill_inst(I, *prob, u, member_buffer(m, cells, 0), member_buffer(m, cells, 1),
+                 rt.eq == EULER2D ? member_buffer(m, cells, 2) : nullptr, nullptr, rt.d_amax, rt.d_ctrl, xt, yt);
+    rt.h_hdr.n_inst = 1;
+    rt.h_hdr.xtiles_total = xt;
+    rt.h_hdr.ytiles_total = yt;
+    rt.wg_per_cu = g_wg_per_cu;
+    rt.set_grids();
+    Ctrl c;
+    std::memset(&c, 0, sizeof(Ctrl));
+    c.t_final = INFINITY;
+    // the same launches as enoao_step: descriptors, maxima of u, the step size, three stages
+    hipLaunchKernelGGL(noalloc_init, dim3(1), dim3(64), 0, s, rt.h_hdr, I, c, rt.d_hdr, rt.d_inst, rt.d_ctrl);
+    HIP_TRY(hipGetLastError());
+    if (enoao_status e = rt.reset_and_maxima(s)) return e;
+    HIP_TRY(launch_set_dt(rt.params(0, -1, -1), 1, dt, s));
+    return rt.steps(1, false, s);
 }
 
 enoao_status enoao_plan_check(enoao_plan *plan, void *stream)

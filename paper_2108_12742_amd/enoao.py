@@ -95,6 +95,7 @@ def lib():
             "enoao_solve": ([vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp], st),
             "enoao_plan_check": ([vp, vp], st),
+            "enoao_step_noalloc": ([pp, vp, ctypes.c_double, vp], st),
             "enoao_selection_size": ([vp], ctypes.c_size_t),
             "enoao_get_selection": ([vp, vp, ctypes.c_size_t, vp], st),
             "enoao_get_step_selection": ([vp, vp, ctypes.c_size_t, vp], st),
@@ -227,6 +228,12 @@ def enoao_solve(plan: Plan, u, t_final, cfl=0.0, dt_fixed=0.0, max_steps=1 << 62
                              float(dt_fixed), int(max_steps), ctypes.byref(t), ctypes.byref(n),
                              _stream(stream)), "enoao_solve")
     return t.value, n.value
+
+
+def enoao_step_noalloc(problem: Problem, u, dt, stream=None):
+    """One step of `problem` on u in place, in the library's per-device scratch array."""
+    _check(lib().enoao_step_noalloc(ctypes.byref(problem), _dev_ptr(u, problem.shape), float(dt),
+                                    _stream(stream)), "enoao_step_noalloc")
 
 
 def enoao_plan_check(plan: Plan, stream=None):
