@@ -8,8 +8,14 @@ Roe characteristic decomposition, SSP-RK3 with the device-side CFL step
 (CFL 0.3); K timed steps after W warm-up steps, inputs resident in HBM.
 
 Prints one JSON line: cell-updates/s of the whole job, the roofline of the
-dominant kernel (HIP events on the stream the kernels run on), and the CPU
-oracle timed on a bounded sample of the same workload.
+dominant kernel (HIP events on the stream the kernels run on) on the
+algorithmic bytes of its Runge-Kutta stage (64/96/96 B per cell in 2D), the
+step-level rooflines (256 B per cell-update against HBM, executed FP64 flops
+from the committed counters against the FP64 peak), and the CPU oracle timed on
+a bounded sample of the same workload on the host's cores.  Extra legs: the
+smooth advection workload's latency (N = 200, 400 steps), the 1D Euler
+workload (N = 2000 to t = 0.2), the batched and served workloads against their
+plain per-solve launches, order 7, and the paper's discontinuous workloads.
 """
 import argparse
 import json
@@ -30,24 +36,13 @@ def kernel_symbol(kind, order, y_strip_columns):
     2D plan without selection record."""
     stage = int(kind[-1])
     if kind.startswith("sweep_x"):
-        return f"enoao::sweep_x<2, {order}, {stage}, false>"
-    return f"enoao::sweep_y<{order}, {stage}, false, {y_strip_columns}>"
+        return f"enoao::sweep_x<2, {order}, {stage}, false, true>"
+    return f"enoao::sweep_y<{order}, {stage}, false, {y_strip_columns}, true>"
 
 
 def kernel_sources_hash():
-    """sha256 (first 16 hex) of the HIP sources and of the build script that holds the
-    compiler flags: a change to either invalidates the recorded byte counters."""
-    import glob
-    import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(here, "paper_2108_12742_amd", "csrc", "*.hip"))
-                   + glob.glob(os.path.join(here, "paper_2108_12742_amd", "csrc", "*.hpp")))
-    files.append(os.path.join(here, "paper_2108_12742_amd", "build.py"))
-    for f in files:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2108_12742_amd.counters import kernel_sources_hash as h
+    return h()
 
 
 def timed_solve(E, plan, u, u0, K, Wu, cfl=0.3):
@@ -86,38 +81,200 @@ def timed_solve(E, plan, u, u0, K, Wu, cfl=0.3):
     return el, el_inst, prof
 
 
-def measured_traffic(symbol, workload):
-    """HBM bytes per launch of `symbol` from the committed rocprofv3 byte counters
-    (profiles/traffic.json, per workload), or None when the kernels changed since
-    they were taken."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+def _counters(workload):
+    """The committed rocprofv3 counters of a workload (profiles/counters.json), or {}
+    when the kernels changed since they were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "counters.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("source_hash") != kernel_sources_hash():
-        return None
-    v = t.get("workloads", {}).get(workload, {}).get("bytes_per_launch", {}).get(symbol)
+        return {}
+    return t.get("workloads", {}).get(workload, {})
+
+
+def measured_traffic(symbol, workload):
+    """HBM bytes per launch of `symbol` (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
+    known size), or None when the kernels changed since the counters were taken."""
+    v = _counters(workload).get("bytes_per_launch", {}).get(symbol)
     return None if v is None else round(v)
 
 
-def cpu_baseline(n_sample=2048, steps=1):
-    """The oracle (single-threaded C, FP64) on a bounded sample of the workload: the
-    first `steps` of its SSP-RK3 steps (same seeded quadrant problem, same size)."""
+def measured_fp64_flops(symbol, workload):
+    """Executed FP64 flops per launch of `symbol` (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes),
+    or None."""
+    v = _counters(workload).get("fp64_flops_per_launch", {}).get(symbol)
+    return None if v is None else float(v)
+
+
+def kernel_roofline(R, equation, kind, stage, cells, ms, symbol, workload, order):
+    """Roofline of one kernel kind: against HBM on the algorithmic bytes of its stage
+    when it completes a stage, else against the FP64 peak on the essential flops of
+    its faces; with the measured traffic (and its ratio to the algorithmic bytes)
+    and the executed FP64 rate where the committed counters cover the kernel."""
+    kern = kind[6] if kind.startswith("sweep") else "s"
+    nbytes = cells * R.algorithmic_bytes(equation, kern, stage)
+    if nbytes > 0:
+        e = R.hbm_entry(nbytes, ms * 1e-3, measured_traffic(symbol, workload))
+        e["algorithmic_bytes_per_cell"] = R.algorithmic_bytes(equation, kern, stage)
+        if e["traffic"] is not None:
+            e["traffic_ratio"] = round(e["traffic"] / nbytes, 3)
+    else:
+        e = R.alu_entry(cells * R.sweep_flops(equation, order, kern, stage), ms * 1e-3)
+        e["flops"] = "essential (top form) flops per face"
+    hw = measured_fp64_flops(symbol, workload)
+    if hw is not None:
+        e["fp64_executed_tflops"] = round(hw / (ms * 1e-3) / 1e12, 3)
+        e["fp64_executed_frac"] = round(hw / (ms * 1e-3) / 1e12 / R.PEAK_FP64_TFLOPS, 4)
+    e["kernel"] = symbol
+    return e
+
+
+def host_cpu():
+    """(logical CPUs, CPU model string) of this host"""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(n_sample=2048, max_threads=16):
+    """The oracle (plain C, FP64, single-threaded calls, unchanged) on a bounded sample
+    of the workload, on the host's cores: one thread per core (at most max_threads,
+    the host share of one GPU) each runs the first SSP-RK3 step of its own copy of
+    the seeded quadrant problem at full size; the oracle's calls release the Python
+    interpreter lock, so the threads run in parallel.  value = threads x cells / wall."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     from paper_2108_12742_amd import workloads as W
+    nproc, model = host_cpu()
+    threads = max(1, min(max_threads, nproc))
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n_sample)
     p = O.Problem(O.EULER2D, nx=n_sample, ny=n_sample, order=5)
-    u = inst.u0
+
+    def one(_):
+        t0 = time.perf_counter()
+        O.step(p, inst.u0, O.cfl_dt(p, inst.u0, 0.3))
+        return time.perf_counter() - t0
+
     t0 = time.perf_counter()
-    for _ in range(steps):
-        dt = O.cfl_dt(p, u, 0.3)
-        u = O.step(p, u, dt)
+    with ThreadPoolExecutor(threads) as ex:
+        per = list(ex.map(one, range(threads)))
     el = time.perf_counter() - t0
-    return {"value": n_sample * n_sample * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of the 2D Euler quadrant workload (seed {W.QUADRANT_BENCH_SEED}) at {n_sample}x{n_sample}, "
-                      f"{el:.1f} s on one host core"}
+    cells = n_sample * n_sample
+    return {"value": threads * cells / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} concurrent copies of the first SSP-RK3 step of the 2D Euler quadrant workload "
+                      f"(seed {W.QUADRANT_BENCH_SEED}) at {n_sample}x{n_sample}, one per thread, {el:.1f} s wall",
+            "per_thread_value": cells / (sum(per) / len(per)), "nproc": nproc, "cpu_model": model}
+
+
+def kernel_table(R, prof, cells, order, y_strip_columns, workload, equation="euler2d"):
+    """Per kernel kind: mean duration, launches, symbol and roofline; and the kind with
+    the largest total time (the dominant kernel)."""
+    kernels, best = {}, None
+    for kind, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        entry = {"mean_ms": round(ms, 4), "launches": cnt}
+        if kind.startswith("sweep"):
+            stage = int(kind[-1])
+            entry["symbol"] = kernel_symbol(kind, order, y_strip_columns)
+            entry["roofline"] = kernel_roofline(R, equation, kind, stage, cells, ms, entry["symbol"], workload, order)
+            if best is None or ms * cnt > best[1]:
+                best = (kind, ms * cnt)
+        kernels[kind] = entry
+    return kernels, best[0]
+
+
+def step_roofline(R, equation, value, kernels, cells, steps, workload):
+    """Whole-step rooflines: algorithmic bytes per cell-update x cell-updates/s against
+    HBM; the executed FP64 flops of the sweeps (committed counters) per step time
+    against the FP64 peak; measured traffic per cell-update against the algorithmic
+    bytes."""
+    bpc = R.cell_update_bytes(equation)
+    gbs = bpc * value / 1e9
+    out = {"bytes_per_cell_update": bpc, "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / R.PEAK_HBM_GBS, 4)}
+    sweeps = [e for k, e in kernels.items() if k.startswith("sweep")]
+    hw = [measured_fp64_flops(e["symbol"], workload) for e in sweeps]
+    tr = [measured_traffic(e["symbol"], workload) for e in sweeps]
+    if sweeps and all(v is not None for v in hw):
+        fl = sum(v * e["launches"] for v, e in zip(hw, sweeps)) / steps  # per step
+        out["fp64_flops_per_cell_update"] = round(fl / cells, 1)
+        tf = fl / cells * value / 1e12
+        out["fp64_executed_tflops"] = round(tf, 3)
+        out["frac_fp64"] = round(tf / R.PEAK_FP64_TFLOPS, 4)
+    if sweeps and all(v is not None for v in tr):
+        b = sum(v * e["launches"] for v, e in zip(tr, sweeps)) / steps / cells
+        out["traffic_bytes_per_cell_update"] = round(b, 1)
+        out["traffic_ratio"] = round(b / bpc, 3)
+    return out
+
+
+def bench_c0(solves=20, seed=0):
+    """The smooth advection workload (N = 200, periodic, fifth order, CFL 0.5, t = 2:
+    400 steps) as one plain solve: latency per whole solve (enoao_solve, state resident
+    on the device; the call runs its steps in one LDS-resident launch and synchronises
+    at its end), median and best of `solves` after a warm-up."""
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import workloads as W
+    inst = W.advection(seed, 200)
+    plan = E.enoao_plan_create(E.problem_from_instance(inst))
+    u0 = torch.from_numpy(inst.u0).cuda()
+    u = u0.clone()
+    E.enoao_solve(plan, u, 2.0, cfl=0.5)  # warm-up
+    lat = []
+    for _ in range(solves):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, n = E.enoao_solve(plan, u, 2.0, cfl=0.5)
+        lat.append(time.perf_counter() - t0)
+        assert (t, n) == (2.0, 400)
+    lat = np.array(lat)
+    err = float(np.abs(u.cpu().numpy() - inst.u0).max())
+    return {"workload": "advection-200-ao5-cfl0.5-t2", "steps": 400, "solves": solves,
+            "latency_ms_p50": float(np.median(lat) * 1e3), "latency_ms_min": float(lat.min() * 1e3),
+            "us_per_step_p50": float(np.median(lat) * 1e6 / 400),
+            "cell_updates_per_s": 200 * 400 / float(np.median(lat)), "max_error_after_one_period": err}
+
+
+def bench_c1(seeds=(0, 1, 2, 3), repeats=3):
+    """The 1D Euler workload: N = 2000, seeded Riemann data with the density
+    perturbation, transmissive ends, CFL 0.3, to t = 0.2, one plain solve per seed
+    (device-side CFL loop over captured graphs of 64 steps; N = 2000 is above the
+    LDS-resident solver's limit, so the streaming kernels run); best of `repeats`."""
+    import torch
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import workloads as W
+    runs = []
+    for seed in seeds:
+        inst = W.riemann_1d(seed, 2000)
+        plan = E.enoao_plan_create(E.problem_from_instance(inst))
+        u0 = torch.from_numpy(inst.u0).cuda()
+        u = u0.clone()
+        E.enoao_solve(plan, u, 0.2, cfl=0.3)  # warm-up (graph capture)
+        best = None
+        for _ in range(repeats):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t, n = E.enoao_solve(plan, u, 0.2, cfl=0.3)
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        runs.append({"seed": seed, "steps": n, "t_final": t, "seconds": best, "us_per_step": best * 1e6 / n,
+                     "cell_updates_per_s": 2000 * n / best})
+    tot = sum(r["steps"] for r in runs) * 2000
+    return {"workload": "euler1d-riemann-2000-ao5-cfl0.3-t0.2", "runs": runs,
+            "cell_updates_per_s": tot / sum(r["seconds"] for r in runs)}
 
 
 def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
@@ -169,22 +326,25 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
     workload = f"euler1d-riemann-batch{count}-{cells}cells-ao5"
     ms, kind = max(((prof[k][0], k) for k in ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3")), key=lambda x: x[0])
     stage = int(kind[-1])
-    roof = R.roofline_entry(cells * R.sweep_flops("euler1d", 5, "x", stage), cells * R.sweep_bytes("euler1d", "x", stage),
-                            ms * 1e-3)
-    roof["kernel"] = f"enoao::sweep_x<1, 5, {stage}, false>"
-    roof["traffic"] = measured_traffic(roof["kernel"], workload)
+    roof = kernel_roofline(R, "euler1d", kind, stage, cells, ms, f"enoao::sweep_x<1, 5, {stage}, false, true>",
+                           workload, 5)
+    value = cells * steps / el
     out = {"workload": workload, "members": count, "cells": cells, "steps": steps,
-           "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+           "value": value, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
            "instrumented_ms_per_step": round(el_inst * 1e3 / steps, 4),
            "members_ok": int((status == 0).sum()), "workgroups_per_cu": best,
-           "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()}, "roofline": roof}
+           "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()}, "roofline": roof,
+           "step_roofline_hbm": round(R.cell_update_bytes("euler1d") * value / 1e9 / R.PEAK_HBM_GBS, 4)}
     if not plain:
         return out
-    # plain: one plan per instance, solved one after another on the same stream
+    # plain: one plan per instance, each solve a call of its own (a solve synchronises
+    # its stream at the end), one after another on one stream, and spread over 8
+    # streams driven by 8 host threads so that solves overlap on the device
+    from concurrent.futures import ThreadPoolExecutor
     plans = [E.enoao_plan_create(p) for p in probs]
     plain = [u.clone() for u in u0]
     for pl, u, v in zip(plans, plain, u0):  # graph capture and first touch, untimed
-        E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=warmup)
+        E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=steps)
         u.copy_(v)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -193,7 +353,24 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
     torch.cuda.synchronize()
     el_plain = time.perf_counter() - t0
     identical = all(torch.equal(a, b) for a, b in zip(states, plain))
+    nstreams = 8
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    for u, v in zip(plain, u0):
+        u.copy_(v)
+    torch.cuda.synchronize()
+
+    def lane(k):
+        for i in range(k, len(plans), nstreams):
+            E.enoao_solve(plans[i], plain[i], 1e300, cfl=0.3, max_steps=steps, stream=streams[k])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nstreams) as ex:
+        list(ex.map(lane, range(nstreams)))
+    torch.cuda.synchronize()
+    el_plain8 = time.perf_counter() - t0
+    identical = identical and all(torch.equal(a, b) for a, b in zip(states, plain))
     out.update({"plain_value": cells * steps / el_plain, "speedup_vs_plain": el_plain / el,
+                "plain_8streams_value": cells * steps / el_plain8, "speedup_vs_plain_8streams": el_plain8 / el,
                 "identical_to_plain": identical})
     return out
 
@@ -245,9 +422,9 @@ def bench_resident(steps=100, count=512, n_hi=1700):
                 E.enoao_batch_profile(b, False)
                 ms, n = prof["resident"]
                 entry["kernel_ms"] = round(ms, 4)
-                roof = R.roofline_entry(cells * steps * R.cell_update_flops("euler1d", 5),
-                                        cells * steps * R.resident_bytes("euler1d", steps), ms * 1e-3)
-                roof["kernel"] = "enoao::resident_1d<1, 5>"
+                roof = R.alu_entry(cells * steps * R.cell_update_flops("euler1d", 5), ms * 1e-3)
+                roof["flops"] = "essential (top form) flops per cell-update"
+                roof["kernel"] = "enoao::resident_1d<1, 5, true>"
                 entry["roofline"] = roof
                 us = final
         finally:
@@ -273,21 +450,12 @@ def bench_order7(n=2048, steps=30, warmup=2):
     u = u0.clone()
     el, el_inst, prof = timed_solve(E, plan, u, u0, steps, warmup)
     cells = n * n
-    kernels = {}
-    for kind, (ms, cnt) in prof.items():
-        if cnt == 0:
-            continue
-        entry = {"mean_ms": round(ms, 4), "launches": cnt}
-        if kind.startswith("sweep"):
-            kern, stage = kind[6], int(kind[-1])
-            entry["symbol"] = kernel_symbol(kind, 7, DEFAULT_STRIP_COLUMNS[7])
-            entry["roofline"] = R.roofline_entry(cells * R.sweep_flops("euler2d", 7, kern, stage),
-                                                 cells * R.sweep_bytes("euler2d", kern, stage), ms * 1e-3)
-            entry["roofline"]["traffic"] = measured_traffic(entry["symbol"], workload)
-        kernels[kind] = entry
-    return {"workload": workload, "steps": steps, "value": cells * steps / el,
+    kernels, best = kernel_table(R, prof, cells, 7, DEFAULT_STRIP_COLUMNS[7], workload)
+    value = cells * steps / el
+    return {"workload": workload, "steps": steps, "value": value,
             "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
-            "instrumented_ms_per_step": round(el_inst * 1e3 / steps, 4), "kernels": kernels}
+            "instrumented_ms_per_step": round(el_inst * 1e3 / steps, 4), "roofline": kernels[best]["roofline"],
+            "step_roofline": step_roofline(R, "euler2d", value, kernels, cells, steps, workload), "kernels": kernels}
 
 
 def bench_discontinuous(order=5):
@@ -298,7 +466,7 @@ def bench_discontinuous(order=5):
     import torch
     from paper_2108_12742_amd import enoao as E
     from paper_2108_12742_amd import workloads as W
-    from tests import riemann_exact as RX
+    from paper_2108_12742_amd import exact_riemann as RX
     out = {}
     for name, inst, tf in (("combination_wave", W.combination_wave(400), 20.0), ("lax_tube", W.lax_tube(200), 0.26)):
         entry = {"n": inst.nx, "order": order}
@@ -330,21 +498,28 @@ def bench_discontinuous(order=5):
 
 def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), arena_gib=4.0):
     """Served workload: Poisson arrivals of 2D Euler quadrant solves, N x N with
-    N ~ U{128..1024}, `nsteps` steps each, admitted into a device pool by arena
-    footprint; p50/p99 latency per arrival rate (fractions of the saturated rate)."""
+    N ~ U{128..1024}, each request its own seeded draw of the quadrant generator,
+    `nsteps` CFL steps each, admitted into a device pool by arena footprint (requests
+    queue when the arena is full); rounds of several steps end when the active
+    request closest to its end finishes.  Saturated throughput (all requests submitted
+    at once) against the plain per-solve path (each request alone: plan, upload,
+    solve, download, one after another), and p50/p99 latency per arrival rate
+    (fractions of the saturated rate).  Host arrays in and out, so PCIe is included.
+    A draw that the scheme drives to a non-physical state stops there (in the pool and
+    alone alike: the request reports the failure); the work counted is the steps each
+    request actually took."""
     import torch
     from paper_2108_12742_amd import enoao as E
     from paper_2108_12742_amd import serve as S
     from paper_2108_12742_amd import workloads as W
-    t_arr, sizes, _ = W.arrivals(1, requests, 1.0)
-    # every request is the four-quadrant problem of the main workload at its own size
-    data = [W.quadrants(W.QUADRANT_BENCH_SEED, int(n)) for n in sizes]
+    t_arr, sizes, seeds = W.arrivals(1, requests, 1.0)
+    data = [W.quadrants(int(sd), int(n)) for sd, n in zip(seeds, sizes)]
     probs = [E.problem_from_instance(d) for d in data]
     like = probs[0]
     arena = int(arena_gib * (1 << 30))
 
     def server():
-        return S.Server(S.GpuPoolBackend(like, max_members=256, arena_bytes=arena), steps_per_round=1)
+        return S.Server(S.GpuPoolBackend(like, max_members=256, arena_bytes=arena))
 
     # saturated: every request submitted at once
     srv = server()
@@ -354,19 +529,44 @@ def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
         srv.submit(p, d.u0, nsteps)
     done = srv.drain()
     sat_s = time.perf_counter() - t0
-    sat_rate = requests / sat_s
-    total_cu = sum(int(p.nx) * int(p.ny) for p in probs) * nsteps
+    by_id = {r.rid: r for r in done}
+    taken = [by_id[i].steps_done for i in range(requests)]
+    work = sum(int(p.nx) * int(p.ny) * k for p, k in zip(probs, taken))
+    failed = [i for i in range(requests) if by_id[i].status != 0]
+    # plain: each request alone, one after another (plan creation included, as a
+    # per-request caller of the plain path would do it)
+    plain_res = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (p, d) in enumerate(zip(probs, data)):
+        plan = E.enoao_plan_create(p)
+        u = torch.from_numpy(d.u0).cuda()
+        try:
+            E.enoao_solve(plan, u, 1e300, cfl=0.3, max_steps=nsteps)
+            plain_res[i] = u.cpu().numpy()
+        except E.EnoaoError:
+            plain_res[i] = None
+        del plan
+    plain_s = time.perf_counter() - t0
+    same = all((by_id[i].status != 0) == (plain_res[i] is None) and
+               (plain_res[i] is None or np.array_equal(by_id[i].result, plain_res[i])) for i in range(requests))
     out = {"workload": f"euler2d-served-{requests}req-{nsteps}steps-N128..1024-ao5", "requests": requests,
-           "saturated": {"requests_per_s": sat_rate, "cell_updates_per_s": total_cu / sat_s,
-                         "failed": sum(r.status != 0 for r in done)}, "rates": []}
+           "request_data": "quadrant draws, one seed per request",
+           "saturated": {"requests_per_s": requests / sat_s, "cell_updates_per_s": work / sat_s,
+                         "failed_nonphysical": len(failed), "rounds": srv.rounds,
+                         "plain_cell_updates_per_s": work / plain_s, "speedup_vs_plain": plain_s / sat_s,
+                         "identical_to_plain": same},
+           "rates": []}
+    sat_rate = requests / sat_s
     for f in rates:
         rate = f * sat_rate
         arr = t_arr / t_arr[-1] * (requests - 1) / rate if requests > 1 else t_arr
         srv = server()
         reqs, wall = S.run_arrivals(srv, arr, lambda i: (probs[i], data[i].u0, nsteps))
         st = S.latency_stats(reqs)
-        st.update({"rate_fraction": f, "requests_per_s": rate, "cell_updates_per_s": total_cu / wall,
-                   "failed": sum(r.status != 0 for r in reqs)})
+        st.update({"rate_fraction": f, "requests_per_s": rate,
+                   "cell_updates_per_s": sum(int(r.problem.nx) * int(r.problem.ny) * r.steps_done for r in reqs) / wall,
+                   "failed": sum(r.status != 0 for r in reqs), "rounds": srv.rounds})
         out["rates"].append(st)
     return out
 
@@ -437,26 +637,10 @@ def main():
 
     cells = n * n
     value = cells * K / el
-    kernels = {}
-    best = None
-    for kind, (ms, cnt) in prof.items():
-        if cnt == 0:
-            continue
-        entry = {"mean_ms": round(ms, 4), "launches": cnt}
-        if kind.startswith("sweep"):
-            kern = kind[6]
-            stage = int(kind[-1])
-            fl = cells * R.sweep_flops("euler2d", args.order, kern, stage)
-            by = cells * R.sweep_bytes("euler2d", kern, stage)
-            entry["roofline"] = R.roofline_entry(fl, by, ms * 1e-3)
-            entry["symbol"] = kernel_symbol(kind, args.order, launch[1])
-            if best is None or ms * cnt > best[1]:
-                best = (kind, ms * cnt)
-        kernels[kind] = entry
-    roof = dict(kernels[best[0]]["roofline"])
-    roof["kernel"] = kernels[best[0]]["symbol"]
     workload = f"euler2d-quadrants-{n}x{n}-ao{args.order}"
-    roof["traffic"] = measured_traffic(roof["kernel"], workload)
+    kernels, best = kernel_table(R, prof, cells, args.order, launch[1], workload)
+    roof = dict(kernels[best]["roofline"])
+    roof["step"] = step_roofline(R, "euler2d", value, kernels, cells, K, workload)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": Wu,
         "ms_per_step": el * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -470,7 +654,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
         "kernels": kernels,
-        "flops_per_cell_update": R.cell_update_flops("euler2d", args.order),
+        "essential_flops_per_cell_update": R.cell_update_flops("euler2d", args.order),
     }
     # stencil choices on the state the timed steps reached (the metric depends on them:
     # waves whose faces all take the top candidate skip the rest of the selection)
@@ -489,7 +673,12 @@ def main():
         print("[bench] oracle baseline on the host ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     if not args.no_extras:
-        print(f"[bench] main workload: {value:.4g} cell-updates/s; batched leg ...", file=sys.stderr, flush=True)
+        print(f"[bench] main workload: {value:.4g} cell-updates/s; smooth advection latency ...", file=sys.stderr,
+              flush=True)
+        out["advection_c0"] = bench_c0()
+        print("[bench] 1D Euler N = 2000 to t = 0.2 ...", file=sys.stderr, flush=True)
+        out["euler1d_c1"] = bench_c1()
+        print("[bench] batched leg ...", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
         print("[bench] batched leg done; LDS-resident small members ...", file=sys.stderr, flush=True)
         out["batched_small"] = bench_resident()

@@ -106,9 +106,12 @@ struct Runtime {
     unsigned long long *d_amax = nullptr;
     int *d_res_order = nullptr;  // LDS-resident launches: members by decreasing size
     Ctrl *h_ctrl = nullptr;    // pinned mirror
-    // captured step graph (K steps of control + stages)
-    hipGraphExec_t graph = nullptr;
-    int graph_k = 0;
+    // captured step graphs (k steps of control + stages), one per step count k
+    // used so far (a pool's server varies k from round to round)
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
+    // one event per stream the object's work was enqueued on: destroy waits for
+    // them instead of the whole device
+    std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
     hipStream_t cap = nullptr;
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
     int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
@@ -329,16 +332,36 @@ struct Runtime {
         grid_m = grid_for(xt, occupancy_maxima(eq));
     }
 
-    // new launch shape: grids recomputed, the captured graph dropped
+    void drop_graphs()
+    {
+        for (auto &g : graphs) hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
+
+    // new launch shape: grids recomputed, the captured graphs dropped
     void set_launch(int wg)
     {
         wg_per_cu = wg;
         set_grids();
-        if (graph) {
-            hipGraphExecDestroy(graph);
-            graph = nullptr;
-            graph_k = 0;
-        }
+        drop_graphs();
+    }
+
+    // the object's work enqueued on s so far ends before this stream's mark
+    hipError_t mark(hipStream_t s)
+    {
+        for (auto &m : marks)
+            if (m.first == s) return hipEventRecord(m.second, s);
+        hipEvent_t e;
+        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (err != hipSuccess) return err;
+        marks.push_back({s, e});
+        return hipEventRecord(e, s);
+    }
+
+    // waits for the object's work on every stream it used
+    void wait_marks()
+    {
+        for (auto &m : marks) (void)hipEventSynchronize(m.second);
     }
 
     // new y tile width: the members' y tile lists rebuilt and uploaded, grids
@@ -366,13 +389,16 @@ struct Runtime {
 
     void release()
     {
+        wait_marks();
+        if (cap) (void)hipStreamSynchronize(cap);
+        for (auto &m : marks) hipEventDestroy(m.second);
+        marks.clear();
         for (auto e : ev_pool) hipEventDestroy(e);
         ev_pool.clear();
-        if (graph) hipGraphExecDestroy(graph);
+        drop_graphs();
         if (cap) hipStreamDestroy(cap);
         if (h_ctrl) hipHostFree(h_ctrl);
         if (d_block) hipFree(d_block);
-        graph = nullptr;
         cap = nullptr;
         h_ctrl = nullptr;
         d_block = nullptr;
@@ -447,13 +473,21 @@ struct Runtime {
         return ENOAO_OK;
     }
 
-    // graph of k controlled steps, captured once and replayed
+    // graph of k controlled steps, captured once per k and replayed
+    hipGraphExec_t graph_for(int k) const
+    {
+        for (auto &g : graphs)
+            if (g.first == k) return g.second;
+        return nullptr;
+    }
+
     enoao_status ensure_graph(int k)
     {
-        if (graph && graph_k == k) return ENOAO_OK;
-        if (graph) {
-            hipGraphExecDestroy(graph);
-            graph = nullptr;
+        if (graph_for(k)) return ENOAO_OK;
+        // a bounded cache: the oldest graph goes when a ninth step count comes
+        if (graphs.size() >= 8) {
+            hipGraphExecDestroy(graphs.front().second);
+            graphs.erase(graphs.begin());
         }
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -464,13 +498,11 @@ struct Runtime {
             return e;
         }
         if (ce != hipSuccess) return ENOAO_EDEVICE;
-        const hipError_t ie = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
-        if (ie != hipSuccess) {
-            graph = nullptr;
-            return ENOAO_EDEVICE;
-        }
-        graph_k = k;
+        if (ie != hipSuccess) return ENOAO_EDEVICE;
+        graphs.push_back({k, exec});
         return ENOAO_OK;
     }
 
@@ -487,7 +519,7 @@ struct Runtime {
     {
         if (profiling || use_resident()) return steps(k, true, s);  // (resident: one launch already)
         if (enoao_status e = ensure_graph(k)) return e;
-        HIP_TRY(hipGraphLaunch(graph, s));
+        HIP_TRY(hipGraphLaunch(graph_for(k), s));
         return ENOAO_OK;
     }
 };
@@ -742,8 +774,7 @@ enoao_status enoao_plan_create(const enoao_problem *prob, void *stream, enoao_pl
 enoao_status enoao_plan_destroy(enoao_plan *plan)
 {
     if (!plan) return ENOAO_EINVAL;
-    hipDeviceSynchronize();
-    plan->rt.release();
+    plan->rt.release();  // waits for the plan's work on the streams it was given
     delete plan;
     return ENOAO_OK;
 }
@@ -758,7 +789,9 @@ enoao_status enoao_rhs(enoao_plan *plan, const double *u, double *L, void *strea
     if (enoao_status e = rt.reset_and_maxima(s)) return e;
     if (enoao_status e = rt.rhs(s)) return e;
     // restore the workspace Lx pointer for later steps
-    if (rt.eq == EULER2D) return rt.set_pointers(0, u, plan->ws_lx, s);
+    if (rt.eq == EULER2D)
+        if (enoao_status e = rt.set_pointers(0, u, plan->ws_lx, s)) return e;
+    HIP_TRY(rt.mark(s));
     return ENOAO_OK;
 }
 
@@ -770,7 +803,9 @@ enoao_status enoao_step(enoao_plan *plan, double *u, double dt, void *stream)
     if (enoao_status e = rt.set_pointers(0, u, plan->ws_lx, s)) return e;
     if (enoao_status e = rt.reset_and_maxima(s)) return e;
     HIP_TRY(launch_set_dt(rt.params(0, -1, -1), 1, dt, s));
-    return rt.steps(1, false, s);
+    if (enoao_status e = rt.steps(1, false, s)) return e;
+    HIP_TRY(rt.mark(s));
+    return ENOAO_OK;
 }
 
 enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl, double dt_fixed,
@@ -822,6 +857,7 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
         if (h.status) { st = ENOAO_ENONPHYSICAL; break; }
         if (h.done || !(h.t < t_final)) break;
     }
+    HIP_TRY(rt.mark(s));
     const Ctrl &h = rt.h_ctrl[0];
     if (t_out) *t_out = h.t;
     if (steps_out) *steps_out = h.steps;
@@ -988,8 +1024,7 @@ enoao_status enoao_batch_create(const enoao_problem *probs, int32_t n, void *str
 enoao_status enoao_batch_destroy(enoao_batch *batch)
 {
     if (!batch) return ENOAO_EINVAL;
-    hipDeviceSynchronize();
-    batch->rt.release();
+    batch->rt.release();  // waits for the batch's work on the streams it was given
     delete batch;
     return ENOAO_OK;
 }
@@ -1044,15 +1079,17 @@ enoao_status enoao_batch_step(enoao_batch *batch, double *const *u, int32_t nste
         // the caller may have changed the states since the last call
         if (enoao_status e = rt.reset_and_maxima(s)) return e;
     }
-    if (nsteps == 0) return ENOAO_OK;
-    const int k = std::min(nsteps, 128);
-    for (int done = 0; done < nsteps; done += k) {
-        if (nsteps - done < k) {
-            if (enoao_status e = rt.steps(nsteps - done, true, s)) return e;
-            break;
+    if (nsteps > 0) {
+        const int k = std::min(nsteps, 128);
+        for (int done = 0; done < nsteps; done += k) {
+            if (nsteps - done < k) {
+                if (enoao_status e = rt.steps(nsteps - done, true, s)) return e;
+                break;
+            }
+            if (enoao_status e = rt.run_steps(k, s)) return e;
         }
-        if (enoao_status e = rt.run_steps(k, s)) return e;
     }
+    HIP_TRY(rt.mark(s));
     return ENOAO_OK;
 }
 
@@ -1161,7 +1198,7 @@ enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, s
 enoao_status enoao_pool_destroy(enoao_pool *pool)
 {
     if (!pool) return ENOAO_EINVAL;
-    hipDeviceSynchronize();
+    pool->rt.wait_marks();  // the pool's work on the streams it was given
     if (pool->h_stage) hipHostFree(pool->h_stage);
     pool->rt.release();
     delete pool;
@@ -1208,6 +1245,7 @@ enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const
         pool->arena_free(off, bytes);
         return ENOAO_EDEVICE;
     }
+    HIP_TRY(r.mark(s));
     pool->slots[slot].used = true;
     pool->slots[slot].prob = *prob;
     pool->slots[slot].off = off;
@@ -1229,8 +1267,10 @@ enoao_status enoao_pool_step(enoao_pool *pool, int32_t nsteps, void *stream)
             if (enoao_status e = r.reset_and_maxima(s)) return e;
         }
     }
-    if (r.n == 0) return ENOAO_OK;
-    return r.run_steps(nsteps, s);
+    if (r.n > 0)
+        if (enoao_status e = r.run_steps(nsteps, s)) return e;
+    HIP_TRY(r.mark(s));
+    return ENOAO_OK;
 }
 
 enoao_status enoao_pool_poll(enoao_pool *pool, int32_t *done, int32_t *status, int64_t *steps, double *t,

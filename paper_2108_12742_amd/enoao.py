@@ -361,6 +361,7 @@ class Pool:
         self.handle = handle
         self.like = like
         self.max_members = max_members
+        self.members = {}  # slot -> Problem of the admitted member (shape checks at retire)
 
     def __del__(self):
         if getattr(self, "handle", None):
@@ -407,6 +408,8 @@ def enoao_pool_admit(pool: Pool, problem: Problem, u0, t_final=1e300, max_steps=
                                     float(t_final), int(max_steps), float(cfl), ctypes.byref(slot), _stream(stream))
     if st == ENOMEM:
         return None
+    if st == OK:
+        pool.members[slot.value] = problem
     _check(st, "enoao_pool_admit")
     return slot.value
 
@@ -428,16 +431,27 @@ def enoao_pool_poll(pool: Pool, stream=None):
 
 def enoao_pool_retire(pool: Pool, slot: int, shape=None, out=None, stream=None):
     """Free a member.  With `shape` (and no `out`) its state is returned as a numpy array;
-    `out` may be a GPU tensor to receive it on the device."""
+    `out` may be a GPU tensor to receive it on the device.  The library copies the
+    member's whole state, so `out` and `shape` must match the admitted problem's
+    (ncomp, ny, nx): anything else raises ValueError before the call."""
+    prob = pool.members.get(int(slot))
+    if prob is None:
+        raise ValueError(f"slot {slot} holds no admitted member")
     if out is not None:
-        _check(lib().enoao_pool_retire(pool.handle, int(slot), _dev_ptr(out), 0, _stream(stream)), "enoao_pool_retire")
+        ptr = _dev_ptr(out, prob.shape, what="out")
+        _check(lib().enoao_pool_retire(pool.handle, int(slot), ptr, 0, _stream(stream)), "enoao_pool_retire")
+        del pool.members[int(slot)]
         return out
     if shape is not None:
-        a = np.empty(shape, np.float64)
+        if tuple(shape) != tuple(prob.shape):
+            raise ValueError(f"shape {tuple(shape)} does not match the member's {tuple(prob.shape)}")
+        a = np.empty(prob.shape, np.float64)
         _check(lib().enoao_pool_retire(pool.handle, int(slot), a.ctypes.data_as(ctypes.c_void_p), 1, _stream(stream)),
                "enoao_pool_retire")
+        del pool.members[int(slot)]
         return a
     _check(lib().enoao_pool_retire(pool.handle, int(slot), None, 1, _stream(stream)), "enoao_pool_retire")
+    del pool.members[int(slot)]
     return None
 
 

@@ -1,4 +1,6 @@
-"""Exact solution of the 1D Riemann problem for an ideal gas (test helper).
+"""Exact solution of the 1D Riemann problem for an ideal gas: a reference to measure
+the error of a computed solution against (the benchmark's Lax-tube error, the tests'
+pins of the oracle).  It is not part of the method: no kernel or oracle code uses it.
 
 Restated from the standard textbook construction (Toro, "Riemann Solvers and
 Numerical Methods for Fluid Dynamics", ch. 4): the star pressure solves

@@ -13,8 +13,14 @@ multiply-add = 2; fabs and negation free).  Two layouts of the same arithmetic:
     differences and a symmetric stencil, seven projected vectors per face.  The
     full selection that waves with a field off the top candidate add is
     data-dependent and not counted (the count is a lower bound there).
-Bytes are the compulsory HBM traffic of a launch: each input array read once,
-each output written once (halo re-reads excluded).
+Bytes: algorithmic HBM traffic of a Runge-Kutta stage, per cell: the stage
+reads its input state once (and u^n in stages 2 and 3) and writes its output
+once -- 2 x, 3 x, 3 x the state's 8 * ncomp bytes, i.e. 64/96/96 = 256 B per 2D
+cell-update, 48/72/72 = 192 B for 1D Euler.  Intermediate arrays of an
+implementation (the x-part of L that the 2D x-sweep writes and the y-sweep
+reads back, second reads of the stage input) are not algorithmic: a stage's
+bytes belong to the kernel that completes the stage (the y-sweep in 2D), and
+the 2D x-sweep carries none of its own.
 
 Peaks (MI355X, published): HBM3E 8.0 TB/s; FP64 vector 78.6 TFLOP/s
 (256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz).
@@ -97,6 +103,22 @@ def stage_cell_flops(equation: str, stage: int) -> int:
     return combine_flops(nc, stage) + MAXIMA_FLOPS[equation] + extra
 
 
+def stage_bytes(equation: str, stage: int) -> int:
+    """Algorithmic HBM bytes per cell of one stage (stage 0: one evaluation of L,
+    read u, write L)."""
+    w = 8 * {"advection": 1, "euler1d": 3, "euler2d": 4}[equation]
+    return 2 * w if stage in (0, 1) else 3 * w
+
+
+def algorithmic_bytes(equation: str, kernel: str, stage: int) -> int:
+    """The stage's algorithmic bytes attributed to one kernel of it: all of them to
+    the kernel that completes the stage (1D x-sweep, 2D y-sweep), none to the 2D
+    x-sweep."""
+    if equation == "euler2d" and kernel == "x":
+        return 0
+    return stage_bytes(equation, stage)
+
+
 def sweep_bytes(equation: str, kernel: str, stage: int) -> int:
     """Compulsory HBM bytes per cell of one launch (stage 0: evaluation of L only).
 
@@ -128,9 +150,30 @@ def cell_update_flops(equation: str, order: int) -> int:
 
 
 def cell_update_bytes(equation: str) -> int:
+    """Algorithmic HBM bytes of one cell-update (three stages): 256 B in 2D."""
+    return sum(stage_bytes(equation, s) for s in (1, 2, 3))
+
+
+def split_sweep_bytes(equation: str) -> int:
+    """Compulsory bytes per cell-update of the split 2D layout (x-part of L written and
+    read back, stage input read by both sweeps): the implementation's own minimum."""
     if equation == "euler2d":
         return sum(sweep_bytes(equation, "x", s) + sweep_bytes(equation, "y", s) for s in (1, 2, 3))
     return sum(sweep_bytes(equation, "x", s) for s in (1, 2, 3))
+
+
+def hbm_entry(nbytes: float, seconds: float, traffic=None):
+    """Roofline against HBM bandwidth (algorithmic bytes / time)."""
+    gbs = nbytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic}
+
+
+def alu_entry(flops: float, seconds: float):
+    """Roofline against the FP64 vector peak (flops / time)."""
+    tf = flops / seconds / 1e12
+    return {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP64_TFLOPS, 4)}
 
 
 def resident_bytes(equation: str, steps: int) -> float:

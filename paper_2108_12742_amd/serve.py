@@ -11,6 +11,13 @@ starts a queued request's upload while a round computes, and `retire` may hand
 back a pending result whose download overlaps later rounds; the server finishes
 a request when its result has arrived.
 
+A round is several steps of the pool when nothing would be gained by stopping
+earlier: with steps_per_round = 0 (the default) a round runs as many steps as
+the active request closest to its end still needs (at most max_round_steps), so
+that request retires, and its memory frees up for the queue, exactly when the
+round ends; every request stops at its own step count on the device either way.
+The host reads the pool's state once per round, not once per step.
+
 The scheduling is independent of the device: `Server` drives any backend with
 the `Backend` methods below.  `GpuPoolBackend` is the HIP pool of the C ABI.
 """
@@ -34,6 +41,7 @@ class Request:
     admitted: float | None = None
     finished: float | None = None
     slot: int | None = None
+    steps_done: int = 0        # steps taken, as of the last poll
     staged: object = None      # backend handle of an upload started before admission
     result: np.ndarray | None = None
     status: int = 0            # 0 ok, non-zero: non-physical state or rejected
@@ -163,7 +171,8 @@ class GpuPoolBackend(Backend):
 @dataclass
 class Server:
     backend: Backend
-    steps_per_round: int = 1
+    steps_per_round: int = 0   # 0: adaptive (the fewest steps an active request still needs)
+    max_round_steps: int = 8   # bound on an adaptive round (latency of newly arrived requests)
     clock: object = time.perf_counter
     stage_ahead: int = 4       # queued requests whose upload starts while a round computes
     queue: deque = field(default_factory=deque)
@@ -193,7 +202,7 @@ class Server:
             if slot is None:
                 break
             self.queue.popleft()
-            r.slot, r.admitted, r.staged = slot, self.clock(), None
+            r.slot, r.admitted, r.staged, r.steps_done = slot, self.clock(), None, 0
             self.active[slot] = r
             n += 1
         return n
@@ -218,6 +227,13 @@ class Server:
                 left.append((r, p))
         self.pending = left
 
+    def round_steps(self):
+        """Steps of the next round: fixed, or the fewest an active request still needs."""
+        if self.steps_per_round > 0:
+            return self.steps_per_round
+        need = min(max(r.nsteps - r.steps_done, 1) for r in self.active.values())
+        return max(1, min(need, self.max_round_steps))
+
     def round(self):
         """Admit, advance every admitted request, retire the finished ones.  While the
         round computes, the next queued requests are staged and arrived results are
@@ -226,12 +242,14 @@ class Server:
         if not self.active:
             self.collect(wait=not self.queue)
             return 0
-        self.backend.step(self.steps_per_round)
+        self.backend.step(self.round_steps())
         self.rounds += 1
         self._stage()
         self.collect()
         done, status, steps = self.backend.poll()
         finished = 0
+        for slot, r in self.active.items():
+            r.steps_done = int(steps[slot])
         for slot in list(self.active):
             if done[slot] == 1 or status[slot] != 0:
                 r = self.active.pop(slot)

@@ -15,7 +15,24 @@ def test_more_than_one_gpu_refused():
 
 
 def test_cpu_baseline_leg():
+    """The oracle on all host cores (at most 16 threads, one copy of the sample each);
+    the host's CPU count and model are stated."""
     sys.path.insert(0, ROOT)
     import bench
-    b = bench.cpu_baseline(n_sample=64, steps=1)
-    assert b["kind"] == "oracle" and b["cores"] == 1 and b["value"] > 0 and "64x64" in b["sample"]
+    b = bench.cpu_baseline(n_sample=64, max_threads=3)
+    assert b["kind"] == "oracle" and b["cores"] == min(3, os.cpu_count()) and b["value"] > 0
+    assert "64x64" in b["sample"] and b["nproc"] == os.cpu_count() and b["cpu_model"]
+    assert b["per_thread_value"] > 0
+
+
+def test_algorithmic_bytes():
+    """Section 2's stage structure: a stage reads its input (and u^n in stages 2, 3) and
+    writes its output once: 64/96/96 B per 2D cell, 256 per cell-update; the 2D x-sweep
+    carries none of them."""
+    from paper_2108_12742_amd import roofline as R
+    assert [R.stage_bytes("euler2d", s) for s in (1, 2, 3)] == [64, 96, 96]
+    assert R.cell_update_bytes("euler2d") == 256 and R.cell_update_bytes("euler1d") == 192
+    assert R.algorithmic_bytes("euler2d", "x", 2) == 0 and R.algorithmic_bytes("euler2d", "y", 2) == 96
+    assert R.algorithmic_bytes("euler1d", "x", 1) == 48
+    e = R.hbm_entry(96 * 4194304, 140.6e-6)
+    assert e["bound"] == "hbm" and abs(e["frac"] - 0.358) < 1e-3

@@ -251,3 +251,83 @@ def test_pool_1d_order7_members():
         u = PT.to_dev(torch, inst.u0)
         E.enoao_solve(plan, u, 1e300, cfl=0.3, max_steps=nsteps[k])
         np.testing.assert_array_equal(results[k], u.cpu().numpy())
+
+
+def _poisoned(inst, k=40):
+    """the instance with a negative pressure at one node (E below the kinetic energy)"""
+    u0 = inst.u0.copy()
+    nc = u0.shape[0]
+    flat = u0.reshape(nc, -1)
+    j = min(k, flat.shape[1] - 1)
+    kin = 0.5 * sum(flat[c, j] ** 2 for c in range(1, nc - 1)) / flat[0, j]
+    flat[nc - 1, j] = 0.5 * kin
+    return u0
+
+
+def test_failure_isolation():
+    """One member with a non-physical state (p < 0 at one node) in a batch, a pool and the
+    server: only that member or request reports the non-physical status; every other
+    member equals its solve alone bitwise."""
+    torch = PT.torch_cuda()
+    E = _E()
+    from paper_2108_12742_amd import serve as S
+    insts = [W.riemann_1d(300 + k, n) for k, n in enumerate([300, 1200, 77, 1600])]
+    bad = 1
+    u0s = [i.u0 if k != bad else _poisoned(i) for k, i in enumerate(insts)]
+    probs = [E.problem_from_instance(i) for i in insts]
+    alone = [_alone(torch, E, i, 8)[0] for i in insts]
+    # batch (streaming kernels and, for members that fit, the LDS-resident solver)
+    for resident in (True, False):
+        E.enoao_set_resident(resident)
+        try:
+            batch = E.enoao_batch_create(probs)
+            us = [PT.to_dev(torch, u) for u in u0s]
+            E.enoao_batch_step(batch, us, 8, 0.3)
+            t, steps, status = E.enoao_batch_query(batch)
+        finally:
+            E.enoao_set_resident(True)
+        assert status[bad] != 0 and all(status[k] == 0 for k in range(4) if k != bad)
+        for k in range(4):
+            if k != bad:
+                assert steps[k] == 8 and np.array_equal(us[k].cpu().numpy(), alone[k]), (resident, k)
+    # pool
+    pool = E.enoao_pool_create(probs[0], 8, 64 << 20)
+    slots = [E.enoao_pool_admit(pool, p, u, max_steps=8) for p, u in zip(probs, u0s)]
+    for _ in range(10):
+        E.enoao_pool_step(pool, 1)
+    done, status, steps, _ = E.enoao_pool_poll(pool)
+    for k, s in enumerate(slots):
+        res = E.enoao_pool_retire(pool, s, shape=insts[k].u0.shape)
+        if k == bad:
+            assert status[s] != 0
+        else:
+            assert status[s] == 0 and steps[s] == 8 and np.array_equal(res, alone[k])
+    # server on a 2D pool: the poisoned request fails, the others are served
+    q = [W.quadrants(1, 70, 60), W.quadrants(3, 96, 96), W.quadrants(5, 40, 33)]
+    qp = [E.problem_from_instance(d) for d in q]
+    srv = S.Server(S.GpuPoolBackend(qp[0], max_members=4, arena_bytes=64 << 20))
+    reqs = [srv.submit(p, d.u0 if k != 1 else _poisoned(d), 6) for k, (p, d) in enumerate(zip(qp, q))]
+    srv.drain()
+    assert reqs[1].status != 0 and reqs[1].error
+    for k in (0, 2):
+        assert reqs[k].status == 0
+        np.testing.assert_array_equal(reqs[k].result, _alone(torch, E, q[k], 6)[0])
+
+
+def test_pool_retire_checks_the_member_shape():
+    """The binding refuses an output whose shape is not the admitted member's (the
+    library copies the whole state)."""
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = W.riemann_1d(7, 200)
+    p = E.problem_from_instance(inst)
+    pool = E.enoao_pool_create(p, 2, 16 << 20)
+    s = E.enoao_pool_admit(pool, p, inst.u0, max_steps=1)
+    with pytest.raises(ValueError):
+        E.enoao_pool_retire(pool, s, shape=(3, 1, 100))
+    with pytest.raises(ValueError):
+        E.enoao_pool_retire(pool, s, out=torch.empty((3, 1, 100), dtype=torch.float64, device="cuda"))
+    out = E.enoao_pool_retire(pool, s, shape=(3, 1, 200))
+    np.testing.assert_array_equal(out, inst.u0)
+    with pytest.raises(ValueError):
+        E.enoao_pool_retire(pool, s, shape=(3, 1, 200))

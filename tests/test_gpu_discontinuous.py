@@ -15,7 +15,7 @@ import pytest
 from oracle import oracle as O
 from paper_2108_12742_amd import workloads as W
 from tests import parity as PT
-from tests import riemann_exact as RX
+from paper_2108_12742_amd import exact_riemann as RX
 
 pytestmark = pytest.mark.gpu
 

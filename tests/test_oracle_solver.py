@@ -11,7 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_2108_12742_amd import workloads as W
 from tests import exact_recon as X
-from tests import riemann_exact as RX
+from paper_2108_12742_amd import exact_riemann as RX
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 

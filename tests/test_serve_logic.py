@@ -175,3 +175,35 @@ def test_overlapped_transfers():
         for _ in range(r.nsteps):
             u = O.step(op, u, O.cfl_dt(op, u, 0.3))
         np.testing.assert_array_equal(r.result, u)
+
+
+def test_adaptive_rounds_stop_when_the_first_request_finishes():
+    """steps_per_round = 0: each round runs the fewest steps an active request still needs
+    (bounded by max_round_steps), so a request retires exactly at the end of a round and
+    the queue is admitted then; results equal each request's solve alone."""
+    clock = Clock()
+    reqs_in = [(_request(11, 24), 7), (_request(12, 24), 3), (_request(13, 24), 12), (_request(14, 24), 5)]
+    budget = 3 * 8 * 3 * 24 * 2  # two members at a time
+    pool = FakePool(max_members=8, arena_bytes=budget, clock=clock)
+    rounds = []
+    srv = S.Server(pool, clock=clock, max_round_steps=4)
+    orig = pool.step
+
+    def step(n):
+        rounds.append(n)
+        orig(n)
+
+    pool.step = step
+    reqs = [srv.submit(*rq, nsteps=n) for rq, n in reqs_in]
+    srv.drain()
+    assert all(r.status == 0 for r in reqs)
+    # members 7 and 3 start: 3 steps; then 7 (4 left) with 12: 4 steps; 12 (8 left) with 5:
+    # 4 (bound), 1 ... every round ends where the closest request ends or at the bound
+    assert rounds[0] == 3 and rounds[1] == 4 and max(rounds) <= 4
+    assert len(rounds) < sum(rounds)  # fewer host polls than pool steps
+    for r, ((prob, u0), n) in zip(reqs, reqs_in):
+        op = prob.oracle()
+        u = u0
+        for _ in range(n):
+            u = O.step(op, u, O.cfl_dt(op, u, 0.3))
+        np.testing.assert_array_equal(r.result, u)
