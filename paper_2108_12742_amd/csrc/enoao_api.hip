@@ -116,10 +116,17 @@ struct Runtime {
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
     int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
     int yw = 8;  // columns per wave strip of the y-sweep tiles (4 or 8); set from the order at creation
-    // every member 1D and small enough for the LDS-resident solver (res_lds
-    // dynamic LDS bytes per workgroup); controlled steps then run there
+    // every member 1D and small enough for the LDS-resident solver; controlled
+    // steps then run there, one launch per LDS size class (below)
     bool resident = false;
-    size_t res_lds = 0;
+    struct ResClass {
+        int first, count;  // members res_order[first .. first + count)
+        int block;         // threads per workgroup
+        size_t lds;        // dynamic LDS bytes per workgroup
+    };
+    std::vector<ResClass> res_classes;
+    std::vector<hipStream_t> res_streams;  // classes after the first run on these, concurrently
+    std::vector<hipEvent_t> res_events;    // fork + one join per extra class
     bool use_resident() const { return resident && g_resident != 0; }
     int kflags = g_shortcut ? 0 : KF_FULL_SELECTION;  // taken when the plan or batch is created
     // optional per-kernel timing: hipEvents recorded around every launch, on the
@@ -281,14 +288,83 @@ struct Runtime {
         wg_per_cu = g_wg_per_cu;
         set_grids();
         if (eq != EULER2D && !rec) {
-            const int nq = eq == ADVECTION ? 1 : 9, g = order == 5 ? 4 : 5;
-            size_t need = 0;
-            for (int i = 0; i < count; ++i)
-                need = std::max<size_t>(need, resident_lds_bytes(nc, nq, g, ps[i].nx));
-            res_lds = need;
-            resident = need <= resident_lds_limit();
+            if (enoao_status e = plan_resident(ps, order_h)) return e;
         }
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        return ENOAO_OK;
+    }
+
+    // LDS size classes of the resident solver.  The dynamic LDS of a launch is the
+    // same for all its workgroups, so one launch for all members would give every
+    // member the largest one's and hold the CUs at the occupancy of the largest.
+    // Members (largest first) are grouped by how many of their workgroups fit one
+    // CU's LDS (4, 3, 2 or 1); each class is one launch, and the classes run
+    // concurrently on streams of their own (forked from and joined to the
+    // caller's stream).  Workgroups of 4 waves: on the small-member batch 8-wave
+    // workgroups (one per CU) for the mid-sized members measured 13% slower.
+    enoao_status plan_resident(const enoao_problem *ps, const std::vector<int> &sorted)
+    {
+        const int nq = eq == ADVECTION ? 1 : 9, g = order == 5 ? 4 : 5;
+        const size_t limit = resident_lds_limit();
+        int per_cu = 0;
+        if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = (int)limit;
+        auto cls = [&](long long nx, int &block, size_t &lds) {
+            block = RES_BLOCK;
+            lds = resident_lds_bytes(nc, nq, g, nx, RES_BLOCK);
+            for (int k = 4; k >= 2; --k)
+                if (lds + 1024 <= (size_t)per_cu / k) return k;  // 1 KiB for each workgroup's static LDS
+            return lds <= limit ? 1 : 0;
+        };
+        res_classes.clear();
+        int prev_k = -1;
+        for (int i = 0; i < (int)sorted.size(); ++i) {
+            int block;
+            size_t lds;
+            const int k = cls(ps[sorted[i]].nx, block, lds);
+            if (k == 0) {  // a member too large for one workgroup's LDS: stream every member
+                res_classes.clear();
+                resident = false;
+                return ENOAO_OK;
+            }
+            if (k != prev_k) {
+                res_classes.push_back({i, 0, block, lds});  // the first member of a class is its largest
+                prev_k = k;
+            }
+            res_classes.back().count++;
+        }
+        resident = !res_classes.empty();
+        for (size_t c = 1; c < res_classes.size(); ++c) {
+            hipStream_t st;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            res_streams.push_back(st);
+        }
+        for (size_t c = 0; c < res_classes.size(); ++c) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            res_events.push_back(e);
+        }
+        return ENOAO_OK;
+    }
+
+    // k controlled steps of every member on the resident solver
+    enoao_status resident_steps(int k, hipStream_t s)
+    {
+        int slot;
+        HIP_TRY(prof_begin(PROF_RESIDENT, s, slot));
+        if (res_classes.size() > 1) HIP_TRY(hipEventRecord(res_events[0], s));
+        for (size_t c = 0; c < res_classes.size(); ++c) {
+            const ResClass &rc = res_classes[c];
+            hipStream_t st = c == 0 ? s : res_streams[c - 1];
+            if (c > 0) HIP_TRY(hipStreamWaitEvent(st, res_events[0], 0));
+            KParams p = params(0, -1, -1);
+            p.res_first = rc.first;
+            HIP_TRY(launch_resident(eq, order, ch, rc.block, p, rc.count, k, rc.lds, st));
+            if (c > 0) HIP_TRY(hipEventRecord(res_events[c], st));
+        }
+        for (size_t c = 1; c < res_classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(s, res_events[c], 0));
+        HIP_TRY(prof_end(slot, s));
         return ENOAO_OK;
     }
 
@@ -395,6 +471,13 @@ struct Runtime {
         marks.clear();
         for (auto e : ev_pool) hipEventDestroy(e);
         ev_pool.clear();
+        for (auto st : res_streams) {
+            (void)hipStreamSynchronize(st);
+            hipStreamDestroy(st);
+        }
+        res_streams.clear();
+        for (auto e : res_events) hipEventDestroy(e);
+        res_events.clear();
         drop_graphs();
         if (cap) hipStreamDestroy(cap);
         if (h_ctrl) hipHostFree(h_ctrl);
@@ -453,13 +536,7 @@ struct Runtime {
 
     enoao_status steps(int k, bool control, hipStream_t s)
     {
-        if (control && use_resident()) {
-            int slot;
-            HIP_TRY(prof_begin(PROF_RESIDENT, s, slot));
-            HIP_TRY(launch_resident(eq, order, ch, params(0, -1, -1), n_cap, k, res_lds, s));
-            HIP_TRY(prof_end(slot, s));
-            return ENOAO_OK;
-        }
+        if (control && use_resident()) return resident_steps(k, s);
         for (int i = 0; i < k; ++i) {
             if (control) {
                 int slot;

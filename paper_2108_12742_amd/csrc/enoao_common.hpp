@@ -72,17 +72,19 @@ struct Inst {
 };
 
 // LDS-resident solver of small 1D members: one workgroup of RES_BLOCK threads
-// holds a member's state, its stage state and its face fluxes in LDS for a
-// whole call; a stage stages node quantities for RES_BLOCK faces at a time.
-constexpr int RES_BLOCK = 512;
-constexpr int RES_WAVES = RES_BLOCK / 64;
+// holds a member's state and both Runge-Kutta stage states in LDS for a whole
+// call; each of its waves stages the nodes of one 64-face segment at a time,
+// and that segment's face fluxes, in LDS of its own.
+constexpr int RES_BLOCK = 256;
 
 // dynamic LDS bytes of a resident member of n nodes (nc components, nq staged
-// quantities per node, halo width g): u^n, stage state, face fluxes, one chunk
-// of staged nodes, the reduction scratch
-constexpr unsigned long long resident_lds_bytes(int nc, int nq, int g, long long n)
+// quantities per node, halo width g, block threads): u^n and the two stage
+// states, each wave's segment staging (nodes and face fluxes), two parities of
+// per-wave maxima
+constexpr unsigned long long resident_lds_bytes(int nc, int nq, int g, long long n, int block = RES_BLOCK)
 {
-    return 8ull * (unsigned long long)(2 * nc * n + nc * (n + 1) + nq * (RES_BLOCK + 2 * g) + RES_WAVES * 8 + 8);
+    const long long nnp = 64 + 2 * g, waves = block / 64;
+    return 8ull * (unsigned long long)(3 * nc * n + waves * (nq * nnp + nc * 64) + 2 * waves * 8);
 }
 
 // Batch header (device memory): kernels read the instance count and the tile

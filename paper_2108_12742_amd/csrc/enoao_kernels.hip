@@ -1081,15 +1081,53 @@ __global__ void step_control(KParams P)
 
 // ---------------------------------------------------------------------------
 // LDS-resident solver of small 1D members.  One workgroup per member runs
-// `nsteps` controlled steps with the state, the stage state and the face
-// fluxes in LDS: HBM is touched only to load the state and store it back.
-// Every arithmetic step is the streaming path's (same node quantities, face
-// flux, flux difference, stage combine, maxima and step control), so a member's
-// result is bitwise the one of the streaming kernels.
+// `nsteps` controlled steps with u^n and both stage states in LDS: HBM is
+// touched only to load the state and store it back.  Within a stage each wave
+// owns 64-face line segments (63 cells each, taken round-robin) and works like
+// a wave of the streaming x-sweep: it stages the segment's node quantities in
+// its own LDS, computes the 64 face fluxes (top differences formed per face, as
+// the y-sweep does: staging them costs a pass and two synchronisations more,
+// and measured 15% slower here) and updates the 63 cells, synchronising only
+// with itself.  The stages write distinct arrays
+// (u^n -> w1 -> w2 -> u^n; stage 3 reads u^n only at the cell it writes), so
+// no wave overwrites what another still reads, and one workgroup barrier per
+// stage (which also publishes the per-wave maxima) is the only one.  Every
+// arithmetic step is the streaming path's (same node quantities, staged top
+// differences, face flux, flux difference, stage combine, maxima and step
+// control), so a member's result is bitwise the one of the streaming kernels.
+// A step of a member takes a fixed latency plus its segments over the waves
+// (measured alone: 13 us at 128 nodes, 41 us at 1700), so a batch step lasts
+// about as long as its largest member's.
 
-// workgroup maximum of the per-thread maxima; the non-physical flag goes to C
-template <int EQ>
-__device__ __forceinline__ void resident_reduce(Maxima<EQ> &mx, double *red, double *cm, Ctrl &C)
+// per-wave LDS of a resident workgroup: staged nodes, face fluxes
+template <int EQ, int ORDER> struct ResWave {
+    static constexpr int NQ = NodeTraits<EQ>::NQ, NC = NodeTraits<EQ>::NC;
+    static constexpr int G = ReconTraits<ORDER>::H + 1;
+    static constexpr int NN = XW_FACES + 2 * G - 1, NNP = NN + 1;
+    static constexpr int DOUBLES = NQ * NNP + NC * XW_FACES;
+};
+
+// all threads: the maxima of the waves of stage `par` (every thread reads every
+// wave's values, so no second barrier is needed); the non-physical flag goes to C
+template <int EQ, int NW>
+__device__ __forceinline__ void resident_maxima(const double *red, int par, double (&cm)[8], Ctrl &C)
+{
+    constexpr int NV = Maxima<EQ>::NV;
+    const double *r = red + par * NW * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cm[i] = 0.0;
+    double bad = 0.0;
+    for (int w = 0; w < NW; ++w) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cm[i] = fmax(cm[i], r[w * 8 + i]);
+        bad = fmax(bad, r[w * 8 + 7]);
+    }
+    if (bad != 0.0) C.status |= 1;
+}
+
+// a wave's maxima to red[par] (lane 0 writes; published by the next barrier)
+template <int EQ, int NW>
+__device__ __forceinline__ void resident_wave_maxima(Maxima<EQ> &mx, double *red, int par)
 {
     constexpr int NV = Maxima<EQ>::NV;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1104,29 +1142,22 @@ __device__ __forceinline__ void resident_reduce(Maxima<EQ> &mx, double *red, dou
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) b |= __shfl_xor(b, o, 64);
     if (lane == 0) {
+        double *r = red + (par * NW + wv) * 8;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) red[wv * 8 + i] = mx.v[i];
-        red[wv * 8 + 7] = (double)b;
+        for (int i = 0; i < NV; ++i) r[i] = mx.v[i];
+        r[7] = (double)b;
     }
-    __syncthreads();
-    if (threadIdx.x < 8) {
-        double x = red[threadIdx.x];
-        for (int w = 1; w < RES_WAVES; ++w) x = fmax(x, red[w * 8 + threadIdx.x]);
-        if (threadIdx.x < NV) cm[threadIdx.x] = x;
-        else if (threadIdx.x < 7) cm[threadIdx.x] = 0.0;
-        else if (x != 0.0) C.status |= 1;
-    }
-    __syncthreads();
 }
 
-template <int EQ, int ORDER, int MODE, bool CH>
-__device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, int n, double *un, double *w,
-                                               double *fx, double *q, double *red, double *cm, Ctrl &C, double dt)
+template <int EQ, int ORDER, int MODE, bool CH, int NW>
+__device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, int n, const double *in,
+                                               const double *base, double *out, double *wl, double *red, int par,
+                                               double (&cm)[8], Ctrl &C, double dt)
 {
-    constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
-    constexpr int G = ReconTraits<ORDER>::H + 1;
-    constexpr int QS = RES_BLOCK + 2 * G;
-    const int tid = threadIdx.x;
+    using RW = ResWave<EQ, ORDER>;
+    constexpr int NC = RW::NC, NQ = RW::NQ, G = RW::G, NN = RW::NN, NNP = RW::NNP;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double al[NC];
     if constexpr (EQ == ADVECTION) {
         al[0] = fabs(I.adv);
@@ -1139,90 +1170,102 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
 #pragma unroll
         for (int c = 0; c < NC; ++c) al[c] = a;
     }
-    const double *in = MODE == M_S1 ? un : w;
-    for (int c0 = 0; c0 <= n; c0 += RES_BLOCK) {
-        for (int i = tid; i < RES_BLOCK + 2 * G - 1; i += RES_BLOCK) {
-            const int x = bc_map(c0 - G + i, n, I.bcx);
-            double U[NC], qq[NQ];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) U[c] = in[c * n + x];
-            node_quantities<EQ>(U, P.gm1, qq);
-#pragma unroll
-            for (int m = 0; m < NQ; ++m) q[m * QS + i] = qq[m];
-        }
-        __syncthreads();
-        const int f = c0 + tid;
-        if (f <= n) {
-            double Fh[NC];
-            int sel[2 * NC];
-            face_flux<EQ, ORDER, false, CH>(q + tid, QS, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv,
-                                        (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) fx[c * (n + 1) + f] = Fh[c];
-        }
-        __syncthreads();
-    }
+    double *q = wl, *fh = wl + NQ * NNP;
     const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
-    double *out = MODE == M_S3 ? un : w;
     Maxima<EQ> mx;
     mx.reset();
-    for (int j = tid; j < n; j += RES_BLOCK) {
-        double Un[NC];
+    const int nseg = (n + XW_CELLS - 1) / XW_CELLS;
+    for (int seg = wv; seg < nseg; seg += NW) {
+        const int sx = seg * XW_CELLS;
+        // node quantities of nodes sx - G .. sx + 63 + G - 1
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double Lc = -(fx[c * (n + 1) + j + 1] - fx[c * (n + 1) + j]) * idx;
-            Un[c] = rk_combine<MODE>(in[c * n + j], un[c * n + j], dt, Lc);
+        for (int j = 0; j < 2; ++j) {
+            const int i = lane + 64 * j;
+            if (i < NN) {
+                const int x = bc_map(sx - G + i, n, I.bcx);
+                double U[NC], qq[NQ];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) U[c] = in[c * n + x];
+                node_quantities<EQ>(U, P.gm1, qq);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) q[m * NNP + i] = qq[m];
+            }
         }
+        wave_sync();
+        double Fh[NC];
+        int sel[2 * NC];
+        face_flux<EQ, ORDER, false, CH>(q + lane, NNP, 1, nullptr, 0, 0, al, P.gm1, P.delta, I.adv,
+                                        (P.flags & KF_FULL_SELECTION) == 0, Fh, sel);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) out[c * n + j] = Un[c];
-        mx.add(Un, P.gamma, idx, idy);
+        for (int c = 0; c < NC; ++c) fh[c * XW_FACES + lane] = Fh[c];
+        wave_sync();
+        const int x = sx + lane;
+        if (lane < XW_CELLS && x < n) {
+            double Un[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double Lc = -(fh[c * XW_FACES + lane + 1] - fh[c * XW_FACES + lane]) * idx;
+                Un[c] = rk_combine<MODE>(q[c * NNP + lane + G], base[c * n + x], dt, Lc);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) out[c * n + x] = Un[c];
+            mx.add(Un, P.gamma, idx, idy);
+        }
+        wave_sync();  // the next segment overwrites the staged nodes and fluxes
     }
-    resident_reduce<EQ>(mx, red, cm, C);
+    resident_wave_maxima<EQ, NW>(mx, red, par);
+    __syncthreads();  // the stage output and every wave's maxima are complete
+    resident_maxima<EQ, NW>(red, par, cm, C);
 }
 
-template <int EQ, int ORDER, bool CH>
-__global__ __launch_bounds__(RES_BLOCK) void resident_1d(KParams P, int nsteps)
+// one launch covers members res_order[res_first .. res_first + gridDim.x) (the
+// members of one LDS size class, largest first), one workgroup of NW waves each
+template <int EQ, int ORDER, bool CH, int NW>
+__global__ __launch_bounds__(64 * NW) void resident_1d(KParams P, int nsteps)
 {
-    constexpr int NC = NodeTraits<EQ>::NC, NQ = NodeTraits<EQ>::NQ;
-    constexpr int G = ReconTraits<ORDER>::H + 1;
-    constexpr int QS = RES_BLOCK + 2 * G;
+    using RW = ResWave<EQ, ORDER>;
+    constexpr int NC = RW::NC;
     extern __shared__ double sm[];
-    __shared__ Ctrl C;
-    __shared__ int go;
-    const Inst &I = P.inst[P.res_order ? P.res_order[blockIdx.x] : (int)blockIdx.x];
+    const int slot = P.res_first + (int)blockIdx.x;
+    const Inst &I = P.inst[P.res_order ? P.res_order[slot] : slot];
     const int n = I.nx, tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     double *un = sm;
-    double *w = un + NC * n;
-    double *fx = w + NC * n;
-    double *q = fx + NC * (n + 1);
-    double *red = q + NQ * QS;
-    double *cm = red + RES_WAVES * 8;
+    double *w1 = un + NC * n;
+    double *w2 = w1 + NC * n;
+    double *wl = w2 + NC * n + wv * RW::DOUBLES;
+    double *red = w2 + NC * n + NW * RW::DOUBLES;  // two parities of NW x 8 values
     GMEM double *ug = gmem(I.u);
-    for (int i = tid; i < NC * n; i += RES_BLOCK) un[i] = ug[i];
-    if (tid == 0) C = *I.ctrl;
-    __syncthreads();
+    for (int i = tid; i < NC * n; i += 64 * NW) un[i] = ug[i];
+    // every thread keeps the same copy of the member's time-loop control
+    Ctrl C = *I.ctrl;
+    double cm[8];
     {
         const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
         Maxima<EQ> mx;
         mx.reset();
-        for (int j = tid; j < n; j += RES_BLOCK) {
+        for (int j = tid; j < n; j += 64 * NW) {
             double U[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) U[c] = un[c * n + j];
+            for (int c = 0; c < NC; ++c) U[c] = ug[c * n + j];
             mx.add(U, P.gamma, idx, idy);
         }
-        resident_reduce<EQ>(mx, red, cm, C);
+        resident_wave_maxima<EQ, NW>(mx, red, 1);
+        __syncthreads();  // u^n loaded, maxima published
+        resident_maxima<EQ, NW>(red, 1, cm, C);
     }
     for (int step = 0; step < nsteps; ++step) {
-        if (tid == 0) go = control_update<EQ>(C, cm[0], cm[2], cm[6], I.dx, I.adv) ? 1 : 0;
-        __syncthreads();
-        if (!go) break;  // uniform: read after the barrier by every thread
+        if (!control_update<EQ>(C, cm[0], cm[2], cm[6], I.dx, I.adv)) break;  // the same in every thread
         const double dt = C.dt;
-        resident_stage<EQ, ORDER, M_S1, CH>(P, I, n, un, w, fx, q, red, cm, C, dt);
-        resident_stage<EQ, ORDER, M_S2, CH>(P, I, n, un, w, fx, q, red, cm, C, dt);
-        resident_stage<EQ, ORDER, M_S3, CH>(P, I, n, un, w, fx, q, red, cm, C, dt);
+        // the maxima alternate between two parities from stage to stage (step 0's
+        // first stage after the initial maxima's parity 1), so a wave that runs
+        // ahead never overwrites values another wave has yet to read
+        const int par = (3 * step) & 1;
+        resident_stage<EQ, ORDER, M_S1, CH, NW>(P, I, n, un, un, w1, wl, red, par, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S2, CH, NW>(P, I, n, w1, un, w2, wl, red, par ^ 1, cm, C, dt);
+        resident_stage<EQ, ORDER, M_S3, CH, NW>(P, I, n, w2, un, un, wl, red, par, cm, C, dt);
     }
-    for (int i = tid; i < NC * n; i += RES_BLOCK) ug[i] = un[i];
+    for (int i = tid; i < NC * n; i += 64 * NW) ug[i] = un[i];
     if (tid == 0) *I.ctrl = C;
 }
 
@@ -1369,24 +1412,26 @@ hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s)
     return launch(clear_done, (n_inst + 63) / 64, 64, p, s);
 }
 
-static KFn2 pick_resident(int eq, int order, bool ch)
+template <int NW> static KFn2 pick_resident_w(int eq, int order, bool ch)
 {
-    if (eq == ADVECTION) return order == 7 ? resident_1d<ADVECTION, 7, true> : resident_1d<ADVECTION, 5, true>;
-    if (ch) return order == 7 ? resident_1d<EULER1D, 7, true> : resident_1d<EULER1D, 5, true>;
-    return order == 7 ? resident_1d<EULER1D, 7, false> : resident_1d<EULER1D, 5, false>;
+    if (eq == ADVECTION) return order == 7 ? resident_1d<ADVECTION, 7, true, NW> : resident_1d<ADVECTION, 5, true, NW>;
+    if (ch) return order == 7 ? resident_1d<EULER1D, 7, true, NW> : resident_1d<EULER1D, 5, true, NW>;
+    return order == 7 ? resident_1d<EULER1D, 7, false, NW> : resident_1d<EULER1D, 5, false, NW>;
 }
 
-hipError_t launch_resident(int eq, int order, bool ch, const KParams &p, int n_inst, int nsteps, size_t lds,
-                           hipStream_t s)
+static KFn2 pick_resident(int eq, int order, bool ch) { return pick_resident_w<RES_BLOCK / 64>(eq, order, ch); }
+
+hipError_t launch_resident(int eq, int order, bool ch, int block, const KParams &p, int n_inst, int nsteps,
+                           size_t lds, hipStream_t s)
 {
-    if (eq == EULER2D) return hipErrorInvalidValue;
+    if (eq == EULER2D || block != RES_BLOCK) return hipErrorInvalidValue;
     const KFn2 fn = pick_resident(eq, order, ch);
     // dynamic LDS beyond the default limit must be allowed per kernel
     const hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     KParams copy = p;
     void *args[] = {&copy, &nsteps};
-    return hipLaunchKernel((const void *)fn, dim3(n_inst), dim3(RES_BLOCK), args, lds, s);
+    return hipLaunchKernel((const void *)fn, dim3(n_inst), dim3(block), args, lds, s);
 }
 
 size_t resident_lds_limit()

@@ -27,6 +27,7 @@ struct KParams {
     // LDS-resident launches: member run by workgroup b (members by decreasing
     // size, so the small ones fill the machine behind the large; null: member b)
     const int *res_order;
+    int res_first;  // first entry of res_order a resident launch covers
 };
 
 // every face takes the full selection (no wave-uniform shortcut); results are
@@ -47,8 +48,9 @@ hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, boo
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
 // nsteps controlled steps of every member (all 1D, all fitting the LDS), one
 // workgroup per member; lds = dynamic LDS bytes per workgroup
-hipError_t launch_resident(int eq, int order, bool ch, const KParams &p, int n_inst, int nsteps, size_t lds,
-                           hipStream_t s);
+// block: RES_BLOCK threads per workgroup; n_inst members from p.res_order[p.res_first]
+hipError_t launch_resident(int eq, int order, bool ch, int block, const KParams &p, int n_inst, int nsteps,
+                           size_t lds, hipStream_t s);
 // largest dynamic LDS a resident workgroup may use on this device (0: none)
 size_t resident_lds_limit();
 
