@@ -277,7 +277,7 @@ def bench_c1(seeds=(0, 1, 2, 3), repeats=3):
             "cell_updates_per_s": tot / sum(r["seconds"] for r in runs)}
 
 
-def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
+def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
     """Batched workload: `count` 1D Euler Riemann instances, N ~ LogUniform[128, 16384],
     `steps` CFL steps each (own dt per member), in one persistent launch per stage
     (graph-captured), against the same solves launched one plan at a time (skipped
@@ -291,7 +291,7 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True):
     probs = [E.problem_from_instance(i) for i in insts]
     u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
     states = [u.clone() for u in u0]
-    (best, yw), timing = T.tune_batch(probs, states, steps=3) if tune else ((0, 8), {})
+    (best, yw), timing = T.tune_batch(probs, states, steps=3) if tune else ((wg, 8), {})
     batch = E.enoao_batch_create(probs)
     E.enoao_batch_set_launch(batch, best)
 
@@ -587,7 +587,9 @@ def main():
                          "order's default width, or --y-strip-columns)")
     ap.add_argument("--y-strip-columns", type=int, default=0, choices=(0, 4, 8),
                     help="with --no-tune: y-sweep strip width (0 = the order's default)")
-    ap.add_argument("--only-leg", choices=("batched",), default=None,
+    ap.add_argument("--workgroups-per-cu", type=int, default=0,
+                    help="with --no-tune: resident workgroups per CU of the persistent sweeps (0 = occupancy)")
+    ap.add_argument("--only-leg", choices=("batched", "batched_small"), default=None,
                     help="run only this extra leg (with --steps, --warmup and --no-tune; no comparison "
                          "against one plan per member) and print its JSON: a short run to profile")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -619,14 +621,17 @@ def main():
         del src, dst
     if args.only_leg == "batched":
         print(json.dumps({"batched": bench_batched(steps=args.steps, warmup=args.warmup, tune=not args.no_tune,
-                                                   plain=False)}), flush=True)
+                                                   plain=False, wg=args.workgroups_per_cu)}), flush=True)
+        return
+    if args.only_leg == "batched_small":
+        print(json.dumps({"batched_small": bench_resident(steps=args.steps)}), flush=True)
         return
     n, K, Wu = args.n, args.steps, args.warmup
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
     ep = E.problem_from_instance(inst, order=args.order)
     u0 = torch.from_numpy(inst.u0).cuda()
     u = u0.clone()
-    launch, tuner = (0, args.y_strip_columns or DEFAULT_STRIP_COLUMNS[args.order]), None
+    launch, tuner = (args.workgroups_per_cu, args.y_strip_columns or DEFAULT_STRIP_COLUMNS[args.order]), None
     if not args.no_tune:  # launch shape (workgroups per CU, y strip columns) from the autotuner
         from paper_2108_12742_amd import tune as T
         launch, tuner = T.tune_batch([ep], [u], steps=3)

@@ -42,6 +42,23 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_symbol(name: str) -> str:
+    """a profiler's kernel name without return type and argument list:
+    "void enoao::sweep_y<5, 2, false, 8, true>(enoao::KParams)" -> "enoao::sweep_y<5, 2, false, 8, true>" """
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
 def read_counter(directory: str, counter: str):
     """[(dispatch id, kernel name, value)] of one counter from the CSV files under
     directory, in dispatch order."""
@@ -51,7 +68,7 @@ def read_counter(directory: str, counter: str):
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") != counter:
                     continue
-                rows.append((int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0), r["Kernel_Name"],
+                rows.append((int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0), kernel_symbol(r["Kernel_Name"]),
                              float(r["Counter_Value"])))
     rows.sort()
     return rows
