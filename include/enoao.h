@@ -288,17 +288,20 @@ enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, 
 
 /* LDS-resident solver for small 1D problems (advection and Euler 1D, any
  * order, no selection record).  When every member of a plan or batch fits one
- * workgroup's LDS (state, stage state and face fluxes of the whole line plus
- * one staging chunk: about 1740 nodes for Euler 1D and 6600 for advection on
- * gfx950), enoao_solve and enoao_batch_step run their time-step-controlled
- * steps in launches of many steps each (up to 1024 in enoao_solve, 32 in
- * enoao_batch_step) with one workgroup per member: the state is read from HBM
- * at the start of a launch, every step and stage runs out of LDS, and the
- * state is written back at its end.  The
- * arithmetic is the streaming kernels' (Sections 2 to 4 as above), so results
- * are bitwise the same either way.  enable = 1 (default) allows it for plans
- * and batches used afterwards, 0 forces the streaming kernels; other values
- * return ENOAO_EINVAL.  enoao_step (host-given step) and pools always stream. */
+ * workgroup's LDS (u^n and both stage states of the whole line plus each
+ * wave's staging buffer: about 1890 nodes for Euler 1D and 6600 for advection
+ * on gfx950), enoao_solve and enoao_batch_step run their time-step-controlled
+ * steps in launches of many steps each (up to 1024 in enoao_solve, 128 in
+ * enoao_batch_step) with one 4-wave workgroup per member: the state is read
+ * from HBM at the start of a launch, every step and stage runs out of LDS, and
+ * the state is written back at its end.  Members are grouped by how many of
+ * their workgroups fit one CU's LDS; each group is one launch, and the groups
+ * run concurrently on streams the library forks from and joins back into the
+ * caller's stream.  The arithmetic is the streaming kernels' (Sections 2 to 4
+ * as above), so results are bitwise the same either way.  enable = 1 (default)
+ * allows it for plans and batches used afterwards, 0 forces the streaming
+ * kernels; other values return ENOAO_EINVAL.  enoao_step (host-given step) and
+ * pools always stream. */
 enoao_status enoao_set_resident(int32_t enable);
 
 /* Wave-uniform shortcut of the face kernels (Section 3.2, first principle):
