@@ -496,7 +496,7 @@ def bench_discontinuous(order=5):
     return out
 
 
-def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), arena_gib=4.0):
+def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), arena_gib=4.0, plain=True):
     """Served workload: Poisson arrivals of 2D Euler quadrant solves, N x N with
     N ~ U{128..1024}, each request its own seeded draw of the quadrant generator,
     `nsteps` CFL steps each, admitted into a device pool by arena footprint (requests
@@ -533,6 +533,13 @@ def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
     taken = [by_id[i].steps_done for i in range(requests)]
     work = sum(int(p.nx) * int(p.ny) * k for p, k in zip(probs, taken))
     failed = [i for i in range(requests) if by_id[i].status != 0]
+    out = {"workload": f"euler2d-served-{requests}req-{nsteps}steps-N128..1024-ao5", "requests": requests,
+           "request_data": "quadrant draws, one seed per request",
+           "saturated": {"requests_per_s": requests / sat_s, "cell_updates_per_s": work / sat_s,
+                         "failed_nonphysical": len(failed), "rounds": srv.rounds},
+           "rates": []}
+    if not plain:
+        return out
     # plain: each request alone, one after another (plan creation included, as a
     # per-request caller of the plain path would do it)
     plain_res = {}
@@ -550,13 +557,8 @@ def bench_served(requests=200, nsteps=50, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
     plain_s = time.perf_counter() - t0
     same = all((by_id[i].status != 0) == (plain_res[i] is None) and
                (plain_res[i] is None or np.array_equal(by_id[i].result, plain_res[i])) for i in range(requests))
-    out = {"workload": f"euler2d-served-{requests}req-{nsteps}steps-N128..1024-ao5", "requests": requests,
-           "request_data": "quadrant draws, one seed per request",
-           "saturated": {"requests_per_s": requests / sat_s, "cell_updates_per_s": work / sat_s,
-                         "failed_nonphysical": len(failed), "rounds": srv.rounds,
-                         "plain_cell_updates_per_s": work / plain_s, "speedup_vs_plain": plain_s / sat_s,
-                         "identical_to_plain": same},
-           "rates": []}
+    out["saturated"].update({"plain_cell_updates_per_s": work / plain_s, "speedup_vs_plain": plain_s / sat_s,
+                             "identical_to_plain": same})
     sat_rate = requests / sat_s
     for f in rates:
         rate = f * sat_rate
@@ -589,7 +591,7 @@ def main():
                     help="with --no-tune: y-sweep strip width (0 = the order's default)")
     ap.add_argument("--workgroups-per-cu", type=int, default=0,
                     help="with --no-tune: resident workgroups per CU of the persistent sweeps (0 = occupancy)")
-    ap.add_argument("--only-leg", choices=("batched", "batched_small"), default=None,
+    ap.add_argument("--only-leg", choices=("batched", "batched_small", "served"), default=None,
                     help="run only this extra leg (with --steps, --warmup and --no-tune; no comparison "
                          "against one plan per member) and print its JSON: a short run to profile")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -625,6 +627,9 @@ def main():
         return
     if args.only_leg == "batched_small":
         print(json.dumps({"batched_small": bench_resident(steps=args.steps)}), flush=True)
+        return
+    if args.only_leg == "served":  # saturated throughput only (no plain path, no arrival rates)
+        print(json.dumps({"served": bench_served(requests=args.served_requests, plain=False)}), flush=True)
         return
     n, K, Wu = args.n, args.steps, args.warmup
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)

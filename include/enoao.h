@@ -223,7 +223,9 @@ enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, in
  * Intended for serving loops: admit requests as memory frees up, step, poll,
  * retire finished ones.
  *
- * enoao_pool_member_bytes: arena bytes a member needs (0 if invalid).
+ * enoao_pool_member_bytes: arena bytes a member needs (0 if invalid).  The
+ *   pool keeps its members' states with rows padded to 128-byte multiples;
+ *   admit and retire take and give the dense [ncomp][ny][nx] layout.
  * enoao_pool_admit: copies the initial state u0 (host memory if u0_on_host,
  *   else device memory) into the arena; the member runs CFL steps (cfl > 0)
  *   until t_final or max_steps.  *slot_out receives its slot (0..max_members-1).

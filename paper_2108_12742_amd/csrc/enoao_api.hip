@@ -66,6 +66,13 @@ constexpr size_t BUF_STAGGER = 544;
 // i-th state-sized buffer of a member block
 inline double *member_buffer(double *m, size_t cells, int i) { return m + (size_t)i * (cells + BUF_STAGGER); }
 
+// Row pitch of the states a pool owns: rows padded to a multiple of 16 doubles
+// (128 bytes), so every row starts on a cache line.  A y-sweep wave reads 8-column
+// strips of 8 rows; with rows at arbitrary 8-byte offsets those straddle two lines
+// about half the time (batches of 2D members with nx = ny = 511 or 625 ran 19-20%
+// below nx = ny = 512 or 624).  Caller-owned states (plans, batches) keep pitch nx.
+inline int padded_pitch(int nx) { return (nx + 15) / 16 * 16; }
+
 // device bytes of one member: w1, w2 (+ Lx for 2D) and the selection record
 size_t member_bytes(const enoao_problem *p)
 {
@@ -370,7 +377,7 @@ struct Runtime {
 
     // descriptor of one member; advances the running tile offsets
     void fill_inst(Inst &I, const enoao_problem &p, double *u, double *w1, double *w2, double *lx, uint8_t *sel,
-                   unsigned long long *amax, Ctrl *ctrl, long long &xt, long long &yt) const
+                   unsigned long long *amax, Ctrl *ctrl, long long &xt, long long &yt, int pitch = 0) const
     {
         std::memset(&I, 0, sizeof(I));
         I.u = u;
@@ -382,6 +389,7 @@ struct Runtime {
         I.ctrl = ctrl;
         I.nx = p.nx;
         I.ny = p.ny;
+        I.pitch = pitch > 0 ? pitch : p.nx;
         I.bcx = p.bc_x;
         I.bcy = eq == EULER2D ? p.bc_y : BC_PERIODIC;
         I.dx = (p.x_hi - p.x_lo) / p.nx;
@@ -736,11 +744,12 @@ struct enoao_pool {
             if (!slots[k].used) continue;
             const enoao_problem &p = slots[k].prob;
             double *m = (double *)(arena + slots[k].off);
-            const size_t cells = (size_t)r.nc * p.nx * p.ny;
+            const int pitch = padded_pitch(p.nx);
+            const size_t cells = (size_t)r.nc * pitch * p.ny;
             Inst I;
             r.fill_inst(I, p, member_buffer(m, cells, 0), member_buffer(m, cells, 1), member_buffer(m, cells, 2),
                         r.eq == EULER2D ? member_buffer(m, cells, 3) : nullptr, nullptr,
-                        r.d_amax + (size_t)k * AMAX_SLOTS * AMAX_VALS, r.d_ctrl + k, xt, yt);
+                        r.d_amax + (size_t)k * AMAX_SLOTS * AMAX_VALS, r.d_ctrl + k, xt, yt, pitch);
             r.h_inst.push_back(I);
         }
         r.n = (int)r.h_inst.size();
@@ -758,7 +767,7 @@ struct enoao_pool {
 
 static size_t pool_member_bytes(const enoao_problem *p)
 {
-    const size_t cells = (size_t)ncomp_of(p->equation) * p->nx * p->ny;
+    const size_t cells = (size_t)ncomp_of(p->equation) * padded_pitch(p->nx) * p->ny;
     return enoao_pool::align((cells + BUF_STAGGER) * sizeof(double) * (p->equation == EULER2D ? 4 : 3));
 }
 
@@ -1307,9 +1316,21 @@ enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const
     size_t off;
     if (!pool->arena_alloc(bytes, off)) return ENOAO_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
-    const size_t state = (size_t)r.nc * prob->nx * prob->ny * sizeof(double);
-    if (hipMemcpyAsync(pool->arena + off, u0, state, u0_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                       s) != hipSuccess) {
+    // dense rows of the caller into the member's padded rows (a host state goes
+    // through the member's w1 buffer, unused until its first step)
+    const int pitch = padded_pitch(prob->nx), rows = r.nc * prob->ny;
+    double *mem = (double *)(pool->arena + off);
+    const size_t cells = (size_t)r.nc * pitch * prob->ny;
+    const double *src = u0;
+    if (u0_on_host) {
+        double *tmp = member_buffer(mem, cells, 1);
+        if (hipMemcpyAsync(tmp, u0, (size_t)rows * prob->nx * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+            pool->arena_free(off, bytes);
+            return ENOAO_EDEVICE;
+        }
+        src = tmp;
+    }
+    if (launch_copy_pitched(src, prob->nx, member_buffer(mem, cells, 0), pitch, prob->nx, rows, s) != hipSuccess) {
         pool->arena_free(off, bytes);
         return ENOAO_EDEVICE;
     }
@@ -1373,9 +1394,15 @@ enoao_status enoao_pool_retire(enoao_pool *pool, int32_t slot, double *u_out, in
     hipStream_t s = (hipStream_t)stream;
     const enoao_problem &p = pool->slots[slot].prob;
     if (u_out) {
-        const size_t state = (size_t)r.nc * p.nx * p.ny * sizeof(double);
-        HIP_TRY(hipMemcpyAsync(u_out, pool->arena + pool->slots[slot].off, state,
-                               u_out_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+        // the padded rows back to the dense layout (for a host result through the
+        // member's w1 buffer: the member no longer steps)
+        const int pitch = padded_pitch(p.nx), rows = r.nc * p.ny;
+        double *mem = (double *)(pool->arena + pool->slots[slot].off);
+        const size_t cells = (size_t)r.nc * pitch * p.ny;
+        double *dst = u_out_on_host ? member_buffer(mem, cells, 1) : u_out;
+        HIP_TRY(launch_copy_pitched(member_buffer(mem, cells, 0), pitch, dst, p.nx, p.nx, rows, s));
+        if (u_out_on_host)
+            HIP_TRY(hipMemcpyAsync(u_out, dst, (size_t)rows * p.nx * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     // the member stops stepping at once; its memory is reused only after the copy
     Ctrl &c = pool->h_stage[slot];

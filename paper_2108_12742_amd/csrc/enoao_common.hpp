@@ -66,7 +66,7 @@ struct Inst {
     int segs_per_row;           // ceil(nx / XW_CELLS)
     int ytiles_per_row;         // ceil(ny / yt_cells(w)) tiles per column group (w: y strip width)
     int ycol_groups;            // ceil(nx / yt_cols(w))
-    int pad;
+    int pitch;                  // row pitch of every state buffer, elements (>= nx; planes pitch * ny apart)
     long long xtile0, ytile0;   // first x / y tile of this instance in the batch lists
     long long xtiles, ytiles;   // number of x / y tiles
 };

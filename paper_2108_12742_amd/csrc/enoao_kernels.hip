@@ -446,7 +446,7 @@ __device__ __forceinline__ double rk_combine(double in, double base, double dt, 
 template <int EQ, int MODE> struct View {
     static constexpr int NC = NodeTraits<EQ>::NC;
     long long t0, t1;      // the instance's tiles in the batch list
-    int k, nx, ny, per_row, bc;
+    int k, nx, ny, pitch, per_row, bc;
     int active;            // the instance is still stepping
     const GMEM double *in;    // stage input
     GMEM double *out;         // stage output
@@ -482,6 +482,7 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
     v.t1 = v.t0 + uniform(Y ? I.ytiles : I.xtiles);
     v.nx = uniform(I.nx);
     v.ny = uniform(I.ny);
+    v.pitch = uniform(I.pitch);
     v.per_row = uniform(Y ? I.ytiles_per_row : I.segs_per_row);
     v.bc = uniform(Y ? I.bcy : I.bcx);
     v.ctrl = gmem(uniform(I.ctrl));
@@ -594,8 +595,8 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
     constexpr int NC = NodeTraits<EQ>::NC, NN = XW_FACES + 2 * G - 1;
     const int nx = v.nx, sx = c.segx * XW_CELLS;
     const int row = min(c.row, v.ny - 1);
-    const long long plane = (long long)nx * v.ny;
-    const GMEM double *rowp = v.in + (long long)row * nx;
+    const long long plane = (long long)v.pitch * v.ny;
+    const GMEM double *rowp = v.in + (long long)row * v.pitch;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int i = min(lane + 64 * j, NN - 1);
@@ -605,7 +606,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
     }
     if constexpr ((MODE == M_S2 || MODE == M_S3) && EQ != EULER2D) {
         const int x = min(sx + lane, nx - 1);
-        const GMEM double *b = v.base + (long long)row * nx + x;
+        const GMEM double *b = v.base + (long long)row * v.pitch + x;
 #pragma unroll
         for (int q = 0; q < NC; ++q) pre.base[q] = b[q * plane];
     }
@@ -655,7 +656,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
         if (MODE != M_RHS && P.r_zero >= 0 && tile == v.t0 && tid < AMAX_VALS)
             v.amax[P.r_zero * AMAX_VALS + tid] = 0ull;
         const int nx = v.nx;
-        const long long plane = (long long)nx * v.ny;
+        const long long plane = (long long)v.pitch * v.ny;
         XCur c = x_cursor(tile, v.t0, v.per_row, wseg);
         x_prefetch<EQ, MODE, G>(v, c, lane, pre);
         for (; tile < tend; ++tile) {
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
 
             const int x = sx + lane;
             if (ok && lane < XW_CELLS && x < nx) {
-                const long long o = (long long)c.row * nx + x;
+                const long long o = (long long)c.row * v.pitch + x;
                 double Lc[NC];
 #pragma unroll
                 for (int q = 0; q < NC; ++q)
@@ -798,7 +799,7 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
     using B = YBuf<G, YW>;
     const int perm[4] = {0, 2, 1, 3};
     const int nx = v.nx, ny = v.ny;
-    const long long plane = (long long)nx * ny;
+    const long long plane = (long long)v.pitch * ny;
     const int sy = c.ty * B::CELLS, cbase = c.cg * B::COLS + wv * YW;
     const int b0 = first ? 0 : B::FRESH;
 #pragma unroll
@@ -808,13 +809,13 @@ __device__ __forceinline__ void y_prefetch(const View<EULER2D, MODE> &v, YCur c,
             const int r = i / YW, c0 = i % YW;
             const int y = bc_map(sy - G + r, ny, v.bc);
             const int x = min(cbase + c0, nx - 1);
-            const GMEM double *p = v.in + (long long)y * nx + x;
+            const GMEM double *p = v.in + (long long)y * v.pitch + x;
 #pragma unroll
             for (int q = 0; q < 4; ++q) pre.U[j][q] = p[perm[q] * plane];
         }
     }
     const int fl = lane / YW, y = min(sy + fl, ny - 1), col = min(cbase + (lane % YW), nx - 1);
-    const long long o = (long long)y * nx + col;
+    const long long o = (long long)y * v.pitch + col;
 #pragma unroll
     for (int q = 0; q < 4; ++q) pre.lx[q] = v.lx[q * plane + o];
     if constexpr (MODE == M_S2 || MODE == M_S3) {
@@ -891,7 +892,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
             continue;
         }
         const int nx = v.nx, ny = v.ny;
-        const long long plane = (long long)nx * ny;
+        const long long plane = (long long)v.pitch * ny;
         YCur c = y_cursor(tile, v.t0, v.per_row);
         bool first = true;  // the tile starts a walk
         y_prefetch<MODE, G, YW>(v, c, true, wv, lane, pre);
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
 
             const int y = sy + fl;
             if (y < ny && col < nx) {
-                const long long o = (long long)y * nx + col;
+                const long long o = (long long)y * v.pitch + col;
                 double Ly[NC];  // natural component order
 #pragma unroll
                 for (int q = 0; q < NC; ++q)
@@ -991,7 +992,7 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
     mx.reset();
     int cur = -1;
     long long end = -1;
-    int nx = 0, ny = 0, spr = 1;
+    int nx = 0, ny = 0, pitch = 0, spr = 1;
     long long first = 0;
     const GMEM double *u = nullptr;
     double idx = 0.0, idy = 0.0;
@@ -1005,18 +1006,19 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
             end = first + I.xtiles;
             nx = I.nx;
             ny = I.ny;
+            pitch = I.pitch;
             spr = I.segs_per_row;
             u = gmem(I.u);
             idx = 1.0 / I.dx;
             idy = 1.0 / I.dy;
         }
-        const long long plane = (long long)nx * ny;
+        const long long plane = (long long)pitch * ny;
         const XCur c = x_cursor(tile, first, spr, wseg);
         const int x = c.segx * XW_CELLS + lane;
         if (c.row < ny && lane < XW_CELLS && x < nx) {
             double U[NC];
 #pragma unroll
-            for (int q = 0; q < NC; ++q) U[q] = u[q * plane + (long long)c.row * nx + x];
+            for (int q = 0; q < NC; ++q) U[q] = u[q * plane + (long long)c.row * pitch + x];
             mx.add(U, P.gamma, idx, idy);
         }
     }
@@ -1228,7 +1230,7 @@ __global__ __launch_bounds__(64 * NW) void resident_1d(KParams P, int nsteps)
     extern __shared__ double sm[];
     const int slot = P.res_first + (int)blockIdx.x;
     const Inst &I = P.inst[P.res_order ? P.res_order[slot] : slot];
-    const int n = I.nx, tid = threadIdx.x;
+    const int n = I.nx, pitch = I.pitch, tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     double *un = sm;
     double *w1 = un + NC * n;
@@ -1236,7 +1238,9 @@ __global__ __launch_bounds__(64 * NW) void resident_1d(KParams P, int nsteps)
     double *wl = w2 + NC * n + wv * RW::DOUBLES;
     double *red = w2 + NC * n + NW * RW::DOUBLES;  // two parities of NW x 8 values
     GMEM double *ug = gmem(I.u);
-    for (int i = tid; i < NC * n; i += 64 * NW) un[i] = ug[i];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        for (int j = tid; j < n; j += 64 * NW) un[c * n + j] = ug[c * pitch + j];
     // every thread keeps the same copy of the member's time-loop control
     Ctrl C = *I.ctrl;
     double cm[8];
@@ -1247,7 +1251,7 @@ __global__ __launch_bounds__(64 * NW) void resident_1d(KParams P, int nsteps)
         for (int j = tid; j < n; j += 64 * NW) {
             double U[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) U[c] = ug[c * n + j];
+            for (int c = 0; c < NC; ++c) U[c] = ug[c * pitch + j];
             mx.add(U, P.gamma, idx, idy);
         }
         resident_wave_maxima<EQ, NW>(mx, red, 1);
@@ -1265,7 +1269,9 @@ __global__ __launch_bounds__(64 * NW) void resident_1d(KParams P, int nsteps)
         resident_stage<EQ, ORDER, M_S2, CH, NW>(P, I, n, w1, un, w2, wl, red, par ^ 1, cm, C, dt);
         resident_stage<EQ, ORDER, M_S3, CH, NW>(P, I, n, w2, un, un, wl, red, par, cm, C, dt);
     }
-    for (int i = tid; i < NC * n; i += 64 * NW) ug[i] = un[i];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        for (int j = tid; j < n; j += 64 * NW) ug[c * pitch + j] = un[c * n + j];
     if (tid == 0) *I.ctrl = C;
 }
 
@@ -1284,6 +1290,14 @@ __global__ void clear_done(KParams P)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < P.hdr->n_inst) P.inst[k].ctrl->done = 0;
+}
+
+// copy between a dense and a row-padded layout (pool admission and retirement)
+__global__ void copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows)
+{
+    for (int r = blockIdx.y; r < rows; r += gridDim.y)
+        for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < width; x += gridDim.x * blockDim.x)
+            dst[(long long)r * dp + x] = src[(long long)r * sp + x];
 }
 
 // host-given step size for a single step (all instances)
@@ -1410,6 +1424,15 @@ hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, boo
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s)
 {
     return launch(clear_done, (n_inst + 63) / 64, 64, p, s);
+}
+
+hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows,
+                               hipStream_t s)
+{
+    if (width <= 0 || rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)std::min((width + 255) / 256, 64), (unsigned)std::min(rows, 8192));
+    void *args[] = {&src, &sp, &dst, &dp, &width, &rows};
+    return hipLaunchKernel((const void *)copy_pitched, grid, dim3(256), args, 0, s);
 }
 
 template <int NW> static KFn2 pick_resident_w(int eq, int order, bool ch)

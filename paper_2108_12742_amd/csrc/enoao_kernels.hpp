@@ -46,6 +46,9 @@ hipError_t launch_step_control(int eq, const KParams &p, int n_inst, hipStream_t
 hipError_t launch_set_dt(const KParams &p, int n_inst, double dt, hipStream_t s);
 hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, bool set_lx, hipStream_t s);
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
+// rows of `width` doubles from src (pitch sp) to dst (pitch dp), pitches in doubles
+hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows,
+                               hipStream_t s);
 // nsteps controlled steps of every member (all 1D, all fitting the LDS), one
 // workgroup per member; lds = dynamic LDS bytes per workgroup
 // block: RES_BLOCK threads per workgroup; n_inst members from p.res_order[p.res_first]
