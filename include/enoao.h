@@ -239,7 +239,17 @@ enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, in
  *   physical state), steps taken, time reached.
  * enoao_pool_retire: copies the member's state to u_out (host or device, may
  *   be NULL), synchronises stream and frees the slot and its arena space.
- * A member's result does not depend on the other members of the pool. */
+ * enoao_pool_retire_async: the same without synchronising, for callers that
+ *   keep several rounds in flight (a server that retires a member right after
+ *   enqueuing its last step): enqueues on stream the copy of the state to u_out
+ *   (device memory, dense [ncomp][ny][nx], may be NULL) and of the member's
+ *   progress to info (device memory, 4 doubles: done flag, status, steps, time,
+ *   as enoao_pool_poll reports them; may be NULL), and frees the slot and its
+ *   arena space at once.  Later admissions reuse that space; their copies must
+ *   be enqueued on the same stream (or ordered after this call's work).
+ * A member's result does not depend on the other members of the pool.  Every
+ * call that takes a stream enqueues its device work there; calls on one pool
+ * are meant to use one stream. */
 size_t enoao_pool_member_bytes(const enoao_problem *prob);
 enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, size_t arena_bytes, void *stream,
                                enoao_pool **out);
@@ -251,6 +261,7 @@ enoao_status enoao_pool_step(enoao_pool *pool, int32_t nsteps, void *stream);
 enoao_status enoao_pool_poll(enoao_pool *pool, int32_t *done, int32_t *status, int64_t *steps, double *t,
                              int32_t n, void *stream);
 enoao_status enoao_pool_retire(enoao_pool *pool, int32_t slot, double *u_out, int32_t u_out_on_host, void *stream);
+enoao_status enoao_pool_retire_async(enoao_pool *pool, int32_t slot, double *u_out, double *info, void *stream);
 enoao_status enoao_pool_usage(const enoao_pool *pool, size_t *arena_used, size_t *arena_total, int32_t *members);
 
 /* ---- per-kernel timing -------------------------------------------------

@@ -699,7 +699,12 @@ struct enoao_pool {
     };
     std::vector<Slot> slots;
     std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted by offset
-    Ctrl *h_stage = nullptr;                           // pinned per-slot control staging
+    // pinned copies of the header and instance list that rebuild uploads: two,
+    // used in turn, each reused only after its last upload has completed, so a
+    // rebuild does not wait for the stream
+    char *h_pin[2] = {nullptr, nullptr};
+    hipEvent_t ev_pin[2] = {nullptr, nullptr};
+    int pin_cur = 0;
     bool dirty = false;
     int graph_steps = 0;
 
@@ -756,11 +761,60 @@ struct enoao_pool {
         r.h_hdr.n_inst = r.n;
         r.h_hdr.xtiles_total = xt;
         r.h_hdr.ytiles_total = yt;
-        if (r.n > 0)
-            HIP_TRY(hipMemcpyAsync(r.d_inst, r.h_inst.data(), sizeof(Inst) * r.n, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(r.d_hdr, &r.h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));  // host copies are reused by the next rebuild
+        pin_cur ^= 1;
+        HIP_TRY(hipEventSynchronize(ev_pin[pin_cur]));  // this buffer's previous upload
+        char *h = h_pin[pin_cur];
+        std::memcpy(h, &r.h_hdr, sizeof(BatchHdr));
+        if (r.n > 0) {
+            std::memcpy(h + pin_inst_offset(), r.h_inst.data(), sizeof(Inst) * r.n);
+            HIP_TRY(hipMemcpyAsync(r.d_inst, h + pin_inst_offset(), sizeof(Inst) * r.n, hipMemcpyHostToDevice, s));
+        }
+        HIP_TRY(hipMemcpyAsync(r.d_hdr, h, sizeof(BatchHdr), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ev_pin[pin_cur], s));
         dirty = false;
+        return ENOAO_OK;
+    }
+
+    static size_t pin_inst_offset() { return align(sizeof(BatchHdr)); }
+    size_t pin_bytes() const { return pin_inst_offset() + sizeof(Inst) * (size_t)max_members; }
+
+    void free_pins()
+    {
+        for (int i = 0; i < 2; ++i) {
+            if (ev_pin[i]) hipEventDestroy(ev_pin[i]);
+            if (h_pin[i]) hipHostFree(h_pin[i]);
+            ev_pin[i] = nullptr;
+            h_pin[i] = nullptr;
+        }
+    }
+
+    // copy out (optional), stop the member, free its slot and arena space.  The
+    // space is reused by later admissions, which enqueue their copies on the
+    // stream after this call's work.
+    enoao_status release_slot(int slot, double *u_out, bool u_out_on_host, double *info, hipStream_t s)
+    {
+        Runtime &r = rt;
+        const enoao_problem &p = slots[slot].prob;
+        if (u_out) {
+            // the padded rows back to the dense layout (for a host result through the
+            // member's w1 buffer: the member no longer steps)
+            const int pitch = padded_pitch(p.nx), rows = r.nc * p.ny;
+            double *mem = (double *)(arena + slots[slot].off);
+            const size_t cells = (size_t)r.nc * pitch * p.ny;
+            double *dst = u_out_on_host ? member_buffer(mem, cells, 1) : u_out;
+            HIP_TRY(launch_copy_pitched(member_buffer(mem, cells, 0), pitch, dst, p.nx, p.nx, rows, s));
+            if (u_out_on_host)
+                HIP_TRY(hipMemcpyAsync(u_out, dst, (size_t)rows * p.nx * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        // the member stops stepping at once
+        Ctrl c;
+        std::memset(&c, 0, sizeof(Ctrl));
+        c.done = 1;
+        HIP_TRY(launch_set_ctrl(r.d_ctrl + slot, c, info, s));
+        HIP_TRY(r.mark(s));
+        arena_free(slots[slot].off, slots[slot].bytes);
+        slots[slot].used = false;
+        dirty = true;
         return ENOAO_OK;
     }
 };
@@ -1213,7 +1267,7 @@ enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, s
     Runtime &r = pl->rt;
     hipStream_t s = (hipStream_t)stream;
     auto fail = [&](enoao_status e) {
-        if (pl->h_stage) hipHostFree(pl->h_stage);
+        pl->free_pins();
         r.release();
         delete pl;
         return e;
@@ -1262,9 +1316,15 @@ enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, s
         r.h_ctrl = nullptr;
         return fail(ENOAO_ENOMEM);
     }
-    if (hipHostMalloc((void **)&pl->h_stage, sizeof(Ctrl) * max_members, hipHostMallocDefault) != hipSuccess) {
-        pl->h_stage = nullptr;
-        return fail(ENOAO_ENOMEM);
+    for (int i = 0; i < 2; ++i) {
+        if (hipHostMalloc((void **)&pl->h_pin[i], pl->pin_bytes(), hipHostMallocDefault) != hipSuccess) {
+            pl->h_pin[i] = nullptr;
+            return fail(ENOAO_ENOMEM);
+        }
+        if (hipEventCreateWithFlags(&pl->ev_pin[i], hipEventDisableTiming) != hipSuccess) {
+            pl->ev_pin[i] = nullptr;
+            return fail(ENOAO_EDEVICE);
+        }
     }
     std::vector<Ctrl> c0(max_members);
     for (auto &c : c0) {
@@ -1285,7 +1345,7 @@ enoao_status enoao_pool_destroy(enoao_pool *pool)
 {
     if (!pool) return ENOAO_EINVAL;
     pool->rt.wait_marks();  // the pool's work on the streams it was given
-    if (pool->h_stage) hipHostFree(pool->h_stage);
+    pool->free_pins();
     pool->rt.release();
     delete pool;
     return ENOAO_OK;
@@ -1334,12 +1394,12 @@ enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const
         pool->arena_free(off, bytes);
         return ENOAO_EDEVICE;
     }
-    Ctrl &c = pool->h_stage[slot];
+    Ctrl c;
     std::memset(&c, 0, sizeof(Ctrl));
     c.t_final = t_final;
     c.cfl = cfl;
     c.max_steps = max_steps;
-    if (hipMemcpyAsync(r.d_ctrl + slot, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s) != hipSuccess) {
+    if (launch_set_ctrl(r.d_ctrl + slot, c, nullptr, s) != hipSuccess) {
         pool->arena_free(off, bytes);
         return ENOAO_EDEVICE;
     }
@@ -1390,30 +1450,16 @@ enoao_status enoao_pool_poll(enoao_pool *pool, int32_t *done, int32_t *status, i
 enoao_status enoao_pool_retire(enoao_pool *pool, int32_t slot, double *u_out, int32_t u_out_on_host, void *stream)
 {
     if (!pool || slot < 0 || slot >= pool->max_members || !pool->slots[slot].used) return ENOAO_EINVAL;
-    Runtime &r = pool->rt;
     hipStream_t s = (hipStream_t)stream;
-    const enoao_problem &p = pool->slots[slot].prob;
-    if (u_out) {
-        // the padded rows back to the dense layout (for a host result through the
-        // member's w1 buffer: the member no longer steps)
-        const int pitch = padded_pitch(p.nx), rows = r.nc * p.ny;
-        double *mem = (double *)(pool->arena + pool->slots[slot].off);
-        const size_t cells = (size_t)r.nc * pitch * p.ny;
-        double *dst = u_out_on_host ? member_buffer(mem, cells, 1) : u_out;
-        HIP_TRY(launch_copy_pitched(member_buffer(mem, cells, 0), pitch, dst, p.nx, p.nx, rows, s));
-        if (u_out_on_host)
-            HIP_TRY(hipMemcpyAsync(u_out, dst, (size_t)rows * p.nx * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    // the member stops stepping at once; its memory is reused only after the copy
-    Ctrl &c = pool->h_stage[slot];
-    std::memset(&c, 0, sizeof(Ctrl));
-    c.done = 1;
-    HIP_TRY(hipMemcpyAsync(r.d_ctrl + slot, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    if (enoao_status e = pool->release_slot(slot, u_out, u_out_on_host != 0, nullptr, s)) return e;
     HIP_TRY(hipStreamSynchronize(s));
-    pool->arena_free(pool->slots[slot].off, pool->slots[slot].bytes);
-    pool->slots[slot].used = false;
-    pool->dirty = true;
     return ENOAO_OK;
+}
+
+enoao_status enoao_pool_retire_async(enoao_pool *pool, int32_t slot, double *u_out, double *info, void *stream)
+{
+    if (!pool || slot < 0 || slot >= pool->max_members || !pool->slots[slot].used) return ENOAO_EINVAL;
+    return pool->release_slot(slot, u_out, false, info, (hipStream_t)stream);
 }
 
 enoao_status enoao_pool_usage(const enoao_pool *pool, size_t *arena_used, size_t *arena_total, int32_t *members)

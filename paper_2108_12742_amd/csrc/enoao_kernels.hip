@@ -1292,6 +1292,21 @@ __global__ void clear_done(KParams P)
     if (k < P.hdr->n_inst) P.inst[k].ctrl->done = 0;
 }
 
+// replace a member's control block (pool admission and retirement); info, if
+// given, receives the old block's done flag, status, step count and time
+__global__ void set_ctrl(Ctrl *c, Ctrl v, double *info)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (info) {
+            info[0] = c->done;
+            info[1] = c->status;
+            info[2] = (double)c->steps;
+            info[3] = c->t;
+        }
+        *c = v;
+    }
+}
+
 // copy between a dense and a row-padded layout (pool admission and retirement)
 __global__ void copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows)
 {
@@ -1424,6 +1439,13 @@ hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, boo
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s)
 {
     return launch(clear_done, (n_inst + 63) / 64, 64, p, s);
+}
+
+hipError_t launch_set_ctrl(Ctrl *c, const Ctrl &v, double *info, hipStream_t s)
+{
+    Ctrl copy = v;
+    void *args[] = {&c, &copy, &info};
+    return hipLaunchKernel((const void *)set_ctrl, dim3(1), dim3(64), args, 0, s);
 }
 
 hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows,

@@ -46,6 +46,9 @@ hipError_t launch_step_control(int eq, const KParams &p, int n_inst, hipStream_t
 hipError_t launch_set_dt(const KParams &p, int n_inst, double dt, hipStream_t s);
 hipError_t launch_patch_inst(Inst *inst, int k, const double *u, double *lx, bool set_lx, hipStream_t s);
 hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
+// *c = v on the stream (v passed by value: no host buffer outlives the call);
+// info (device, 4 doubles, may be null) receives the old done, status, steps, t
+hipError_t launch_set_ctrl(Ctrl *c, const Ctrl &v, double *info, hipStream_t s);
 // rows of `width` doubles from src (pitch sp) to dst (pitch dp), pitches in doubles
 hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows,
                                hipStream_t s);

@@ -130,6 +130,7 @@ def lib():
             "enoao_pool_poll": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp], st),
             "enoao_pool_retire": ([vp, ctypes.c_int32, vp, ctypes.c_int32, vp], st),
+            "enoao_pool_retire_async": ([vp, ctypes.c_int32, vp, vp, vp], st),
             "enoao_pool_usage": ([vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                   ctypes.POINTER(ctypes.c_int32)], st),
         }
@@ -453,6 +454,23 @@ def enoao_pool_retire(pool: Pool, slot: int, shape=None, out=None, stream=None):
     _check(lib().enoao_pool_retire(pool.handle, int(slot), None, 1, _stream(stream)), "enoao_pool_retire")
     del pool.members[int(slot)]
     return None
+
+
+def enoao_pool_retire_async(pool: Pool, slot: int, out=None, info=None, stream=None):
+    """Free a member without synchronising: the copy of its state to `out` (a GPU
+    tensor of the member's shape, or None) and of its progress to `info` (a GPU
+    float64 tensor of 4 elements: done, status, steps, t; or None) are enqueued on
+    the stream; the slot and its arena space are free at once (later admissions on
+    the same stream reuse them after this work)."""
+    prob = pool.members.get(int(slot))
+    if prob is None:
+        raise ValueError(f"slot {slot} holds no admitted member")
+    optr = _dev_ptr(out, prob.shape, what="out") if out is not None else None
+    iptr = _dev_ptr(info, (4,), what="info") if info is not None else None
+    _check(lib().enoao_pool_retire_async(pool.handle, int(slot), optr, iptr, _stream(stream)),
+           "enoao_pool_retire_async")
+    del pool.members[int(slot)]
+    return out
 
 
 def enoao_pool_usage(pool: Pool):

@@ -16,7 +16,15 @@ earlier: with steps_per_round = 0 (the default) a round runs as many steps as
 the active request closest to its end still needs (at most max_round_steps), so
 that request retires, and its memory frees up for the queue, exactly when the
 round ends; every request stops at its own step count on the device either way.
-The host reads the pool's state once per round, not once per step.
+
+A pipelined backend (retire_async and fence) lets the host run ahead of the
+device: every member takes exactly the steps it is given, so the server knows
+which requests end with a round without reading the device, retires them right
+after enqueuing that round (their copies follow it on the stream), and admits
+the next ones into the freed memory while the round computes.  A request that
+stopped early (a non-physical state) is found from the progress its retirement
+returns.  fence() keeps at most a few rounds in flight.  Otherwise the host
+reads the pool's state once per round (poll) and retires what it reports done.
 
 The scheduling is independent of the device: `Server` drives any backend with
 the `Backend` methods below.  `GpuPoolBackend` is the HIP pool of the C ABI.
@@ -25,6 +33,7 @@ from __future__ import annotations
 
 import time
 from collections import deque
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -60,6 +69,7 @@ class Backend:
     """What the server needs from a device pool."""
     max_members: int
     arena_bytes: int
+    pipelined = False   # True: retire_async and fence below are available
 
     def member_bytes(self, problem) -> int: ...
     def admit(self, problem, u0, nsteps, cfl): ...  # slot, or None when there is no room now
@@ -72,6 +82,16 @@ class Backend:
         of u0.  The default keeps u0 (admit copies it)."""
         return u0
 
+    def retire_async(self, slot: int, shape):  # a Pending whose info() gives (status, steps)
+        raise NotImplementedError
+
+    def ready(self, staged) -> bool:
+        """Whether a staged state has arrived (admitting it would not wait)."""
+        return True
+
+    def fence(self):
+        """Called after each round is enqueued: waits while too many are in flight."""
+
 
 class Pending:
     """A result on its way to the host."""
@@ -79,10 +99,14 @@ class Pending:
     def ready(self) -> bool: ...
     def result(self) -> np.ndarray: ...
 
+    def info(self):
+        """(status, steps) of the member when it was retired, or None if unknown."""
+        return None
+
 
 class _Download(Pending):
-    def __init__(self, host, event):
-        self.host, self.event = host, event
+    def __init__(self, host, event, host_info=None):
+        self.host, self.event, self.host_info = host, event, host_info
 
     def ready(self):
         return self.event.query()
@@ -93,25 +117,39 @@ class _Download(Pending):
         self.event.synchronize()
         return self.host.numpy()
 
+    def info(self):
+        if self.host_info is None:
+            return None
+        self.event.synchronize()
+        i = self.host_info.numpy()
+        return int(i[1]), int(i[2])
+
 
 class GpuPoolBackend(Backend):
     """The HIP pool.  With overlap=True, host states move through pinned memory on a
-    copy stream of their own: inputs are uploaded while a round computes and admitted
-    from the device; results are copied out of the arena on the device and downloaded
-    while later rounds compute."""
+    copy stream of their own: inputs are copied into pinned memory and uploaded by a
+    staging thread while rounds compute, and admitted from the device; results are
+    copied out of the arena on the device and downloaded while later rounds compute.
+    (Uploading at admission instead, from pageable memory, held the host about 1 ms per
+    request while the device idled at the boundary between two generations of
+    requests.)"""
 
     def __init__(self, like, max_members=256, arena_bytes=8 << 30, stream=None, workgroups_per_cu=0,
-                 overlap=True):
+                 overlap=True, depth=2):
         import torch
         from . import enoao as E
         self.E, self.torch = E, torch
         self.stream = stream
+        self.pipelined = overlap
+        self.depth = depth      # rounds in flight at most (pipelined)
+        self.inflight = deque()
         self.pool = E.enoao_pool_create(like, max_members, arena_bytes, stream)
         if workgroups_per_cu:
             E.enoao_pool_set_launch(self.pool, workgroups_per_cu)
         self.max_members = max_members
         self.arena_bytes = E.enoao_pool_usage(self.pool)[1]
         self.copy = torch.cuda.Stream() if overlap else None
+        self.stager = ThreadPoolExecutor(1) if overlap else None
 
     def _compute(self):
         return self.stream if self.stream is not None else self.torch.cuda.current_stream()
@@ -122,6 +160,10 @@ class GpuPoolBackend(Backend):
     def stage(self, problem, u0):
         if self.copy is None or not isinstance(u0, np.ndarray):
             return u0
+        return self.stager.submit(self._upload, u0)
+
+    def _upload(self, u0):
+        # staging thread: pinned copy, then the upload on the copy stream
         torch = self.torch
         host = torch.empty(u0.shape, dtype=torch.float64, pin_memory=True)
         host.numpy()[...] = u0
@@ -132,7 +174,14 @@ class GpuPoolBackend(Backend):
             ev.record(self.copy)
         return (dev, ev, host)
 
+    def ready(self, staged):
+        if isinstance(staged, Future):
+            return staged.done() and staged.result()[1].query()
+        return True
+
     def admit(self, problem, u0, nsteps, cfl):
+        if isinstance(u0, Future):
+            u0 = u0.result()
         if isinstance(u0, tuple):
             dev, ev, _ = u0
             comp = self._compute()
@@ -164,7 +213,34 @@ class GpuPoolBackend(Backend):
         dev.record_stream(self.copy)
         return _Download(host, ev)
 
+    def retire_async(self, slot, shape):
+        torch = self.torch
+        comp = self._compute()
+        dev = torch.empty(shape, dtype=torch.float64, device="cuda")
+        info = torch.empty(4, dtype=torch.float64, device="cuda")
+        self.E.enoao_pool_retire_async(self.pool, slot, out=dev, info=info, stream=self.stream)
+        host = torch.empty(shape, dtype=torch.float64, pin_memory=True)
+        host_info = torch.empty(4, dtype=torch.float64, pin_memory=True)
+        self.copy.wait_stream(comp)
+        with torch.cuda.stream(self.copy):
+            host.copy_(dev, non_blocking=True)
+            host_info.copy_(info, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        dev.record_stream(self.copy)
+        info.record_stream(self.copy)
+        return _Download(host, ev, host_info)
+
+    def fence(self):
+        ev = self.torch.cuda.Event()
+        ev.record(self._compute())
+        self.inflight.append(ev)
+        while len(self.inflight) > self.depth:
+            self.inflight.popleft().synchronize()
+
     def close(self):
+        if self.stager is not None:
+            self.stager.shutdown(wait=True)
         self.E.enoao_pool_destroy(self.pool)
 
 
@@ -174,7 +250,8 @@ class Server:
     steps_per_round: int = 0   # 0: adaptive (the fewest steps an active request still needs)
     max_round_steps: int = 8   # bound on an adaptive round (latency of newly arrived requests)
     clock: object = time.perf_counter
-    stage_ahead: int = 4       # queued requests whose upload starts while a round computes
+    stage_ahead: int = 64      # queued requests whose upload may start while rounds compute
+    stage_bytes: int = 1 << 30  # ... as long as their states total at most this many bytes
     queue: deque = field(default_factory=deque)
     active: dict = field(default_factory=dict)   # slot -> Request
     pending: list = field(default_factory=list)  # (Request, Pending) results on their way
@@ -194,10 +271,14 @@ class Server:
         return r
 
     def admit(self):
-        """FIFO admission while slots and arena memory allow."""
+        """FIFO admission while slots and arena memory allow.  While other requests
+        compute, a request whose staged upload has not arrived yet waits for the next
+        round instead of holding the host."""
         n = 0
         while self.queue and len(self.active) < self.backend.max_members:
             r = self.queue[0]
+            if self.active and r.staged is not None and not self.backend.ready(r.staged):
+                break
             slot = self.backend.admit(r.problem, r.u0 if r.staged is None else r.staged, r.nsteps, r.cfl)
             if slot is None:
                 break
@@ -208,9 +289,15 @@ class Server:
         return n
 
     def _stage(self):
-        for r in list(self.queue)[:self.stage_ahead]:
+        staged = sum(r.u0.nbytes for r in self.queue if r.staged is not None)
+        for i, r in enumerate(self.queue):
+            if i >= self.stage_ahead:
+                break
             if r.staged is None:
+                if staged > 0 and staged + r.u0.nbytes > self.stage_bytes:
+                    break
                 r.staged = self.backend.stage(r.problem, r.u0)
+                staged += r.u0.nbytes
 
     def _finish(self, r, result):
         r.result = result
@@ -222,7 +309,16 @@ class Server:
         left = []
         for r, p in self.pending:
             if wait or p.ready():
-                self._finish(r, p.result())
+                res = p.result()
+                info = p.info()
+                if info is not None:  # retired on the prediction: check what the device did
+                    status, steps = info
+                    r.steps_done = steps
+                    if status:
+                        r.status, r.error = status, "non-physical state"
+                    elif steps != r.nsteps:
+                        r.status, r.error = -2, f"stopped after {steps} of {r.nsteps} steps"
+                self._finish(r, res)
             else:
                 left.append((r, p))
         self.pending = left
@@ -242,8 +338,22 @@ class Server:
         if not self.active:
             self.collect(wait=not self.queue)
             return 0
-        self.backend.step(self.round_steps())
+        k = self.round_steps()
+        self.backend.step(k)
         self.rounds += 1
+        if self.backend.pipelined:
+            finished = 0
+            for slot in list(self.active):
+                r = self.active[slot]
+                r.steps_done = min(r.nsteps, r.steps_done + k)
+                if r.steps_done >= r.nsteps:
+                    del self.active[slot]
+                    self.pending.append((r, self.backend.retire_async(slot, r.problem.shape)))
+                    finished += 1
+            self.backend.fence()
+            self._stage()
+            self.collect()
+            return finished
         self._stage()
         self.collect()
         done, status, steps = self.backend.poll()

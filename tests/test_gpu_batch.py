@@ -115,6 +115,51 @@ def test_pool_members_join_and_leave():
     assert E.enoao_pool_usage(pool)[0] == 0
 
 
+def test_pool_retire_async_reuses_space_in_stream_order():
+    """enoao_pool_retire_async: no host synchronisation between rounds.  Members are
+    retired on their own step count right after the step call that finished them, the
+    next member is admitted into the freed arena space at once (its copy follows the
+    retirement's on the stream), and the host reads nothing until the end: every result
+    equals its solve alone and every progress record says status 0 and its step count."""
+    torch = PT.torch_cuda()
+    E = _E()
+    insts = [W.quadrants(s, n, n + 3) for s, n in ((1, 45), (2, 33), (3, 61), (5, 20), (1, 40), (4, 52))]
+    nsteps = [5, 3, 4, 6, 2, 3]
+    like = E.problem_from_instance(insts[0])
+    bytes_per = [E.enoao_pool_member_bytes(E.problem_from_instance(i)) for i in insts]
+    pool = E.enoao_pool_create(like, 2, sum(sorted(bytes_per)[-2:]) + 4096)
+    outs = {k: torch.empty(i.u0.shape, dtype=torch.float64, device="cuda") for k, i in enumerate(insts)}
+    infos = {k: torch.empty(4, dtype=torch.float64, device="cuda") for k in range(len(insts))}
+    slots, left, pending, rounds = {}, {}, list(range(len(insts))), 0
+    while pending or slots:
+        while pending:
+            k = pending[0]
+            s = E.enoao_pool_admit(pool, E.problem_from_instance(insts[k]), PT.to_dev(torch, insts[k].u0),
+                                   max_steps=nsteps[k])
+            if s is None:
+                break
+            slots[s], left[s] = k, nsteps[k]
+            pending.pop(0)
+        n = min(left.values())
+        E.enoao_pool_step(pool, n)
+        rounds += 1
+        for s in list(slots):
+            left[s] -= n
+            if left[s] == 0:
+                k = slots.pop(s)
+                del left[s]
+                E.enoao_pool_retire_async(pool, s, out=outs[k], info=infos[k])
+        assert rounds < 100
+    torch.cuda.synchronize()
+    for k, inst in enumerate(insts):
+        ref, _, _ = _alone(torch, E, inst, nsteps[k])
+        np.testing.assert_array_equal(outs[k].cpu().numpy(), ref)
+        done, status, steps, t = infos[k].cpu().numpy()
+        # (done is set by the step control of the step after the last one)
+        assert done in (0, 1) and status == 0 and steps == nsteps[k] and t > 0
+    assert E.enoao_pool_usage(pool)[0] == 0
+
+
 def test_server_on_gpu_pool():
     PT.torch_cuda()
     E = _E()

@@ -207,3 +207,80 @@ def test_adaptive_rounds_stop_when_the_first_request_finishes():
         for _ in range(n):
             u = O.step(op, u, O.cfl_dt(op, u, 0.3))
         np.testing.assert_array_equal(r.result, u)
+
+
+class _Retired(S.Pending):
+    def __init__(self, value, status, steps, clock, at):
+        self.value, self.status, self.steps, self.clock, self.at = value, status, steps, clock, at
+
+    def ready(self):
+        return self.clock.t >= self.at
+
+    def result(self):
+        return self.value
+
+    def info(self):
+        return self.status, self.steps
+
+
+class PipelinedFakePool(FakePool):
+    """A pipelined backend: the server never polls; it retires on its own step count and
+    learns from the retirement what the member did.  Members whose initial state is
+    marked fail after `fail_after` steps (they stop there with a non-zero status, as the
+    device does on a non-physical state)."""
+    pipelined = True
+
+    def __init__(self, *a, fail_after=None, **k):
+        super().__init__(*a, **k)
+        self.fail_after = fail_after or {}
+        self.fences = 0
+        self.status = {}
+
+    def admit(self, problem, u0, nsteps, cfl):
+        slot = super().admit(problem, u0, nsteps, cfl)
+        if slot is not None:
+            self.status[slot] = 0
+            key = np.ascontiguousarray(u0).tobytes()
+            if key in self.fail_after:
+                self.members[slot][3] = self.fail_after[key]   # the device stops it there
+                self.status[slot] = 1
+        return slot
+
+    def poll(self):
+        raise AssertionError("a pipelined server does not poll")
+
+    def retire_async(self, slot, shape):
+        steps = self.members[slot][2]
+        status = self.status.pop(slot)
+        return _Retired(super().retire(slot, shape), status, steps, self.clock, self.clock.t + 1.0)
+
+    def fence(self):
+        self.fences += 1
+
+
+def test_pipelined_rounds_retire_on_the_step_count():
+    """Pipelined backend: requests retire right after the round that gives them their last
+    step, without polling; a request whose member stopped early on the device reports
+    the failure from its retirement; every other result equals its solve alone."""
+    clock = Clock()
+    reqs_in = [(_request(21, 24), 7), (_request(22, 24), 3), (_request(23, 24), 12), (_request(24, 24), 5),
+               (_request(25, 24), 4)]
+    bad = reqs_in[2][0][1]
+    budget = 3 * 8 * 3 * 24 * 2  # two members at a time
+    pool = PipelinedFakePool(max_members=8, arena_bytes=budget, clock=clock,
+                             fail_after={np.ascontiguousarray(bad).tobytes(): 2})
+    srv = S.Server(pool, clock=clock, max_round_steps=4)
+    reqs = [srv.submit(*rq, nsteps=n) for rq, n in reqs_in]
+    srv.drain()
+    assert srv.idle() and pool.fences == srv.rounds and pool.used == 0
+    assert reqs[2].status != 0 and reqs[2].error == "non-physical state" and reqs[2].steps_done == 2
+    for k, (r, ((prob, u0), n)) in enumerate(zip(reqs, reqs_in)):
+        if k == 2:
+            continue
+        assert r.status == 0 and r.steps_done == n and r.finished >= r.admitted
+        op = prob.oracle()
+        u = u0
+        for _ in range(n):
+            u = O.step(op, u, O.cfl_dt(op, u, 0.3))
+        np.testing.assert_array_equal(r.result, u)
+    assert [r.admitted for r in reqs] == sorted(r.admitted for r in reqs)
