@@ -244,6 +244,26 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(r, e, r);
 }
 
+// sqrt(x) for positive normal x: hardware reciprocal square root refined by
+// Goldschmidt's coupled iteration for sqrt(x) and 1/(2 sqrt(x)), with two
+// Newton corrections of the root.  The compiler's sqrt takes the same steps
+// plus a range scaling and special-value selects, which the kernels' operands
+// (densities, squared sound speeds of physical states) never need; on them the
+// results agree bit for bit.
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double r = __builtin_amdgcn_rsq(x);
+    double y = x * r;
+    double h = 0.5 * r;
+    const double e = fma(-h, y, 0.5);
+    y = fma(y, e, y);
+    h = fma(h, e, h);
+    double d = fma(-y, y, x);
+    y = fma(d, h, y);
+    d = fma(-y, y, x);
+    return fma(d, h, y);
+}
+
 template <int EQ> struct NodeTraits;
 template <> struct NodeTraits<ADVECTION> { static constexpr int NC = 1, NQ = 1; };
 template <> struct NodeTraits<EULER1D> { static constexpr int NC = 3, NQ = 9; };
@@ -264,7 +284,7 @@ __device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>
         const double p = gm1 * fma(-0.5 * rho, u * u, E);
         q[0] = rho; q[1] = m; q[2] = E;
         q[3] = m; q[4] = fma(m, u, p); q[5] = (E + p) * u;
-        q[6] = sqrt(rho); q[7] = u; q[8] = (E + p) * ir;
+        q[6] = sqrt_nr(rho); q[7] = u; q[8] = (E + p) * ir;
         return rho > 0.0 && p > 0.0;
     } else {
         const double rho = U[0], m = U[1], n = U[2], E = U[3];
@@ -273,7 +293,7 @@ __device__ __forceinline__ bool node_quantities(const double (&U)[NodeTraits<EQ>
         const double p = gm1 * fma(-0.5 * rho, fma(u, u, v * v), E);
         q[0] = rho; q[1] = m; q[2] = n; q[3] = E;
         q[4] = m; q[5] = fma(m, u, p); q[6] = m * v; q[7] = (E + p) * u;
-        q[8] = sqrt(rho); q[9] = u; q[10] = v; q[11] = (E + p) * ir;
+        q[8] = sqrt_nr(rho); q[9] = u; q[10] = v; q[11] = (E + p) * ir;
         return rho > 0.0 && p > 0.0;
     }
 }
@@ -295,7 +315,7 @@ __device__ __forceinline__ RoeState roe_state(double sL, double uL, double vL, d
     r.H = fma(wL, HL, wR * HR);
     r.q2h = 0.5 * fma(r.u, r.u, r.v * r.v);
     const double c2 = gm1 * (r.H - r.q2h);
-    r.c = sqrt(c2);
+    r.c = sqrt_nr(c2);
     r.ic = rcp_nr(r.c);
     r.b1 = gm1 * r.ic * r.ic;
     r.b2 = r.q2h * r.b1;

@@ -99,7 +99,7 @@ template <int EQ> struct Maxima {
         } else if constexpr (EQ == EULER1D) {
             const double rho = U[0], ir = rcp_nr(rho), u = U[1] * ir;
             const double p = (gamma - 1.0) * fma(-0.5 * rho, u * u, U[2]);
-            const double c = sqrt(gamma * p * ir);
+            const double c = sqrt_nr(gamma * p * ir);
             bad |= !(rho > 0.0 && p > 0.0);
             v[0] = fmax(v[0], fabs(u - c));
             v[1] = fmax(v[1], fabs(u));
@@ -107,7 +107,7 @@ template <int EQ> struct Maxima {
         } else {
             const double rho = U[0], ir = rcp_nr(rho), u = U[1] * ir, w = U[2] * ir;
             const double p = (gamma - 1.0) * fma(-0.5 * rho, fma(u, u, w * w), U[3]);
-            const double c = sqrt(gamma * p * ir);
+            const double c = sqrt_nr(gamma * p * ir);
             bad |= !(rho > 0.0 && p > 0.0);
             v[0] = fmax(v[0], fabs(u - c));
             v[1] = fmax(v[1], fabs(u));
