@@ -558,11 +558,19 @@ __device__ __forceinline__ XCur x_cursor(long long tile, long long t0, int per_r
     return XCur{(int)row, (int)(seg - row * (unsigned)per_row)};
 }
 
-__device__ __forceinline__ XCur x_advance(XCur c, int per_row)
+// segment number seg of an instance (grid lines of per_row segments each)
+__device__ __forceinline__ XCur x_segment(unsigned seg, int per_row)
 {
-    c.segx += XW_SEGS;
-    while (c.segx >= per_row) {
-        c.segx -= per_row;
+    const unsigned row = seg / (unsigned)per_row;
+    return XCur{(int)row, (int)(seg - row * (unsigned)per_row)};
+}
+
+// the next segment of an instance; it continues c along the same grid line
+// unless it starts a new one (segx == 0)
+__device__ __forceinline__ XCur x_next(XCur c, int per_row)
+{
+    if (++c.segx == per_row) {
+        c.segx = 0;
         ++c.row;
     }
     return c;
@@ -579,18 +587,21 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // a lane's global operands of one x tile: the nodes it stages (segment
-// positions lane and lane + 64) and, for a 1D stage 2 or 3, u^n at its cell.
-// Every register is written on every path (lanes and rows past the end load a
-// clamped, in-bounds address whose value goes unused): a register that kept
-// its old value would be copied while its previous load may still be in
-// flight, and the copy's wait would stall on the prefetch just issued.
+// positions lane and lane + 64; for a segment that continues the wave's
+// previous one along its line only the 63 new nodes, positions 2G + lane) and,
+// for a 1D stage 2 or 3, u^n at its cell.  Every register is written on every
+// path (lanes and rows past the end load a clamped, in-bounds address whose
+// value goes unused): a register that kept its old value would be copied while
+// its previous load may still be in flight, and the copy's wait would stall on
+// the prefetch just issued.
 template <int NC> struct XPre {
     double U[2][NC];
     double base[NC];
 };
 
 template <int EQ, int MODE, int G>
-__device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int lane, XPre<NodeTraits<EQ>::NC> &pre)
+__device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, bool cont, int lane,
+                                           XPre<NodeTraits<EQ>::NC> &pre)
 {
     constexpr int NC = NodeTraits<EQ>::NC, NN = XW_FACES + 2 * G - 1;
     const int nx = v.nx, sx = c.segx * XW_CELLS;
@@ -599,7 +610,7 @@ __device__ __forceinline__ void x_prefetch(const View<EQ, MODE> &v, XCur c, int 
     const GMEM double *rowp = v.in + (long long)row * v.pitch;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const int i = min(lane + 64 * j, NN - 1);
+        const int i = cont ? min(2 * G + lane, NN - 1) : min(lane + 64 * j, NN - 1);
         const int x = bc_map(sx - G + i, nx, v.bc);
 #pragma unroll
         for (int q = 0; q < NC; ++q) pre.U[j][q] = rowp[q * plane + x];
@@ -657,31 +668,48 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
             v.amax[P.r_zero * AMAX_VALS + tid] = 0ull;
         const int nx = v.nx;
         const long long plane = (long long)v.pitch * v.ny;
-        XCur c = x_cursor(tile, v.t0, v.per_row, wseg);
-        x_prefetch<EQ, MODE, G>(v, c, lane, pre);
-        for (; tile < tend; ++tile) {
+        // the waves take the instance's segments of this chunk in four contiguous
+        // runs, so that a wave's next segment mostly continues its current one
+        // along the grid line and shares its last 2G staged nodes
+        const int T = (int)(tend - tile);
+        XCur c = x_segment((unsigned)(tile - v.t0) * XW_SEGS + (unsigned)(wseg * T), v.per_row);
+        bool cont = false;  // c continues the wave's previous segment
+        x_prefetch<EQ, MODE, G>(v, c, cont, lane, pre);
+        for (int k = 0; k < T; ++k) {
             const bool ok = c.row < v.ny;
             const int sx = c.segx * XW_CELLS;
 
             // stage this tile's nodes (flux, Roe inputs) into LDS
             if (ok) {
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int i = lane + 64 * j;
-                    if (i < NN) {
-                        double q[NQ];
-                        node_quantities<EQ>(pre.U[j], P.gm1, q);
-#pragma unroll
-                        for (int m = 0; m < NQ; ++m) L[m * XW_SEGS * NNP + i] = q[m];
+                if (cont) {
+                    // the previous segment's nodes 63 .. 63 + 2G - 1 are this one's first
+                    for (int t = lane; t < 2 * G * NQ; t += 64) {
+                        const int m = t / (2 * G), i = t - m * (2 * G);
+                        L[m * XW_SEGS * NNP + i] = L[m * XW_SEGS * NNP + XW_CELLS + i];
                     }
+                }
+                // nodes 2G + lane of a continuing segment, else lane and 64 + lane
+                const int p0 = cont ? 2 * G + lane : lane;
+                if (p0 < NN) {
+                    double q[NQ];
+                    node_quantities<EQ>(pre.U[0], P.gm1, q);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) L[m * XW_SEGS * NNP + p0] = q[m];
+                }
+                if (!cont && lane + 64 < NN) {
+                    double q[NQ];
+                    node_quantities<EQ>(pre.U[1], P.gm1, q);
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) L[m * XW_SEGS * NNP + 64 + lane] = q[m];
                 }
             }
             double base[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) base[q] = pre.base[q];
             // issue the next tile's loads before this tile's arithmetic
-            const XCur cn = x_advance(c, v.per_row);
-            if (tile + 1 < tend) x_prefetch<EQ, MODE, G>(v, cn, lane, pre);
+            const XCur cn = x_next(c, v.per_row);
+            const bool cont_n = cn.segx != 0;
+            if (k + 1 < T) x_prefetch<EQ, MODE, G>(v, cn, cont_n, lane, pre);
             wave_sync();
             // top differences of the nodes that start one (faces 0..63 read
             // 0..65), two consecutive nodes per lane
@@ -733,7 +761,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
             }
             wave_sync();
             c = cn;
+            cont = cont_n;
         }
+        tile = tend;
         if (FULL) mx.flush(v.amax, v.ctrl, P.r_out, red);
     }
 }
