@@ -148,6 +148,7 @@ class GpuPoolBackend(Backend):
             E.enoao_pool_set_launch(self.pool, workgroups_per_cu)
         self.max_members = max_members
         self.arena_bytes = E.enoao_pool_usage(self.pool)[1]
+        self.device = torch.cuda.current_device()
         self.copy = torch.cuda.Stream() if overlap else None
         self.stager = ThreadPoolExecutor(1) if overlap else None
 
@@ -167,7 +168,7 @@ class GpuPoolBackend(Backend):
         torch = self.torch
         host = torch.empty(u0.shape, dtype=torch.float64, pin_memory=True)
         host.numpy()[...] = u0
-        with torch.cuda.stream(self.copy):
+        with torch.cuda.device(self.device), torch.cuda.stream(self.copy):
             dev = torch.empty(u0.shape, dtype=torch.float64, device="cuda")
             dev.copy_(host, non_blocking=True)
             ev = torch.cuda.Event()
