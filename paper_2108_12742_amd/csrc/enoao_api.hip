@@ -798,7 +798,8 @@ struct enoao_pool {
         if (u_out) {
             // the padded rows back to the dense layout (for a host result through the
             // member's w1 buffer: the member no longer steps)
-            const int pitch = padded_pitch(p.nx), rows = r.nc * p.ny;
+            const int pitch = padded_pitch(p.nx);
+            const long long rows = (long long)r.nc * p.ny;
             double *mem = (double *)(arena + slots[slot].off);
             const size_t cells = (size_t)r.nc * pitch * p.ny;
             double *dst = u_out_on_host ? member_buffer(mem, cells, 1) : u_out;
@@ -1378,7 +1379,8 @@ enoao_status enoao_pool_admit(enoao_pool *pool, const enoao_problem *prob, const
     hipStream_t s = (hipStream_t)stream;
     // dense rows of the caller into the member's padded rows (a host state goes
     // through the member's w1 buffer, unused until its first step)
-    const int pitch = padded_pitch(prob->nx), rows = r.nc * prob->ny;
+    const int pitch = padded_pitch(prob->nx);
+    const long long rows = (long long)r.nc * prob->ny;
     double *mem = (double *)(pool->arena + off);
     const size_t cells = (size_t)r.nc * pitch * prob->ny;
     const double *src = u0;

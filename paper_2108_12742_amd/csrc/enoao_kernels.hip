@@ -1338,9 +1338,9 @@ __global__ void set_ctrl(Ctrl *c, Ctrl v, double *info)
 }
 
 // copy between a dense and a row-padded layout (pool admission and retirement)
-__global__ void copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows)
+__global__ void copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, long long rows)
 {
-    for (int r = blockIdx.y; r < rows; r += gridDim.y)
+    for (long long r = blockIdx.y; r < rows; r += gridDim.y)
         for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < width; x += gridDim.x * blockDim.x)
             dst[(long long)r * dp + x] = src[(long long)r * sp + x];
 }
@@ -1478,11 +1478,11 @@ hipError_t launch_set_ctrl(Ctrl *c, const Ctrl &v, double *info, hipStream_t s)
     return hipLaunchKernel((const void *)set_ctrl, dim3(1), dim3(64), args, 0, s);
 }
 
-hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows,
-                               hipStream_t s)
+hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width,
+                               long long rows, hipStream_t s)
 {
     if (width <= 0 || rows <= 0) return hipSuccess;
-    const dim3 grid((unsigned)std::min((width + 255) / 256, 64), (unsigned)std::min(rows, 8192));
+    const dim3 grid((unsigned)std::min((width + 255) / 256, 64), (unsigned)std::min(rows, 8192ll));
     void *args[] = {&src, &sp, &dst, &dp, &width, &rows};
     return hipLaunchKernel((const void *)copy_pitched, grid, dim3(256), args, 0, s);
 }

@@ -50,8 +50,8 @@ hipError_t launch_clear_done(const KParams &p, int n_inst, hipStream_t s);
 // info (device, 4 doubles, may be null) receives the old done, status, steps, t
 hipError_t launch_set_ctrl(Ctrl *c, const Ctrl &v, double *info, hipStream_t s);
 // rows of `width` doubles from src (pitch sp) to dst (pitch dp), pitches in doubles
-hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width, int rows,
-                               hipStream_t s);
+hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, long long dp, int width,
+                               long long rows, hipStream_t s);
 // nsteps controlled steps of every member (all 1D, all fitting the LDS), one
 // workgroup per member; lds = dynamic LDS bytes per workgroup
 // block: RES_BLOCK threads per workgroup; n_inst members from p.res_order[p.res_first]

@@ -284,3 +284,50 @@ def test_pipelined_rounds_retire_on_the_step_count():
             u = O.step(op, u, O.cfl_dt(op, u, 0.3))
         np.testing.assert_array_equal(r.result, u)
     assert [r.admitted for r in reqs] == sorted(r.admitted for r in reqs)
+
+
+def test_staging_stays_within_its_byte_budget():
+    """Queued requests are staged in FIFO order while their states total at most
+    stage_bytes (at least one is staged), and admission takes staged uploads only once
+    they have arrived, in order."""
+    clock = Clock()
+
+    class Staging(FakePool):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.staged_bytes = []
+            self.arrived = set()
+
+        def stage(self, problem, u0):
+            self.staged_bytes.append(u0.nbytes)
+            return ("staged", id(u0), u0)
+
+        def ready(self, staged):
+            return staged[1] in self.arrived
+
+        def admit(self, problem, u0, nsteps, cfl):
+            if isinstance(u0, tuple):
+                u0 = u0[2]
+            return super().admit(problem, u0, nsteps, cfl)
+
+    pool = Staging(max_members=2, arena_bytes=1 << 30, clock=clock)
+    reqs_in = [_request(30 + k, 32) for k in range(6)]
+    one = reqs_in[0][1].nbytes
+    srv = S.Server(pool, steps_per_round=1, clock=clock, stage_ahead=64, stage_bytes=2 * one)
+    reqs = [srv.submit(*rq, nsteps=2) for rq in reqs_in]
+    srv._stage()
+    assert pool.staged_bytes == [one, one]          # the budget holds two states
+    srv._stage()
+    assert len(pool.staged_bytes) == 2              # nothing new while both wait
+    srv.admit()
+    # an empty pool takes the first even before its upload arrives; with it running,
+    # the second waits for its own
+    assert reqs[0].slot is not None and reqs[1].slot is None
+    pool.arrived.add(reqs[1].staged[1])
+    srv.admit()
+    assert reqs[1].slot is not None and reqs[2].slot is None  # two slots: full
+    srv._stage()
+    assert len(pool.staged_bytes) == 4              # the admitted ones left the budget
+    srv.drain()
+    assert all(r.status == 0 and r.finished is not None for r in reqs)
+    assert [r.admitted for r in reqs] == sorted(r.admitted for r in reqs)
