@@ -524,7 +524,9 @@ __device__ __forceinline__ View<EQ, MODE> load_view(const KParams &P, int n_inst
 }
 
 // ---------------------------------------------------------------------------
-// x-sweep.  Each wave: one segment of a grid line (64 faces, 63 cells).
+// x-sweep.  Each wave: one segment of a grid line (64 faces, 63 cells) per
+// tile, the wave's segments of a chunk in one contiguous run (a segment that
+// continues the previous one along its line reuses its last 2G staged nodes).
 // Tiles are software-pipelined: the global operands of tile t+1 are loaded into
 // registers while tile t is reconstructed, so the memory latency hides behind
 // the face arithmetic.  Waves per SIMD the register allocation must allow
@@ -550,6 +552,8 @@ struct XCur {
     int row, segx;
 };
 
+// the segment of wave wseg in tile `tile` when the waves take consecutive
+// segments (the maxima kernel's order)
 __device__ __forceinline__ XCur x_cursor(long long tile, long long t0, int per_row, int wseg)
 {
     // (segment counts of an instance fit 32 bits: ny * ceil(nx / 63))
