@@ -247,9 +247,16 @@ enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, in
  *   as enoao_pool_poll reports them; may be NULL), and frees the slot and its
  *   arena space at once.  Later admissions reuse that space; their copies must
  *   be enqueued on the same stream (or ordered after this call's work).
- * A member's result does not depend on the other members of the pool.  Every
- * call that takes a stream enqueues its device work there; calls on one pool
- * are meant to use one stream. */
+ * enoao_pool_set_launch: grid of the pool's persistent sweeps, in workgroups
+ *   per CU (0: the kernels' occupancy; default 16).  The grids are sized once
+ *   for a full arena; each launch shares its tiles among as many of those
+ *   workgroups as give 32 tiles each, and at least as many as the occupancy
+ *   keeps resident, so a pool holding a few small members runs them as a plan
+ *   would, and a full one runs many short chunks that the workgroups finishing
+ *   early take up (members of uneven cost even out).
+ * A member's result does not depend on the other members of the pool or on
+ * the launch shape.  Every call that takes a stream enqueues its device work
+ * there; calls on one pool are meant to use one stream. */
 size_t enoao_pool_member_bytes(const enoao_problem *prob);
 enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, size_t arena_bytes, void *stream,
                                enoao_pool **out);

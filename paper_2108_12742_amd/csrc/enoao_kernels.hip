@@ -33,6 +33,19 @@
 
 namespace enoao {
 
+// Workgroups sharing a persistent launch's tile list of T tiles: the whole
+// grid, or for a pool as many as give P.tiles_per_wg tiles each (at least
+// P.grid_min, at most the grid).  A pool's grid covers the machine several
+// times over; many small chunks let the workgroups that finish early take
+// more of them, which evens out members of uneven cost, while a pool holding
+// few tiles keeps chunks long enough for the y walks' row reuse.
+__device__ __forceinline__ long long chunk_groups(const KParams &P, long long T)
+{
+    const long long g = gridDim.x;
+    if (P.tiles_per_wg <= 0) return g;
+    return min(g, max((long long)P.grid_min, T / P.tiles_per_wg));
+}
+
 __device__ __forceinline__ int bc_map(int k, int n, int bc)
 {
     if (bc == BC_PERIODIC) {
@@ -647,7 +660,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
     const int wseg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->xtiles_total;
-    const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
+    const long long NG = chunk_groups(P, T);
+    if (blockIdx.x >= NG) return;
+    const long long t0 = (long long)blockIdx.x * T / NG, t1 = (long long)(blockIdx.x + 1) * T / NG;
     Maxima<EQ> mx;
     mx.reset();
     XPre<NC> pre;
@@ -909,7 +924,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ORDER == 
     double *WF = fh + wv * NC * (CELLS + 1) * YW;
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->ytiles_total;
-    const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
+    const long long NG = chunk_groups(P, T);
+    if (blockIdx.x >= NG) return;
+    const long long t0 = (long long)blockIdx.x * T / NG, t1 = (long long)(blockIdx.x + 1) * T / NG;
     Maxima<EULER2D> mx;
     mx.reset();
     YPre<G, YW> pre;
@@ -1021,7 +1038,9 @@ __global__ __launch_bounds__(BLOCK) void state_maxima(KParams P)
     const int wseg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_inst = P.hdr->n_inst;
     const long long T = P.hdr->xtiles_total;
-    const long long t0 = (long long)blockIdx.x * T / gridDim.x, t1 = (long long)(blockIdx.x + 1) * T / gridDim.x;
+    const long long NG = chunk_groups(P, T);
+    if (blockIdx.x >= NG) return;
+    const long long t0 = (long long)blockIdx.x * T / NG, t1 = (long long)(blockIdx.x + 1) * T / NG;
     Maxima<EQ> mx;
     mx.reset();
     int cur = -1;

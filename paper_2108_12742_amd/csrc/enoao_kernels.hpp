@@ -28,6 +28,11 @@ struct KParams {
     // size, so the small ones fill the machine behind the large; null: member b)
     const int *res_order;
     int res_first;  // first entry of res_order a resident launch covers
+    // Persistent sweeps of a pool: the grid is sized for a full arena, and the
+    // workgroups that share the tile list are as many as give tiles_per_wg
+    // tiles each, at least grid_min (0: the whole grid shares it).
+    int tiles_per_wg;
+    int grid_min;
 };
 
 // every face takes the full selection (no wave-uniform shortcut); results are

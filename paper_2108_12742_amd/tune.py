@@ -16,7 +16,7 @@ import math
 import os
 import time
 
-CANDIDATES = (0, 1, 2, 3, 4, 6, 8)  # W; 0 = the occupancy the kernels' resources allow
+CANDIDATES = (0, 1, 2, 3, 4, 6, 8, 12, 16)  # W; 0 = the occupancy the kernels' resources allow
 Y_WIDTHS = (8, 4)                    # columns per wave strip of the y tiles (2D only)
 
 

@@ -115,6 +115,40 @@ def test_pool_members_join_and_leave():
     assert E.enoao_pool_usage(pool)[0] == 0
 
 
+def test_pool_launch_shape_and_short_chunks():
+    """A pool's grid covers the machine 16 times (workgroups per CU) and each launch
+    shares its tiles among as many workgroups as give 32 tiles each, at least the
+    occupancy.  24 members of about 512^2 hold more tiles than 32 per resident
+    workgroup in both sweeps, so the short-chunk path runs; at the occupancy
+    (enoao_pool_set_launch 0) every launch shares its tiles among the resident
+    workgroups only.  Both give every member bitwise its solve alone."""
+    torch = PT.torch_cuda()
+    E = _E()
+    sizes = [(512, 512)] * 20 + [(509, 515), (497, 520), (530, 480), (512, 500)]
+    insts = [W.quadrants(k + 1, nx, ny) for k, (nx, ny) in enumerate(sizes)]
+    probs = [E.problem_from_instance(i) for i in insts]
+    arena = sum(E.enoao_pool_member_bytes(p) for p in probs) + (1 << 20)
+    nsteps = 3
+    results = {}
+    for wg in (None, 0):
+        pool = E.enoao_pool_create(probs[0], len(insts), arena)
+        if wg is not None:
+            E.enoao_pool_set_launch(pool, wg)
+        slots = [E.enoao_pool_admit(pool, p, PT.to_dev(torch, i.u0), max_steps=nsteps) for p, i in zip(probs, insts)]
+        assert None not in slots
+        E.enoao_pool_step(pool, nsteps)
+        done, status, steps, _ = E.enoao_pool_poll(pool)
+        for s in slots:
+            assert status[s] == 0 and steps[s] == nsteps
+        results[wg] = [E.enoao_pool_retire(pool, s, shape=i.u0.shape) for s, i in zip(slots, insts)]
+        E.enoao_pool_destroy(pool)
+    for a, b in zip(results[None], results[0]):
+        np.testing.assert_array_equal(a, b)
+    for k in (0, 20, 21, 23):
+        ref, _, _ = _alone(torch, E, insts[k], nsteps)
+        np.testing.assert_array_equal(results[None][k], ref)
+
+
 def test_pool_retire_async_reuses_space_in_stream_order():
     """enoao_pool_retire_async: no host synchronisation between rounds.  Members are
     retired on their own step count right after the step call that finished them, the
