@@ -51,9 +51,10 @@ def _case(kind, n, seed):
     return W.riemann_1d(seed, n)
 
 
+# sizes up to the LDS limit of an Euler member (about 1890 nodes at order 5)
 CASES = [("adv", 1, 5), ("adv", 200, 5), ("adv-left", 513, 7), ("adv", 3000, 5), ("e1", 5, 5), ("e1", 63, 5),
          ("e1", 512, 5), ("e1", 513, 7), ("e1-periodic", 700, 5), ("e1", 1024, 5), ("e1", 1500, 7),
-         ("e1-comp", 900, 5), ("e1-comp", 600, 7)]
+         ("e1", 1700, 5), ("e1", 1800, 5), ("e1-comp", 900, 5), ("e1-comp", 600, 7)]
 
 
 @pytest.mark.parametrize("kind,n,order", CASES, ids=[f"{k}-{n}-ao{o}" for k, n, o in CASES])
