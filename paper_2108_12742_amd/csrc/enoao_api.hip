@@ -442,7 +442,7 @@ struct Runtime {
 
     void drop_graphs()
     {
-        for (auto &g : graphs) hipGraphExecDestroy(g.second);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
     }
 
@@ -499,21 +499,21 @@ struct Runtime {
     {
         wait_marks();
         if (cap) (void)hipStreamSynchronize(cap);
-        for (auto &m : marks) hipEventDestroy(m.second);
+        for (auto &m : marks) (void)hipEventDestroy(m.second);
         marks.clear();
-        for (auto e : ev_pool) hipEventDestroy(e);
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
         for (auto st : res_streams) {
             (void)hipStreamSynchronize(st);
-            hipStreamDestroy(st);
+            (void)hipStreamDestroy(st);
         }
         res_streams.clear();
-        for (auto e : res_events) hipEventDestroy(e);
+        for (auto e : res_events) (void)hipEventDestroy(e);
         res_events.clear();
         drop_graphs();
-        if (cap) hipStreamDestroy(cap);
-        if (h_ctrl) hipHostFree(h_ctrl);
-        if (d_block) hipFree(d_block);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (h_ctrl) (void)hipHostFree(h_ctrl);
+        if (d_block) (void)hipFree(d_block);
         cap = nullptr;
         h_ctrl = nullptr;
         d_block = nullptr;
@@ -596,7 +596,7 @@ struct Runtime {
         if (graph_for(k)) return ENOAO_OK;
         // a bounded cache: the oldest graph goes when a ninth step count comes
         if (graphs.size() >= 8) {
-            hipGraphExecDestroy(graphs.front().second);
+            (void)hipGraphExecDestroy(graphs.front().second);
             graphs.erase(graphs.begin());
         }
         hipGraph_t g = nullptr;
@@ -604,13 +604,13 @@ struct Runtime {
         enoao_status e = steps(k, true, cap);
         const hipError_t ce = hipStreamEndCapture(cap, &g);
         if (e) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return e;
         }
         if (ce != hipSuccess) return ENOAO_EDEVICE;
         hipGraphExec_t exec = nullptr;
         const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (ie != hipSuccess) return ENOAO_EDEVICE;
         graphs.push_back({k, exec});
         return ENOAO_OK;
@@ -806,8 +806,8 @@ struct enoao_pool {
     void free_pins()
     {
         for (int i = 0; i < 2; ++i) {
-            if (ev_pin[i]) hipEventDestroy(ev_pin[i]);
-            if (h_pin[i]) hipHostFree(h_pin[i]);
+            if (ev_pin[i]) (void)hipEventDestroy(ev_pin[i]);
+            if (h_pin[i]) (void)hipHostFree(h_pin[i]);
             ev_pin[i] = nullptr;
             h_pin[i] = nullptr;
         }
