@@ -297,8 +297,9 @@ def test_c2_full_size_solve_step(order):
     """The 2D Euler workload at its full size (2048^2, quadrant data, the benchmark's seed):
     one CFL-controlled SSP-RK3 step through enoao_solve -- the captured graph of stage
     kernels without selection record that the benchmark times, at the default launch
-    shape -- against the oracle's time loop; then the same step at another launch shape
-    (resident workgroups per CU and y strip width) and through the recording kernels,
+    shape -- against the oracle's time loop; then the same step at two other launch
+    shapes (resident workgroups per CU and y strip width; one of them 3 per CU at the
+    order's default width, the benchmark's usual tuned shape) and through the recording kernels,
     bitwise equal; the oracle's step from the same state replays the recorded choices
     at near ties and matches every cell."""
     torch = PT.torch_cuda()
@@ -310,14 +311,16 @@ def test_c2_full_size_solve_step(order):
     u = PT.to_dev(torch, inst.u0)
     t, n = E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=1)
     E.enoao_plan_check(plan)
-    other = E.enoao_plan_create(ep)
-    E.enoao_plan_set_launch(other, 2)
-    E.enoao_plan_set_tiles(other, 4 if order == 5 else 8)
-    u2 = PT.to_dev(torch, inst.u0)
-    E.enoao_solve(other, u2, 1e30, cfl=0.3, max_steps=1)
-    torch.cuda.synchronize()
-    assert torch.equal(u, u2), "launch shape changed the result"
-    del u2
+    # another launch shape, and the one the benchmark's tuner usually picks (3 per CU)
+    for wg, yw in ((2, 4 if order == 5 else 8), (3, 0)):
+        other = E.enoao_plan_create(ep)
+        E.enoao_plan_set_launch(other, wg)
+        E.enoao_plan_set_tiles(other, yw)
+        u2 = PT.to_dev(torch, inst.u0)
+        E.enoao_solve(other, u2, 1e30, cfl=0.3, max_steps=1)
+        torch.cuda.synchronize()
+        assert torch.equal(u, u2), f"launch shape {wg}/{yw} changed the result"
+        del u2, other
     rec_ep = E.problem_from_instance(inst, order=order, record_selection=True)
     rec = E.enoao_plan_create(rec_ep)
     u3 = PT.to_dev(torch, inst.u0)
