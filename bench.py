@@ -292,8 +292,11 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
     u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
     states = [u.clone() for u in u0]
     (best, yw), timing = T.tune_batch(probs, states, steps=3) if tune else ((wg, 8), {})
+    kinds, kinds_info = T.tune_kinds(probs, states, best, yw, steps=3) if tune else (None, None)
     batch = E.enoao_batch_create(probs)
     E.enoao_batch_set_launch(batch, best)
+    if kinds:
+        E.enoao_batch_set_launch_kinds(batch, kinds)
 
     def restart():
         E.enoao_batch_reset(batch)
@@ -333,7 +336,9 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
            "value": value, "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
            "instrumented_ms_per_step": round(el_inst * 1e3 / steps, 4),
            "members_ok": int((status == 0).sum()), "workgroups_per_cu": best,
-           "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()}, "roofline": roof,
+           "workgroups_per_cu_by_kernel": list(kinds) if kinds else None,
+           "tuner_ms_per_step": {str(k): round(v, 4) for k, v in timing.items()}, "tuner_by_kernel": kinds_info,
+           "roofline": roof,
            "step_roofline_hbm": round(R.cell_update_bytes("euler1d") * value / 1e9 / R.PEAK_HBM_GBS, 4)}
     if not plain:
         return out
@@ -637,12 +642,16 @@ def main():
     u0 = torch.from_numpy(inst.u0).cuda()
     u = u0.clone()
     launch, tuner = (args.workgroups_per_cu, args.y_strip_columns or DEFAULT_STRIP_COLUMNS[args.order]), None
+    kinds, kinds_info = None, None
     if not args.no_tune:  # launch shape (workgroups per CU, y strip columns) from the autotuner
         from paper_2108_12742_amd import tune as T
         launch, tuner = T.tune_batch([ep], [u], steps=3)
+        kinds, kinds_info = T.tune_kinds([ep], [u], launch[0], launch[1], steps=3)
     plan = E.enoao_plan_create(ep)
     E.enoao_plan_set_launch(plan, launch[0])
     E.enoao_plan_set_tiles(plan, launch[1])
+    if kinds:
+        E.enoao_plan_set_launch_kinds(plan, kinds)
     el, el_inst, prof = timed_solve(E, plan, u, u0, K, Wu)
 
     cells = n * n
@@ -659,8 +668,10 @@ def main():
                           "ms_per_step": round(el_inst * 1e3 / K, 4)},
         "config": {"workload": workload, "nx": n, "ny": n, "order": args.order,
                    "bc": "periodic", "cfl": 0.3, "seed": W.QUADRANT_BENCH_SEED, "parallelism": "single-gpu",
-                   "workgroups_per_cu": launch[0], "y_strip_columns": launch[1]},
+                   "workgroups_per_cu": launch[0], "y_strip_columns": launch[1],
+                   "workgroups_per_cu_by_kernel": list(kinds) if kinds else None},
         "tuner_ms_per_step": tuner,
+        "tuner_by_kernel": kinds_info,
         "roofline": roof,
         "cpu_baseline": None,
         "kernels": kernels,

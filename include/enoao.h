@@ -297,6 +297,18 @@ enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved);
 enoao_status enoao_plan_set_launch(enoao_plan *plan, int32_t workgroups_per_cu);
 enoao_status enoao_batch_set_launch(enoao_batch *batch, int32_t workgroups_per_cu);
 
+/* Launch shape per kernel kind: workgroups_per_cu[k] (0..64) for kind k of
+ * the stage kernels, k = 0..2 the x-sweep of stage 1..3 and 3..5 the y-sweep
+ * of stage 1..3 (the kinds of enoao_profile_read); 0, or k >= n_kinds, keeps
+ * the object's uniform setting (enoao_plan_set_launch / enoao_batch_set_launch,
+ * which in turn clears these).  The sweeps of one stage can prefer different
+ * shapes (on the 2048^2 2D Euler workload: the x-sweep 6 per CU, the first
+ * y-sweep 2, the others 3).  ENOAO_EINVAL: n_kinds outside 0..6, a NULL array
+ * with n_kinds > 0, or an entry outside 0..64.  The captured graphs are
+ * rebuilt on the next call; results do not depend on the shapes. */
+enoao_status enoao_plan_set_launch_kinds(enoao_plan *plan, const int32_t *workgroups_per_cu, int32_t n_kinds);
+enoao_status enoao_batch_set_launch_kinds(enoao_batch *batch, const int32_t *workgroups_per_cu, int32_t n_kinds);
+
 /* Tile width of the 2D y-sweep: columns per wave strip, 4 or 8 (0 = the
  * default: 8 for order 5, 4 for order 7).  A y tile is 4 strips wide and 64/w cell rows tall; wider
  * strips load longer row segments per wave, narrower ones stage fewer halo

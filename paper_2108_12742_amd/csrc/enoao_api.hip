@@ -124,6 +124,9 @@ struct Runtime {
     // pools: the fewest workgroups that share a tile list (the kernel's occupancy)
     int gmin_x[4] = {0, 0, 0, 0}, gmin_y[4] = {0, 0, 0, 0}, gmin_m = 0;
     int wg_per_cu = 0;  // resident workgroups per CU of the persistent sweeps (0: occupancy)
+    // per kernel kind (x-sweep stages 1..3, y-sweep stages 1..3): workgroups per
+    // CU of that launch (0: wg_per_cu)
+    int wg_kind[6] = {0, 0, 0, 0, 0, 0};
     int yw = 8;  // columns per wave strip of the y-sweep tiles (4 or 8); set from the order at creation
     // every member 1D and small enough for the LDS-resident solver; controlled
     // steps then run there, one launch per LDS size class (below)
@@ -209,9 +212,9 @@ struct Runtime {
     // long at 16 per CU.
     bool dynamic = false;
     static constexpr int POOL_WG_PER_CU = 16, POOL_TILES_PER_WG = 32;
-    int grid_for(long long tiles, int occ) const
+    int grid_for(long long tiles, int occ, int kind_wg = 0) const
     {
-        const int per_cu = wg_per_cu > 0 ? wg_per_cu : occ;
+        const int per_cu = kind_wg > 0 ? kind_wg : wg_per_cu > 0 ? wg_per_cu : occ;
         const long long g = dynamic ? (long long)cus * per_cu : std::min<long long>(tiles, (long long)cus * per_cu);
         return (int)std::max<long long>(g, 1);
     }
@@ -428,11 +431,11 @@ struct Runtime {
         const long long xt = h_hdr.xtiles_total, yt = h_hdr.ytiles_total;
         for (int m = 0; m < 4; ++m) {
             const int ox = occupancy_x(eq, order, m, false, ch);
-            grid_x[m] = grid_for(xt, ox);
+            grid_x[m] = grid_for(xt, ox, m >= 1 ? wg_kind[m - 1] : 0);
             gmin_x[m] = std::min(grid_x[m], cus * ox);
             if (eq == EULER2D) {
                 const int oy = occupancy_y(order, m, false, ch, yw);
-                grid_y[m] = grid_for(yt, oy);
+                grid_y[m] = grid_for(yt, oy, m >= 1 ? wg_kind[2 + m] : 0);
                 gmin_y[m] = std::min(grid_y[m], cus * oy);
             }
         }
@@ -446,10 +449,18 @@ struct Runtime {
         graphs.clear();
     }
 
-    // new launch shape: grids recomputed, the captured graphs dropped
+    // new launch shape: grids recomputed, the captured graphs dropped; a uniform
+    // shape clears the per-kernel ones
     void set_launch(int wg)
     {
         wg_per_cu = wg;
+        for (int &k : wg_kind) k = 0;
+        set_grids();
+        drop_graphs();
+    }
+    void set_launch_kinds(const int32_t *wg, int n)
+    {
+        for (int k = 0; k < 6; ++k) wg_kind[k] = k < n ? wg[k] : 0;
         set_grids();
         drop_graphs();
     }
@@ -876,6 +887,28 @@ enoao_status enoao_set_launch(int32_t workgroups_per_cu, int32_t reserved)
 {
     if (workgroups_per_cu < 0 || workgroups_per_cu > 64 || reserved != 0) return ENOAO_EINVAL;
     g_wg_per_cu = workgroups_per_cu;
+    return ENOAO_OK;
+}
+
+static bool valid_kinds(const int32_t *wg, int32_t n)
+{
+    if (n < 0 || n > 6 || (n > 0 && !wg)) return false;
+    for (int k = 0; k < n; ++k)
+        if (wg[k] < 0 || wg[k] > 64) return false;
+    return true;
+}
+
+enoao_status enoao_plan_set_launch_kinds(enoao_plan *plan, const int32_t *workgroups_per_cu, int32_t n_kinds)
+{
+    if (!plan || !valid_kinds(workgroups_per_cu, n_kinds)) return ENOAO_EINVAL;
+    plan->rt.set_launch_kinds(workgroups_per_cu, n_kinds);
+    return ENOAO_OK;
+}
+
+enoao_status enoao_batch_set_launch_kinds(enoao_batch *batch, const int32_t *workgroups_per_cu, int32_t n_kinds)
+{
+    if (!batch || !valid_kinds(workgroups_per_cu, n_kinds)) return ENOAO_EINVAL;
+    batch->rt.set_launch_kinds(workgroups_per_cu, n_kinds);
     return ENOAO_OK;
 }
 

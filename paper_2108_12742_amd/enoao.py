@@ -113,6 +113,8 @@ def lib():
             "enoao_batch_set_tiles": ([vp, ctypes.c_int32, vp], st),
             "enoao_plan_set_launch": ([vp, ctypes.c_int32], st),
             "enoao_batch_set_launch": ([vp, ctypes.c_int32], st),
+            "enoao_plan_set_launch_kinds": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32], st),
+            "enoao_batch_set_launch_kinds": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32], st),
             "enoao_profile": ([vp, ctypes.c_int32], st),
             "enoao_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.c_int32, vp], st),
@@ -347,6 +349,22 @@ def enoao_plan_set_launch(plan: Plan, workgroups_per_cu: int):
 
 def enoao_batch_set_launch(batch: Batch, workgroups_per_cu: int):
     _check(lib().enoao_batch_set_launch(batch.handle, int(workgroups_per_cu)), "enoao_batch_set_launch")
+
+
+def _kinds(workgroups_per_cu):
+    vals = [int(w) for w in workgroups_per_cu]
+    return (ctypes.c_int32 * max(len(vals), 1))(*vals), len(vals)
+
+
+def enoao_plan_set_launch_kinds(plan: Plan, workgroups_per_cu):
+    """Workgroups per CU per kernel kind (x-sweep stages 1..3, y-sweep stages 1..3; 0 = uniform)."""
+    arr, n = _kinds(workgroups_per_cu)
+    _check(lib().enoao_plan_set_launch_kinds(plan.handle, arr, n), "enoao_plan_set_launch_kinds")
+
+
+def enoao_batch_set_launch_kinds(batch: Batch, workgroups_per_cu):
+    arr, n = _kinds(workgroups_per_cu)
+    _check(lib().enoao_batch_set_launch_kinds(batch.handle, arr, n), "enoao_batch_set_launch_kinds")
 
 
 def enoao_plan_set_tiles(plan: Plan, y_strip_columns: int, stream=None):

@@ -6,8 +6,10 @@ tiles.  In 2D the y-sweep tile width is a second knob: wave strips of 4 or 8
 columns (longer row segments per load against fewer staged halo rows).  The
 tuner times a few steps of the caller's batch for each candidate (W, width)
 and keeps the fastest per (equation, order, size bucket) in a JSON cache
-(ENOAO_TUNE_CACHE, default ~/.cache/enoao_tune.json).  Results do not depend on
-either knob, so tuning never changes answers.
+(ENOAO_TUNE_CACHE, default ~/.cache/enoao_tune.json).  tune_kinds then lets
+each stage kernel take its own W (the per-kernel durations of one profiled run
+per candidate), kept when a whole step beats the uniform shape.  Results do
+not depend on any of these knobs, so tuning never changes answers.
 """
 from __future__ import annotations
 
@@ -110,3 +112,81 @@ def tune_batch(problems, states, steps=4, candidates=CANDIDATES, cfl=0.3, use_ca
     w, yw = (int(x) for x in best.split("/"))
     store(key, {"workgroups_per_cu": w, "y_strip_columns": yw, "ms_per_step": timing})
     return (w, yw), timing
+
+
+KINDS = ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3", "sweep_y_s1", "sweep_y_s2", "sweep_y_s3")
+
+
+def tune_kinds(problems, states, w, yw, steps=4, candidates=CANDIDATES, cfl=0.3, use_cache=True, rounds=2):
+    """Per-kernel launch shapes on top of the uniform (w, yw) from tune_batch: for
+    each candidate W (0 stands for w), profiled runs of `steps` steps give every
+    stage kernel's mean duration (best of `rounds`); each kernel kind takes its
+    fastest W.  Kept only if a whole timed step (best of `rounds`) beats the
+    uniform shape by more than half a percent.  Returns (shapes, info):
+    shapes is a tuple of workgroups per CU per kind (x-sweep stages 1..3, then in
+    2D y-sweep stages 1..3) or None, info has the per-kind durations and both step
+    times (ms)."""
+    import torch
+    from . import enoao as E
+    key = bucket_key(problems) + f"-kinds-w{w}-y{yw}"
+    if use_cache:
+        hit = load_cache().get(key)
+        if hit is not None and "shapes" in hit:
+            return (tuple(hit["shapes"]) if hit["shapes"] else None), hit["info"]
+    nk = 6 if problems[0].equation == E.EULER2D else 3
+    saved = [u.clone() for u in states]
+
+    def restore():
+        for u, s in zip(states, saved):
+            u.copy_(s)
+
+    def make(shape):
+        batch = E.enoao_batch_create(problems)
+        E.enoao_batch_set_launch(batch, w)
+        E.enoao_batch_set_tiles(batch, yw)
+        if shape is not None:
+            E.enoao_batch_set_launch_kinds(batch, shape)
+        return batch
+
+    def timed(shape):
+        batch = make(shape)
+        E.enoao_batch_step(batch, states, steps, cfl)  # graph capture outside the timing
+        best = math.inf
+        for _ in range(max(rounds, 1)):
+            E.enoao_batch_reset(batch)
+            restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            E.enoao_batch_step(batch, states, steps, cfl)
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t0) * 1e3 / max(steps, 1))
+        E.enoao_batch_destroy(batch)
+        restore()
+        return best
+
+    per_kind = {k: {} for k in KINDS[:nk]}
+    for _ in range(max(rounds, 1)):
+        for cand in candidates:
+            batch = make([cand] * nk)
+            E.enoao_batch_step(batch, states, steps, cfl)  # untimed: first launches of this shape
+            E.enoao_batch_reset(batch)
+            restore()
+            E.enoao_batch_profile(batch, True)
+            E.enoao_batch_step(batch, states, steps, cfl)
+            prof = E.enoao_batch_profile_read(batch)
+            E.enoao_batch_destroy(batch)
+            restore()
+            for k in per_kind:
+                ms, n = prof[k]
+                if n > 0:
+                    per_kind[k][cand] = min(per_kind[k].get(cand, ms), ms)
+    shape = tuple(min(per_kind[k], key=per_kind[k].get) if per_kind[k] else 0 for k in KINDS[:nk])
+    uniform_ms = timed(None)
+    kinds_ms = timed(shape) if any(shape) else uniform_ms
+    # kept when some kernel takes another shape and the whole step gains beyond timing noise
+    keep = any(shape) and kinds_ms < 0.995 * uniform_ms
+    info = {"per_kind_ms": {k: {str(c): round(v, 4) for c, v in d.items()} for k, d in per_kind.items()},
+            "uniform_ms_per_step": round(uniform_ms, 4), "kinds_ms_per_step": round(kinds_ms, 4),
+            "shapes": list(shape)}
+    store(key, {"shapes": list(shape) if keep else None, "info": info})
+    return (shape if keep else None), info

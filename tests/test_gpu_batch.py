@@ -68,9 +68,12 @@ def test_batch_2d_members_and_launch_shape():
     insts = [W.quadrants(1, 40, 37), W.quadrants(3, 16, 15), W.quadrants(5, 70, 31), W.quadrants(6, 5, 9)]
     probs = [E.problem_from_instance(i) for i in insts]
     outs = []
-    for wg in (0, 1):
+    # uniform shapes, then a shape per kernel kind (x stages 1..3, y stages 1..3)
+    for wg, kinds in ((0, None), (1, None), (3, (6, 1, 16, 2, 4, 3))):
         batch = E.enoao_batch_create(probs)
         E.enoao_batch_set_launch(batch, wg)
+        if kinds:
+            E.enoao_batch_set_launch_kinds(batch, kinds)
         us = [PT.to_dev(torch, i.u0) for i in insts]
         E.enoao_batch_step(batch, us, 4, 0.3)
         outs.append([u.cpu() for u in us])
@@ -78,6 +81,10 @@ def test_batch_2d_members_and_launch_shape():
         ref, _, _ = _alone(torch, E, inst, 4)
         assert torch.equal(outs[0][k], torch.from_numpy(ref))
         assert torch.equal(outs[1][k], outs[0][k])
+        assert torch.equal(outs[2][k], outs[0][k])
+    for bad in ((1,) * 7, (-1,), (65, 2)):
+        with pytest.raises(E.EnoaoError):
+            E.enoao_batch_set_launch_kinds(batch, bad)
 
 
 def test_pool_members_join_and_leave():
@@ -238,6 +245,21 @@ def test_autotuner_restores_states_and_picks_a_candidate(tmp_path, monkeypatch):
         outs.append([v.cpu() for v in vs])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+    # a shape per kernel kind on top of the uniform one: states restored, and the
+    # shapes (if kept) give the same results
+    kinds, info = T.tune_kinds(probs, us, w, yw, steps=2, candidates=(0, 2, 4))
+    assert set(info["per_kind_ms"]) == set(T.KINDS)
+    assert kinds is None or (len(kinds) == 6 and set(kinds) <= {0, 2, 4})
+    for u, i in zip(us, insts):
+        assert torch.equal(u.cpu(), torch.from_numpy(i.u0))
+    b = E.enoao_batch_create(probs)
+    E.enoao_batch_set_launch(b, w)
+    E.enoao_batch_set_tiles(b, yw)
+    E.enoao_batch_set_launch_kinds(b, info["shapes"])
+    vs = [PT.to_dev(torch, i.u0) for i in insts]
+    E.enoao_batch_step(b, vs, 3, 0.3)
+    for v, a in zip(vs, outs[0]):
+        assert torch.equal(v.cpu(), a)
 
 
 @pytest.mark.slow

@@ -297,11 +297,11 @@ def test_c2_full_size_solve_step(order):
     """The 2D Euler workload at its full size (2048^2, quadrant data, the benchmark's seed):
     one CFL-controlled SSP-RK3 step through enoao_solve -- the captured graph of stage
     kernels without selection record that the benchmark times, at the default launch
-    shape -- against the oracle's time loop; then the same step at two other launch
-    shapes (resident workgroups per CU and y strip width; one of them 3 per CU at the
-    order's default width, the benchmark's usual tuned shape) and through the recording kernels,
-    bitwise equal; the oracle's step from the same state replays the recorded choices
-    at near ties and matches every cell."""
+    shape -- against the oracle's time loop; then the same step at other launch shapes
+    (resident workgroups per CU and y strip width; 3 per CU at the order's default
+    width, the benchmark's usual tuned shape; a shape per kernel kind) and through the
+    recording kernels, bitwise equal; the oracle's step from the same state replays the
+    recorded choices at near ties and matches every cell."""
     torch = PT.torch_cuda()
     E = _E()
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, 2048)
@@ -311,11 +311,14 @@ def test_c2_full_size_solve_step(order):
     u = PT.to_dev(torch, inst.u0)
     t, n = E.enoao_solve(plan, u, 1e30, cfl=0.3, max_steps=1)
     E.enoao_plan_check(plan)
-    # another launch shape, and the one the benchmark's tuner usually picks (3 per CU)
-    for wg, yw in ((2, 4 if order == 5 else 8), (3, 0)):
+    # another launch shape, the one the benchmark's tuner usually picks (3 per CU), and
+    # a shape per kernel kind as the tuner may add to it
+    for wg, yw, kinds in ((2, 4 if order == 5 else 8, None), (3, 0, None), (3, 0, (6, 6, 6, 2, 3, 3))):
         other = E.enoao_plan_create(ep)
         E.enoao_plan_set_launch(other, wg)
         E.enoao_plan_set_tiles(other, yw)
+        if kinds:
+            E.enoao_plan_set_launch_kinds(other, kinds)
         u2 = PT.to_dev(torch, inst.u0)
         E.enoao_solve(other, u2, 1e30, cfl=0.3, max_steps=1)
         torch.cuda.synchronize()
