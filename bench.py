@@ -441,24 +441,37 @@ def bench_resident(steps=100, count=512, n_hi=1700):
     return res
 
 
-def bench_order7(n=2048, steps=30, warmup=2):
-    """The main 2D workload at order 7 (ENO-AO7, Section 3.3's nine candidates), with the
-    default launch shape: throughput, per-kernel mean times and each sweep's roofline."""
+def bench_order7(n=2048, steps=30, warmup=2, tune=True):
+    """The main 2D workload at order 7 (ENO-AO7, Section 3.3's nine candidates), at the
+    autotuner's launch shape (the order's default with tune=False): throughput, per-kernel
+    mean times and each sweep's roofline."""
     import torch
     from paper_2108_12742_amd import enoao as E
     from paper_2108_12742_amd import roofline as R
+    from paper_2108_12742_amd import tune as T
     from paper_2108_12742_amd import workloads as W
     workload = f"euler2d-quadrants-{n}x{n}-ao7"
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
-    plan = E.enoao_plan_create(E.problem_from_instance(inst, order=7))
+    ep = E.problem_from_instance(inst, order=7)
     u0 = torch.from_numpy(inst.u0).cuda()
     u = u0.clone()
+    (wg, yw), kinds = (0, DEFAULT_STRIP_COLUMNS[7]), None
+    if tune:
+        (wg, yw), _ = T.tune_batch([ep], [u], steps=3)
+        kinds, _ = T.tune_kinds([ep], [u], wg, yw, steps=3)
+    plan = E.enoao_plan_create(ep)
+    E.enoao_plan_set_launch(plan, wg)
+    E.enoao_plan_set_tiles(plan, yw)
+    if kinds:
+        E.enoao_plan_set_launch_kinds(plan, kinds)
     el, el_inst, prof = timed_solve(E, plan, u, u0, steps, warmup)
     cells = n * n
-    kernels, best = kernel_table(R, prof, cells, 7, DEFAULT_STRIP_COLUMNS[7], workload)
+    kernels, best = kernel_table(R, prof, cells, 7, yw, workload)
     value = cells * steps / el
     return {"workload": workload, "steps": steps, "value": value,
             "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+            "workgroups_per_cu": wg, "y_strip_columns": yw,
+            "workgroups_per_cu_by_kernel": list(kinds) if kinds else None,
             "instrumented_ms_per_step": round(el_inst * 1e3 / steps, 4), "roofline": kernels[best]["roofline"],
             "step_roofline": step_roofline(R, "euler2d", value, kernels, cells, steps, workload), "kernels": kernels}
 
