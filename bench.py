@@ -292,7 +292,7 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
     u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
     states = [u.clone() for u in u0]
     (best, yw), timing = T.tune_batch(probs, states, steps=3) if tune else ((wg, 8), {})
-    kinds, kinds_info = T.tune_kinds(probs, states, best, yw, steps=3) if tune else (None, None)
+    kinds, kinds_info = T.tune_kinds(probs, states, best, yw) if tune else (None, None)
     batch = E.enoao_batch_create(probs)
     E.enoao_batch_set_launch(batch, best)
     if kinds:
@@ -458,7 +458,7 @@ def bench_order7(n=2048, steps=30, warmup=2, tune=True):
     (wg, yw), kinds = (0, DEFAULT_STRIP_COLUMNS[7]), None
     if tune:
         (wg, yw), _ = T.tune_batch([ep], [u], steps=3)
-        kinds, _ = T.tune_kinds([ep], [u], wg, yw, steps=3)
+        kinds, _ = T.tune_kinds([ep], [u], wg, yw)
     plan = E.enoao_plan_create(ep)
     E.enoao_plan_set_launch(plan, wg)
     E.enoao_plan_set_tiles(plan, yw)
@@ -659,7 +659,7 @@ def main():
     if not args.no_tune:  # launch shape (workgroups per CU, y strip columns) from the autotuner
         from paper_2108_12742_amd import tune as T
         launch, tuner = T.tune_batch([ep], [u], steps=3)
-        kinds, kinds_info = T.tune_kinds([ep], [u], launch[0], launch[1], steps=3)
+        kinds, kinds_info = T.tune_kinds([ep], [u], launch[0], launch[1])
     plan = E.enoao_plan_create(ep)
     E.enoao_plan_set_launch(plan, launch[0])
     E.enoao_plan_set_tiles(plan, launch[1])

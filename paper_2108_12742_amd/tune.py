@@ -7,9 +7,9 @@ columns (longer row segments per load against fewer staged halo rows).  The
 tuner times a few steps of the caller's batch for each candidate (W, width)
 and keeps the fastest per (equation, order, size bucket) in a JSON cache
 (ENOAO_TUNE_CACHE, default ~/.cache/enoao_tune.json).  tune_kinds then lets
-each stage kernel take its own W (the per-kernel durations of one profiled run
-per candidate), kept when a whole step beats the uniform shape.  Results do
-not depend on any of these knobs, so tuning never changes answers.
+each stage kernel take its own W (coordinate descent on whole timed steps),
+kept when a whole step beats the uniform shape.  Results do not depend on any
+of these knobs, so tuning never changes answers.
 """
 from __future__ import annotations
 
@@ -117,15 +117,20 @@ def tune_batch(problems, states, steps=4, candidates=CANDIDATES, cfl=0.3, use_ca
 KINDS = ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3", "sweep_y_s1", "sweep_y_s2", "sweep_y_s3")
 
 
-def tune_kinds(problems, states, w, yw, steps=4, candidates=CANDIDATES, cfl=0.3, use_cache=True, rounds=2):
-    """Per-kernel launch shapes on top of the uniform (w, yw) from tune_batch: for
-    each candidate W (0 stands for w), profiled runs of `steps` steps give every
-    stage kernel's mean duration (best of `rounds`); each kernel kind takes its
-    fastest W.  Kept only if a whole timed step (best of `rounds`) beats the
-    uniform shape by more than half a percent.  Returns (shapes, info):
-    shapes is a tuple of workgroups per CU per kind (x-sweep stages 1..3, then in
-    2D y-sweep stages 1..3) or None, info has the per-kind durations and both step
-    times (ms)."""
+def tune_kinds(problems, states, w, yw, steps=30, candidates=(2, 3, 4, 6), cfl=0.3, use_cache=True, rounds=3):
+    """Per-kernel launch shapes on top of the uniform (w, yw) from tune_batch, by
+    coordinate descent on whole steps: kernel kind by kind (x-sweep stages 1..3,
+    then in 2D y-sweep stages 1..3), each candidate W for that kind is compared
+    with the current shapes on whole captured steps, the two timed in turn (best
+    of `rounds` timings of `steps` steps each: long enough that the launch and the
+    synchronisation around a timing stay below the differences sought, and taken
+    in turn so that drifts of the clock affect both), and kept when it gains more
+    than 0.3%.  The result is kept if it beats the uniform shape by more than
+    0.5% in a last comparison of the same kind.  (The kernels' durations in a
+    profiled run, with events between the launches, did not rank the shapes of the
+    later y-sweeps as a graph replay does.)  Returns (shapes, info): shapes is a
+    tuple of workgroups per CU per kind (0: the uniform w) or None; info has the
+    trials (ms per step, current and candidate) and the last comparison."""
     import torch
     from . import enoao as E
     key = bucket_key(problems) + f"-kinds-w{w}-y{yw}"
@@ -146,47 +151,49 @@ def tune_kinds(problems, states, w, yw, steps=4, candidates=CANDIDATES, cfl=0.3,
         E.enoao_batch_set_tiles(batch, yw)
         if shape is not None:
             E.enoao_batch_set_launch_kinds(batch, shape)
+        E.enoao_batch_step(batch, states, steps, cfl)  # graph capture outside the timings
+        restore()
         return batch
 
-    def timed(shape):
-        batch = make(shape)
-        E.enoao_batch_step(batch, states, steps, cfl)  # graph capture outside the timing
-        best = math.inf
-        for _ in range(max(rounds, 1)):
-            E.enoao_batch_reset(batch)
-            restore()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            E.enoao_batch_step(batch, states, steps, cfl)
-            torch.cuda.synchronize()
-            best = min(best, (time.perf_counter() - t0) * 1e3 / max(steps, 1))
-        E.enoao_batch_destroy(batch)
+    def one(batch):
+        E.enoao_batch_reset(batch)
         restore()
-        return best
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E.enoao_batch_step(batch, states, steps, cfl)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / max(steps, 1)
 
-    per_kind = {k: {} for k in KINDS[:nk]}
-    for _ in range(max(rounds, 1)):
-        for cand in candidates:
-            batch = make([cand] * nk)
-            E.enoao_batch_step(batch, states, steps, cfl)  # untimed: first launches of this shape
-            E.enoao_batch_reset(batch)
-            restore()
-            E.enoao_batch_profile(batch, True)
-            E.enoao_batch_step(batch, states, steps, cfl)
-            prof = E.enoao_batch_profile_read(batch)
-            E.enoao_batch_destroy(batch)
-            restore()
-            for k in per_kind:
-                ms, n = prof[k]
-                if n > 0:
-                    per_kind[k][cand] = min(per_kind[k].get(cand, ms), ms)
-    shape = tuple(min(per_kind[k], key=per_kind[k].get) if per_kind[k] else 0 for k in KINDS[:nk])
-    uniform_ms = timed(None)
-    kinds_ms = timed(shape) if any(shape) else uniform_ms
-    # kept when some kernel takes another shape and the whole step gains beyond timing noise
+    def compare(sa, sb, n):
+        a, b = make(sa), make(sb)
+        ta = tb = math.inf
+        for _ in range(max(n, 1)):
+            ta = min(ta, one(a))
+            tb = min(tb, one(b))
+        E.enoao_batch_destroy(a)
+        E.enoao_batch_destroy(b)
+        restore()
+        return ta, tb
+
+    shape = [0] * nk
+    trials = {}
+    for k in range(nk):
+        for c in candidates:
+            if c == w or c == shape[k]:
+                continue
+            trial = list(shape)
+            trial[k] = c
+            t_cur, t_new = compare(shape, trial, rounds)
+            trials[f"{KINDS[k]}={c}"] = [round(t_cur, 4), round(t_new, 4)]
+            if t_new < 0.997 * t_cur:
+                shape = trial
+    shape = tuple(shape)
+    if any(shape):
+        uniform_ms, kinds_ms = compare(None, shape, rounds + 2)
+    else:
+        uniform_ms = kinds_ms = compare(None, None, 1)[0]
     keep = any(shape) and kinds_ms < 0.995 * uniform_ms
-    info = {"per_kind_ms": {k: {str(c): round(v, 4) for c, v in d.items()} for k, d in per_kind.items()},
-            "uniform_ms_per_step": round(uniform_ms, 4), "kinds_ms_per_step": round(kinds_ms, 4),
-            "shapes": list(shape)}
+    info = {"trials_ms_per_step": trials, "uniform_ms_per_step": round(uniform_ms, 4),
+            "kinds_ms_per_step": round(kinds_ms, 4), "shapes": list(shape)}
     store(key, {"shapes": list(shape) if keep else None, "info": info})
     return (shape if keep else None), info
