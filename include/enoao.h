@@ -211,7 +211,8 @@ enoao_status enoao_batch_reset(enoao_batch *batch, void *stream);
 
 /* Synchronises stream; copies each member's time and step count (either
  * pointer may be NULL) and returns ENOAO_ENONPHYSICAL if a member failed a
- * device-side check (member_status[i] != 0 marks it; may be NULL). */
+ * device-side check (member_status[i] != 0 marks it; may be NULL; bit 1 of it
+ * marks a failed grid barrier of the cooperative solver, see enoao_set_coop). */
 enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, int32_t *member_status,
                                void *stream);
 
@@ -276,10 +277,11 @@ enoao_status enoao_pool_usage(const enoao_pool *pool, size_t *arena_used, size_t
  * eagerly (no graph replay) and record a hipEvent pair around every kernel on
  * the stream the kernel runs on.  enoao_profile_read synchronises stream and
  * returns, per kernel kind, the mean duration in ms and the number of
- * launches since profiling was enabled.  Kinds (n_kinds <= 9):
+ * launches since profiling was enabled.  Kinds (n_kinds <= 10):
  *   0..2 x-sweep of stage 1..3, 3..5 y-sweep of stage 1..3 (2D only),
- *   6 time-step control, 7 initial per-field maxima, 8 LDS-resident solver
- *   (one launch per call: all of its controlled steps). */
+ *   6 time-step control, 7 initial per-field maxima, 8 LDS-resident solver,
+ *   9 cooperative solver (8 and 9: one launch per call, all of its controlled
+ *   steps). */
 enoao_status enoao_profile(enoao_plan *plan, int32_t enable);
 enoao_status enoao_profile_read(enoao_plan *plan, double *avg_ms, int64_t *count, int32_t n_kinds, void *stream);
 enoao_status enoao_batch_profile(enoao_batch *batch, int32_t enable);
@@ -335,6 +337,26 @@ enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, 
  * kernels; other values return ENOAO_EINVAL.  enoao_step (host-given step) and
  * pools always stream. */
 enoao_status enoao_set_resident(int32_t enable);
+
+/* Cooperative solver of one mid-sized 1D problem.  A plan (or a one-member
+ * batch) of a 1D problem whose line has at most one 63-cell segment per wave of
+ * one 4-wave workgroup per CU (about 64K cells on MI355X), and that is too long
+ * for the LDS-resident solver or fits it with more than 9 segments (Euler;
+ * advection: 20; there this path measured faster), runs the time-step-
+ * controlled steps of enoao_solve and enoao_batch_step in one cooperative
+ * launch (hipLaunchCooperativeKernel: every workgroup resident) of many steps:
+ * the stage states stay in the plan's HBM buffers, a grid barrier replaces the
+ * kernel boundary after each stage, and every workgroup takes the same
+ * time-step decision from the maxima the workgroups fold together.  On such a
+ * line a kernel boundary costs about as much as a stage's work.  The
+ * arithmetic is the streaming kernels' (Sections 2 to 4 as above), so results
+ * are bitwise the same.  A barrier wait is bounded (the bound is never meant to
+ * be reached): past it the launch stops stepping, the member's status gets
+ * bit 1 (value 2) and enoao_solve returns ENOAO_EDEVICE.  enable = 1 (default)
+ * allows it for plans and batches used afterwards; 0 leaves such problems to
+ * the resident solver or the streaming kernels; other values return
+ * ENOAO_EINVAL.  Devices without cooperative launches never use it. */
+enoao_status enoao_set_coop(int32_t enable);
 
 /* Wave-uniform shortcut of the face kernels (Section 3.2, first principle):
  * when every face of a wave has the top candidate's indicator within delta on

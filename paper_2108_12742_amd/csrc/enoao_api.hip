@@ -21,10 +21,14 @@ namespace {
 
 int g_wg_per_cu = 0;  // 0: occupancy of each kernel
 int g_resident = 1;   // small 1D members: LDS-resident solver for controlled steps
+int g_coop = 1;       // one mid-sized 1D member: cooperative solver for controlled steps
 int g_shortcut = 1;   // wave-uniform top-candidate shortcut of the face kernels
 
 // kernel kinds of the per-kernel timing (enoao_profile_read order)
-enum { PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_RESIDENT, PROF_KINDS };
+enum {
+    PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_RESIDENT, PROF_COOP,
+    PROF_KINDS
+};
 
 int ncomp_of(int eq) { return eq == ADVECTION ? 1 : eq == EULER1D ? 3 : eq == EULER2D ? 4 : 0; }
 
@@ -140,6 +144,20 @@ struct Runtime {
     std::vector<hipStream_t> res_streams;  // classes after the first run on these, concurrently
     std::vector<hipEvent_t> res_events;    // fork + one join per extra class
     bool use_resident() const { return resident && g_resident != 0; }
+    // one 1D member too long for the resident solver but at most one segment per
+    // wave of one workgroup per CU: the cooperative solver (coop_groups workgroups)
+    bool coop = false;
+    int coop_groups = 0;
+    unsigned *d_bar = nullptr;  // its grid barrier words
+    bool use_coop() const { return coop && g_coop != 0; }
+    // A member that also fits the resident solver takes the cooperative one when
+    // its line has more segments than this: a resident stage takes its segments
+    // four at a time (one per wave), a cooperative one all at once but pays its
+    // barrier and the HBM round trips (measured alone, Euler: 13.4 us per step
+    // resident at 250 nodes, 20 cooperative; 25 against 20 at 630 nodes, 41
+    // against 20 at 1700; advection: 7.8 against 9.9 at 800, 13 against 11 at 1600)
+    int coop_over_resident_segs() const { return eq == ADVECTION ? 20 : 9; }
+    bool coop_first = false;
     int kflags = g_shortcut ? 0 : KF_FULL_SELECTION;  // taken when the plan or batch is created
     // optional per-kernel timing: hipEvents recorded around every launch, on the
     // stream the kernel is launched on (eager launches, no graph)
@@ -260,6 +278,7 @@ struct Runtime {
         const size_t o_ctrl = take(sizeof(Ctrl) * count);
         const size_t o_amax = take(8ull * AMAX_SLOTS * AMAX_VALS * count);
         const size_t o_order = take(sizeof(int) * count);
+        const size_t o_bar = take(2 * sizeof(unsigned));
         std::vector<size_t> o_mem(count);
         for (int i = 0; i < count; ++i) o_mem[i] = take(member_bytes(&ps[i]));
         if (hipMalloc(&d_block, off) != hipSuccess) {
@@ -272,6 +291,7 @@ struct Runtime {
         d_ctrl = (Ctrl *)(base + o_ctrl);
         d_amax = (unsigned long long *)(base + o_amax);
         d_res_order = (int *)(base + o_order);
+        d_bar = (unsigned *)(base + o_bar);
         if (hipHostMalloc((void **)&h_ctrl, sizeof(Ctrl) * count, hipHostMallocDefault) != hipSuccess) {
             h_ctrl = nullptr;
             return ENOAO_ENOMEM;
@@ -316,6 +336,13 @@ struct Runtime {
         set_grids();
         if (eq != EULER2D && !rec) {
             if (enoao_status e = plan_resident(ps, order_h)) return e;
+            if (count == 1) {
+                const int segs = (ps[0].nx + XW_CELLS - 1) / XW_CELLS;
+                const int groups = (segs + RES_BLOCK / 64 - 1) / (RES_BLOCK / 64);
+                coop_groups = groups;
+                coop = groups <= cus && groups <= coop_max_groups(eq, order, ch);
+                coop_first = segs > coop_over_resident_segs();
+            }
         }
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         return ENOAO_OK;
@@ -580,7 +607,14 @@ struct Runtime {
 
     enoao_status steps(int k, bool control, hipStream_t s)
     {
-        if (control && use_resident()) return resident_steps(k, s);
+        if (control && use_resident() && !(use_coop() && coop_first)) return resident_steps(k, s);
+        if (control && use_coop()) {
+            int slot;
+            HIP_TRY(prof_begin(PROF_COOP, s, slot));
+            HIP_TRY(launch_coop(eq, order, ch, coop_groups, params(0, -1, -1), k, h_inst[0].amax, d_bar, s));
+            HIP_TRY(prof_end(slot, s));
+            return ENOAO_OK;
+        }
         for (int i = 0; i < k; ++i) {
             if (control) {
                 int slot;
@@ -638,7 +672,7 @@ struct Runtime {
     // k controlled steps: one graph replay, or eager launches when profiling
     enoao_status run_steps(int k, hipStream_t s)
     {
-        if (profiling || use_resident()) return steps(k, true, s);  // (resident: one launch already)
+        if (profiling || use_resident() || use_coop()) return steps(k, true, s);  // (one launch already)
         if (enoao_status e = ensure_graph(k)) return e;
         HIP_TRY(hipGraphLaunch(graph_for(k), s));
         return ENOAO_OK;
@@ -931,6 +965,13 @@ enoao_status enoao_set_resident(int32_t enable)
     return ENOAO_OK;
 }
 
+enoao_status enoao_set_coop(int32_t enable)
+{
+    if (enable != 0 && enable != 1) return ENOAO_EINVAL;
+    g_coop = enable;
+    return ENOAO_OK;
+}
+
 enoao_status enoao_set_shortcut(int32_t enable)
 {
     if (enable != 0 && enable != 1) return ENOAO_EINVAL;
@@ -1037,7 +1078,7 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
     }
     // the resident solver runs a call's steps in one launch (it stops by itself at
     // t_final): fewer, longer launches
-    if (rt.use_resident()) k = 1024;
+    if (rt.use_resident() || rt.use_coop()) k = 1024;
     if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps);
     k = std::max(k, 1);
     enoao_status st = ENOAO_OK;
@@ -1053,7 +1094,10 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
         if (enoao_status e = rt.read_ctrl(s)) return e;
         const Ctrl &h = rt.h_ctrl[0];
         taken = h.steps;
-        if (h.status) { st = ENOAO_ENONPHYSICAL; break; }
+        if (h.status) {  // bit 1: a grid barrier of the cooperative solver failed (it never should)
+            st = (h.status & 2) ? ENOAO_EDEVICE : ENOAO_ENONPHYSICAL;
+            break;
+        }
         if (h.done || !(h.t < t_final)) break;
     }
     HIP_TRY(rt.mark(s));

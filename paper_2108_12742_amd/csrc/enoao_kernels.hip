@@ -1204,15 +1204,20 @@ __device__ __forceinline__ void resident_wave_maxima(Maxima<EQ> &mx, double *red
     }
 }
 
-template <int EQ, int ORDER, int MODE, bool CH, int NW>
-__device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, int n, const double *in,
-                                               const double *base, double *out, double *wl, double *red, int par,
-                                               double (&cm)[8], Ctrl &C, double dt)
+// One stage over a 1D line for the waves of a resident or cooperative launch:
+// segments first, first + stride, ... (63 cells each).  Each wave stages a
+// segment's node quantities in its own LDS (wl), computes the segment's 64 face
+// fluxes and updates its cells from `in` (and `base`: u^n) into `out`; alpha
+// comes from cm, the maxima of the stage input, and the output's maxima
+// accumulate in mx.
+template <int EQ, int ORDER, int MODE, bool CH>
+__device__ __forceinline__ void line_stage(const KParams &P, const Inst &I, int n, const double *in,
+                                           const double *base, double *out, double *wl, const double (&cm)[8],
+                                           double dt, int first, int stride, Maxima<EQ> &mx)
 {
     using RW = ResWave<EQ, ORDER>;
     constexpr int NC = RW::NC, NQ = RW::NQ, G = RW::G, NN = RW::NN, NNP = RW::NNP;
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double al[NC];
     if constexpr (EQ == ADVECTION) {
         al[0] = fabs(I.adv);
@@ -1227,10 +1232,8 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
     }
     double *q = wl, *fh = wl + NQ * NNP;
     const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
-    Maxima<EQ> mx;
-    mx.reset();
     const int nseg = (n + XW_CELLS - 1) / XW_CELLS;
-    for (int seg = wv; seg < nseg; seg += NW) {
+    for (int seg = first; seg < nseg; seg += stride) {
         const int sx = seg * XW_CELLS;
         // node quantities of nodes sx - G .. sx + 63 + G - 1
 #pragma unroll
@@ -1268,6 +1271,17 @@ __device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, 
         }
         wave_sync();  // the next segment overwrites the staged nodes and fluxes
     }
+}
+
+template <int EQ, int ORDER, int MODE, bool CH, int NW>
+__device__ __forceinline__ void resident_stage(const KParams &P, const Inst &I, int n, const double *in,
+                                               const double *base, double *out, double *wl, double *red, int par,
+                                               double (&cm)[8], Ctrl &C, double dt)
+{
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Maxima<EQ> mx;
+    mx.reset();
+    line_stage<EQ, ORDER, MODE, CH>(P, I, n, in, base, out, wl, cm, dt, wv, NW, mx);
     resident_wave_maxima<EQ, NW>(mx, red, par);
     __syncthreads();  // the stage output and every wave's maxima are complete
     resident_maxima<EQ, NW>(red, par, cm, C);
@@ -1326,6 +1340,153 @@ __global__ __launch_bounds__(64 * NW) void resident_1d(KParams P, int nsteps)
     for (int c = 0; c < NC; ++c)
         for (int j = tid; j < n; j += 64 * NW) ug[c * pitch + j] = un[c * n + j];
     if (tid == 0) *I.ctrl = C;
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative solver of one mid-sized 1D line (too long for one workgroup's
+// LDS, short enough for one segment per wave of at most one workgroup per CU).
+// A kernel boundary between stages costs several microseconds, about a stage's
+// work on such a line; here one cooperative launch (every workgroup resident)
+// runs every controlled step of a call, the stage states in the plan's HBM
+// buffers, with a grid barrier after each stage.  Each wave takes its segments
+// like a wave of the resident solver (line_stage: the same arithmetic, so a
+// result is bitwise the streaming kernels'), each workgroup folds its maxima
+// into the member's three-slot ring with one atomic max per value, and after
+// the barrier every thread reads them and takes the same time-step decision.
+
+constexpr unsigned COOP_SPIN_LIMIT = 1u << 19;  // polls of one barrier wait (about 0.5 s; never reached)
+
+// Grid barrier: bar[0] counts arrivals (monotonic; the n-th barrier waits for
+// n x grid), bar[1] is set when a wait outlasts its bound.  Every thread's
+// stores before it are visible to every thread after it.  Returns false once
+// a wait has failed (then it no longer waits).
+__device__ __forceinline__ bool grid_barrier(GMEM unsigned *bar, unsigned target)
+{
+    __shared__ int ok;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        for (unsigned spin = 0;; ++spin) {
+            if (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                spin >= COOP_SPIN_LIMIT) {
+                __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        ok = good;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+// a workgroup's maxima into slot `slot` of the member: one atomic max per value,
+// the non-physical flag as value 7
+template <int EQ, int NW>
+__device__ __forceinline__ void coop_publish(Maxima<EQ> &mx, double *red, GMEM unsigned long long *am, int slot)
+{
+    resident_wave_maxima<EQ, NW>(mx, red, 0);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < Maxima<EQ>::NV || t == 7) {
+        double x = red[t];
+        for (int w = 1; w < NW; ++w) x = fmax(x, red[w * 8 + t]);
+        __hip_atomic_fetch_max(&am[slot * AMAX_VALS + t], as_bits(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// every thread: the maxima of slot `slot` (after the barrier that completes them)
+template <int EQ>
+__device__ __forceinline__ void coop_read(GMEM unsigned long long *am, int slot, double (&cm)[8], Ctrl &C)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cm[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Maxima<EQ>::NV; ++i)
+        cm[i] = as_double(__hip_atomic_load(&am[slot * AMAX_VALS + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (__hip_atomic_load(&am[slot * AMAX_VALS + 7], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull)
+        C.status |= 1;
+}
+
+template <int EQ, int ORDER, int MODE, bool CH>
+__device__ __forceinline__ bool coop_stage(const KParams &P, const Inst &I, const double *in, const double *base,
+                                           double *out, double *wl, double *red, GMEM unsigned long long *am,
+                                           GMEM unsigned *bar, unsigned &nb, int s, double (&cm)[8], Ctrl &C,
+                                           double dt)
+{
+    constexpr int NW = RES_BLOCK / 64;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int slot = s % 3;  // stage s writes slot s mod 3 and clears the next one
+    if (blockIdx.x == 0 && threadIdx.x < AMAX_VALS) am[((s + 1) % 3) * AMAX_VALS + threadIdx.x] = 0ull;
+    Maxima<EQ> mx;
+    mx.reset();
+    line_stage<EQ, ORDER, MODE, CH>(P, I, I.nx, in, base, out, wl, cm, dt, (int)blockIdx.x * NW + wv,
+                                    (int)gridDim.x * NW, mx);
+    coop_publish<EQ, NW>(mx, red, am, slot);
+    if (!grid_barrier(bar, ++nb * gridDim.x)) return false;
+    coop_read<EQ>(am, slot, cm, C);
+    return true;
+}
+
+// bar: the plan's barrier words; the member's maxima slots and bar are zero at launch
+template <int EQ, int ORDER, bool CH>
+__global__ __launch_bounds__(RES_BLOCK) void coop_1d(KParams P, int nsteps, unsigned *bar_)
+{
+    constexpr int NW = RES_BLOCK / 64, NC = NodeTraits<EQ>::NC;
+    using RW = ResWave<EQ, ORDER>;
+    __shared__ double wls[NW * RW::DOUBLES];
+    __shared__ double red[NW * 8];
+    const Inst &I = P.inst[0];
+    const int n = I.nx, tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double *wl = wls + wv * RW::DOUBLES;
+    // global memory, so that the stage's loads and stores compile to global instructions
+    double *un = (double *)gmem(I.u), *w1 = (double *)gmem(I.w1), *w2 = (double *)gmem(I.w2);
+    GMEM unsigned long long *am = gmem(I.amax);
+    GMEM unsigned *bar = gmem(bar_);
+    Ctrl C = *I.ctrl;
+    unsigned nb = 0;  // barriers passed
+    double cm[8];
+    bool ok;
+    {
+        // maxima of u^n into slot 0
+        const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
+        Maxima<EQ> mx;
+        mx.reset();
+        for (int j = (int)blockIdx.x * RES_BLOCK + tid; j < n; j += (int)gridDim.x * RES_BLOCK) {
+            double U[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) U[c] = un[c * n + j];
+            mx.add(U, P.gamma, idx, idy);
+        }
+        coop_publish<EQ, NW>(mx, red, am, 0);
+        ok = grid_barrier(bar, ++nb * gridDim.x);
+        if (ok) coop_read<EQ>(am, 0, cm, C);
+    }
+    for (int step = 0; ok && step < nsteps; ++step) {
+        if (!control_update<EQ>(C, cm[0], cm[2], cm[6], I.dx, I.adv)) break;  // the same in every thread
+        const double dt = C.dt;
+        ok = coop_stage<EQ, ORDER, M_S1, CH>(P, I, un, un, w1, wl, red, am, bar, nb, 1, cm, C, dt) &&
+             coop_stage<EQ, ORDER, M_S2, CH>(P, I, w1, un, w2, wl, red, am, bar, nb, 2, cm, C, dt) &&
+             coop_stage<EQ, ORDER, M_S3, CH>(P, I, w2, un, un, wl, red, am, bar, nb, 3, cm, C, dt);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        if (!ok) C.status |= 2;
+        *I.ctrl = C;
+    }
+}
+
+// zero the member's maxima slots and the barrier words before a cooperative launch
+__global__ void coop_reset(unsigned long long *amax, unsigned *bar)
+{
+    const int t = threadIdx.x;
+    if (t < AMAX_SLOTS * AMAX_VALS) amax[t] = 0ull;
+    if (t < 2) bar[t] = 0u;
 }
 
 // bind caller pointers into a member's descriptor (kernel arguments are
@@ -1510,6 +1671,8 @@ hipError_t launch_copy_pitched(const double *src, long long sp, double *dst, lon
     return hipLaunchKernel((const void *)copy_pitched, grid, dim3(256), args, 0, s);
 }
 
+using KFn2c = void (*)(KParams, int, unsigned *);
+
 template <int NW> static KFn2 pick_resident_w(int eq, int order, bool ch)
 {
     if (eq == ADVECTION) return order == 7 ? resident_1d<ADVECTION, 7, true, NW> : resident_1d<ADVECTION, 5, true, NW>;
@@ -1530,6 +1693,38 @@ hipError_t launch_resident(int eq, int order, bool ch, int block, const KParams 
     KParams copy = p;
     void *args[] = {&copy, &nsteps};
     return hipLaunchKernel((const void *)fn, dim3(n_inst), dim3(block), args, lds, s);
+}
+
+static KFn2c pick_coop(int eq, int order, bool ch)
+{
+    if (eq == ADVECTION) return order == 7 ? coop_1d<ADVECTION, 7, true> : coop_1d<ADVECTION, 5, true>;
+    if (ch) return order == 7 ? coop_1d<EULER1D, 7, true> : coop_1d<EULER1D, 5, true>;
+    return order == 7 ? coop_1d<EULER1D, 7, false> : coop_1d<EULER1D, 5, false>;
+}
+
+int coop_max_groups(int eq, int order, bool ch)
+{
+    int dev = 0, cus = 0, coop = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick_coop(eq, order, ch), RES_BLOCK, 0) !=
+        hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+hipError_t launch_coop(int eq, int order, bool ch, int groups, const KParams &p, int nsteps,
+                       unsigned long long *amax, unsigned *bar, hipStream_t s)
+{
+    if (eq == EULER2D || groups < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(coop_reset, dim3(1), dim3(64), 0, s, amax, bar);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    KParams copy = p;
+    void *args[] = {&copy, &nsteps, &bar};
+    return hipLaunchCooperativeKernel((const void *)pick_coop(eq, order, ch), dim3(groups), dim3(RES_BLOCK), args, 0,
+                                      s);
 }
 
 size_t resident_lds_limit()

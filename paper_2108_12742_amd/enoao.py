@@ -108,6 +108,7 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int32), vp], st),
             "enoao_set_launch": ([ctypes.c_int32, ctypes.c_int32], st),
             "enoao_set_resident": ([ctypes.c_int32], st),
+            "enoao_set_coop": ([ctypes.c_int32], st),
             "enoao_set_shortcut": ([ctypes.c_int32], st),
             "enoao_plan_set_tiles": ([vp, ctypes.c_int32, vp], st),
             "enoao_batch_set_tiles": ([vp, ctypes.c_int32, vp], st),
@@ -303,7 +304,7 @@ def enoao_batch_query(batch: Batch, stream=None, raise_on_failure=False):
 
 
 PROFILE_KINDS = ("sweep_x_s1", "sweep_x_s2", "sweep_x_s3", "sweep_y_s1", "sweep_y_s2", "sweep_y_s3",
-                 "step_control", "state_maxima", "resident")
+                 "step_control", "state_maxima", "resident", "coop")
 
 
 def enoao_profile(plan: Plan, enable: bool):
@@ -333,6 +334,10 @@ def enoao_batch_profile_read(batch: Batch, stream=None):
 
 def enoao_set_resident(enable: bool):
     _check(lib().enoao_set_resident(1 if enable else 0), "enoao_set_resident")
+
+
+def enoao_set_coop(enable: bool):
+    _check(lib().enoao_set_coop(1 if enable else 0), "enoao_set_coop")
 
 
 def enoao_set_shortcut(enable: bool):

@@ -16,7 +16,10 @@ def _E():
 
 
 def _solve(torch, E, inst, order, resident, t_final=1e300, max_steps=40, cfl=0.3, profile=False):
+    # the resident solver or the streaming kernels, never the cooperative solver
+    # (which a lone member of more than 9 segments would take)
     E.enoao_set_resident(resident)
+    E.enoao_set_coop(False)
     try:
         plan = E.enoao_plan_create(E.problem_from_instance(inst, order=order,
                                                            recon_vars=inst.meta.get("recon", 0)))
@@ -27,6 +30,7 @@ def _solve(torch, E, inst, order, resident, t_final=1e300, max_steps=40, cfl=0.3
         prof = E.enoao_profile_read(plan) if profile else None
     finally:
         E.enoao_set_resident(True)
+        E.enoao_set_coop(True)
     return u.cpu(), t, n, prof
 
 
