@@ -247,34 +247,48 @@ def bench_c0(solves=20, seed=0):
             "cell_updates_per_s": 200 * 400 / float(np.median(lat)), "max_error_after_one_period": err}
 
 
-def bench_c1(seeds=(0, 1, 2, 3), repeats=3):
+def bench_c1(seeds=(0, 1, 2, 3), repeats=3, streaming=True):
     """The 1D Euler workload: N = 2000, seeded Riemann data with the density
-    perturbation, transmissive ends, CFL 0.3, to t = 0.2, one plain solve per seed
-    (device-side CFL loop over captured graphs of 64 steps; N = 2000 is above the
-    LDS-resident solver's limit, so the streaming kernels run); best of `repeats`."""
+    perturbation, transmissive ends, CFL 0.3, to t = 0.2, one plain solve per seed;
+    best of `repeats`.  N = 2000 is above the LDS-resident solver's limit, so the
+    cooperative solver runs (one cooperative launch of up to 1024 controlled steps per
+    enoao_solve call); with streaming=True the same solves on the streaming kernels
+    (device-side CFL loop over captured graphs of 64 steps) are timed beside it."""
     import torch
     from paper_2108_12742_amd import enoao as E
     from paper_2108_12742_amd import workloads as W
-    runs = []
-    for seed in seeds:
-        inst = W.riemann_1d(seed, 2000)
-        plan = E.enoao_plan_create(E.problem_from_instance(inst))
-        u0 = torch.from_numpy(inst.u0).cuda()
-        u = u0.clone()
-        E.enoao_solve(plan, u, 0.2, cfl=0.3)  # warm-up (graph capture)
-        best = None
-        for _ in range(repeats):
-            u.copy_(u0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            t, n = E.enoao_solve(plan, u, 0.2, cfl=0.3)
-            el = time.perf_counter() - t0
-            best = el if best is None else min(best, el)
-        runs.append({"seed": seed, "steps": n, "t_final": t, "seconds": best, "us_per_step": best * 1e6 / n,
-                     "cell_updates_per_s": 2000 * n / best})
-    tot = sum(r["steps"] for r in runs) * 2000
-    return {"workload": "euler1d-riemann-2000-ao5-cfl0.3-t0.2", "runs": runs,
-            "cell_updates_per_s": tot / sum(r["seconds"] for r in runs)}
+
+    def leg():
+        runs = []
+        for seed in seeds:
+            inst = W.riemann_1d(seed, 2000)
+            plan = E.enoao_plan_create(E.problem_from_instance(inst))
+            u0 = torch.from_numpy(inst.u0).cuda()
+            u = u0.clone()
+            E.enoao_solve(plan, u, 0.2, cfl=0.3)  # warm-up (graph capture)
+            best = None
+            for _ in range(repeats):
+                u.copy_(u0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t, n = E.enoao_solve(plan, u, 0.2, cfl=0.3)
+                el = time.perf_counter() - t0
+                best = el if best is None else min(best, el)
+            runs.append({"seed": seed, "steps": n, "t_final": t, "seconds": best, "us_per_step": best * 1e6 / n,
+                         "cell_updates_per_s": 2000 * n / best})
+        return runs, sum(r["steps"] for r in runs) * 2000 / sum(r["seconds"] for r in runs)
+
+    runs, rate = leg()
+    out = {"workload": "euler1d-riemann-2000-ao5-cfl0.3-t0.2", "solver": "cooperative", "runs": runs,
+           "cell_updates_per_s": rate}
+    if streaming:
+        E.enoao_set_coop(False)
+        try:
+            sruns, srate = leg()
+        finally:
+            E.enoao_set_coop(True)
+        out["streaming"] = {"cell_updates_per_s": srate, "us_per_step": [round(r["us_per_step"], 2) for r in sruns]}
+    return out
 
 
 def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
@@ -609,7 +623,7 @@ def main():
                     help="with --no-tune: y-sweep strip width (0 = the order's default)")
     ap.add_argument("--workgroups-per-cu", type=int, default=0,
                     help="with --no-tune: resident workgroups per CU of the persistent sweeps (0 = occupancy)")
-    ap.add_argument("--only-leg", choices=("batched", "batched_small", "served"), default=None,
+    ap.add_argument("--only-leg", choices=("batched", "batched_small", "served", "c1"), default=None,
                     help="run only this extra leg (with --steps, --warmup and --no-tune; no comparison "
                          "against one plan per member) and print its JSON: a short run to profile")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -648,6 +662,9 @@ def main():
         return
     if args.only_leg == "served":  # saturated throughput only (no plain path, no arrival rates)
         print(json.dumps({"served": bench_served(requests=args.served_requests, plain=False)}), flush=True)
+        return
+    if args.only_leg == "c1":  # the 1D Euler N = 2000 solves, cooperative solver only
+        print(json.dumps({"euler1d_c1": bench_c1(repeats=1, streaming=False)}), flush=True)
         return
     n, K, Wu = args.n, args.steps, args.warmup
     inst = W.quadrants(W.QUADRANT_BENCH_SEED, n)
