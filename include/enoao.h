@@ -352,10 +352,13 @@ enoao_status enoao_set_resident(int32_t enable);
  * arithmetic is the streaming kernels' (Sections 2 to 4 as above), so results
  * are bitwise the same.  A barrier wait is bounded (the bound is never meant to
  * be reached): past it the launch stops stepping, the member's status gets
- * bit 1 (value 2) and enoao_solve returns ENOAO_EDEVICE.  enable = 1 (default)
- * allows it for plans and batches used afterwards; 0 leaves such problems to
- * the resident solver or the streaming kernels; other values return
- * ENOAO_EINVAL.  Devices without cooperative launches never use it. */
+ * bit 1 (value 2) and enoao_solve returns ENOAO_EDEVICE.  Cooperative
+ * launches do not overlap one another: callers that solve many such plans at
+ * once on several streams do better on the streaming kernels (512 plans over 8
+ * streams measured 2.6 times faster with it off).  enable = 1 (default) allows
+ * it for plans and batches used afterwards; 0 leaves such problems to the
+ * resident solver or the streaming kernels; other values return ENOAO_EINVAL.
+ * Devices without cooperative launches never use it. */
 enoao_status enoao_set_coop(int32_t enable);
 
 /* Wave-uniform shortcut of the face kernels (Section 3.2, first principle):
