@@ -362,9 +362,13 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
     from concurrent.futures import ThreadPoolExecutor
     plans = [E.enoao_plan_create(p) for p in probs]
     plain = [u.clone() for u in u0]
-    for pl, u, v in zip(plans, plain, u0):  # graph capture and first touch, untimed
-        E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=steps)
-        u.copy_(v)
+    # graph capture and first touch, untimed, for both solvers of a lone 1D member
+    # (the streaming graphs are captured on first use)
+    for coop in (False, True):
+        E.enoao_set_coop(coop)
+        for pl, u, v in zip(plans, plain, u0):
+            E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=steps)
+            u.copy_(v)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for pl, u in zip(plans, plain):

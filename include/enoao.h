@@ -355,7 +355,7 @@ enoao_status enoao_set_resident(int32_t enable);
  * bit 1 (value 2) and enoao_solve returns ENOAO_EDEVICE.  Cooperative
  * launches do not overlap one another: callers that solve many such plans at
  * once on several streams do better on the streaming kernels (512 plans over 8
- * streams measured 2.6 times faster with it off).  enable = 1 (default) allows
+ * streams measured 2.7 times faster with it off).  enable = 1 (default) allows
  * it for plans and batches used afterwards; 0 leaves such problems to the
  * resident solver or the streaming kernels; other values return ENOAO_EINVAL.
  * Devices without cooperative launches never use it. */
