@@ -249,9 +249,9 @@ enoao_status enoao_batch_query(enoao_batch *batch, double *t, int64_t *steps, in
  *   arena space at once.  Later admissions reuse that space; their copies must
  *   be enqueued on the same stream (or ordered after this call's work).
  * enoao_pool_set_launch: grid of the pool's persistent sweeps, in workgroups
- *   per CU (0: the kernels' occupancy; default 16).  The grids are sized once
+ *   per CU (0: the kernels' occupancy; default 24).  The grids are sized once
  *   for a full arena; each launch shares its tiles among as many of those
- *   workgroups as give 32 tiles each, and at least as many as the occupancy
+ *   workgroups as give 16 tiles each, and at least as many as the occupancy
  *   keeps resident, so a pool holding a few small members runs them as a plan
  *   would, and a full one runs many short chunks that the workgroups finishing
  *   early take up (members of uneven cost even out).

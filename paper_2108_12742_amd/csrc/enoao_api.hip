@@ -227,9 +227,10 @@ struct Runtime {
     // as a plan would).  On the served mix of 128^2..1024^2 requests, 16 per CU
     // measured 4.7-5.0e9 cell-updates/s against 3.9-4.1e9 at the occupancy
     // (2-3 per CU); with long chunks only, a lone request's step took twice as
-    // long at 16 per CU.
+    // long at 16 per CU.  24 per CU with 16-tile chunks measured 3% above 16 with
+    // 32 (64-tile chunks: 7% below); a lone request's time is the same at all.
     bool dynamic = false;
-    static constexpr int POOL_WG_PER_CU = 16, POOL_TILES_PER_WG = 32;
+    static constexpr int POOL_WG_PER_CU = 24, POOL_TILES_PER_WG = 16;
     int grid_for(long long tiles, int occ, int kind_wg = 0) const
     {
         const int per_cu = kind_wg > 0 ? kind_wg : wg_per_cu > 0 ? wg_per_cu : occ;

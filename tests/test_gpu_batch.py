@@ -123,9 +123,9 @@ def test_pool_members_join_and_leave():
 
 
 def test_pool_launch_shape_and_short_chunks():
-    """A pool's grid covers the machine 16 times (workgroups per CU) and each launch
-    shares its tiles among as many workgroups as give 32 tiles each, at least the
-    occupancy.  24 members of about 512^2 hold more tiles than 32 per resident
+    """A pool's grid covers the machine 24 times (workgroups per CU) and each launch
+    shares its tiles among as many workgroups as give 16 tiles each, at least the
+    occupancy.  24 members of about 512^2 hold more tiles than 16 per resident
     workgroup in both sweeps, so the short-chunk path runs; at the occupancy
     (enoao_pool_set_launch 0) every launch shares its tiles among the resident
     workgroups only.  Both give every member bitwise its solve alone."""
