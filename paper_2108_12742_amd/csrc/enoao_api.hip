@@ -24,6 +24,15 @@ int g_resident = 1;   // small 1D members: LDS-resident solver for controlled st
 int g_coop = 1;       // one mid-sized 1D member: cooperative solver for controlled steps
 int g_shortcut = 1;   // wave-uniform top-candidate shortcut of the face kernels
 
+// Graph capture: one stream per device, shared by every plan, batch and pool of
+// the process and created on first use, instead of a HIP stream per object (a
+// few hundred plans made a few hundred streams, which the runtime maps onto its
+// few hardware queues next to the caller's).  A capture only records launches;
+// the mutex keeps two of them from using the stream at once.
+constexpr int CAPTURE_MAX_DEVICES = 64;
+std::mutex capture_mutex;
+hipStream_t capture_streams[CAPTURE_MAX_DEVICES] = {};
+
 // kernel kinds of the per-kernel timing (enoao_profile_read order)
 enum {
     PROF_X1 = 0, PROF_X2, PROF_X3, PROF_Y1, PROF_Y2, PROF_Y3, PROF_CONTROL, PROF_MAXIMA, PROF_RESIDENT, PROF_COOP,
@@ -123,7 +132,6 @@ struct Runtime {
     // one event per stream the object's work was enqueued on: destroy waits for
     // them instead of the whole device
     std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
-    hipStream_t cap = nullptr;
     int grid_x[4] = {0, 0, 0, 0}, grid_y[4] = {0, 0, 0, 0}, grid_m = 0;
     // pools: the fewest workgroups that share a tile list (the kernel's occupancy)
     int gmin_x[4] = {0, 0, 0, 0}, gmin_y[4] = {0, 0, 0, 0}, gmin_m = 0;
@@ -345,7 +353,6 @@ struct Runtime {
                 coop_first = segs > coop_over_resident_segs();
             }
         }
-        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         return ENOAO_OK;
     }
 
@@ -537,7 +544,6 @@ struct Runtime {
     void release()
     {
         wait_marks();
-        if (cap) (void)hipStreamSynchronize(cap);
         for (auto &m : marks) (void)hipEventDestroy(m.second);
         marks.clear();
         for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -550,10 +556,8 @@ struct Runtime {
         for (auto e : res_events) (void)hipEventDestroy(e);
         res_events.clear();
         drop_graphs();
-        if (cap) (void)hipStreamDestroy(cap);
         if (h_ctrl) (void)hipHostFree(h_ctrl);
         if (d_block) (void)hipFree(d_block);
-        cap = nullptr;
         h_ctrl = nullptr;
         d_block = nullptr;
     }
@@ -644,6 +648,20 @@ struct Runtime {
         if (graphs.size() >= 8) {
             (void)hipGraphExecDestroy(graphs.front().second);
             graphs.erase(graphs.begin());
+        }
+        if (device < 0 || device >= CAPTURE_MAX_DEVICES) return ENOAO_EDEVICE;
+        std::lock_guard<std::mutex> lock(capture_mutex);
+        hipStream_t &cap = capture_streams[device];
+        if (!cap) {  // on the object's device
+            int cur = 0;
+            HIP_TRY(hipGetDevice(&cur));
+            if (cur != device) HIP_TRY(hipSetDevice(device));
+            const hipError_t ce = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+            if (cur != device) HIP_TRY(hipSetDevice(cur));
+            if (ce != hipSuccess) {
+                cap = nullptr;
+                return ENOAO_EDEVICE;
+            }
         }
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -1439,7 +1457,6 @@ enoao_status enoao_pool_create(const enoao_problem *like, int32_t max_members, s
         return fail(ENOAO_EDEVICE);
     r.wg_per_cu = Runtime::POOL_WG_PER_CU;
     r.set_grids();
-    if (hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking) != hipSuccess) return fail(ENOAO_EDEVICE);
     if (pl->rebuild(s)) return fail(ENOAO_EDEVICE);
     *out = pl;
     return ENOAO_OK;
