@@ -357,9 +357,8 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
     if not plain:
         return out
     # plain: one plan per instance, each solve a call of its own (a solve synchronises
-    # its stream at the end), one after another on one stream, and spread over 8
-    # streams driven by 8 host threads so that solves overlap on the device
-    from concurrent.futures import ThreadPoolExecutor
+    # its stream at the end), one after another on one stream (spread over 8 streams:
+    # bench_plain_8streams, the benchmark's last leg)
     plans = [E.enoao_plan_create(p) for p in probs]
     plain = [u.clone() for u in u0]
     # graph capture and first touch, untimed, for both solvers of a lone 1D member
@@ -376,20 +375,45 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
     torch.cuda.synchronize()
     el_plain = time.perf_counter() - t0
     identical = all(torch.equal(a, b) for a, b in zip(states, plain))
+    out.update({"plain_value": cells * steps / el_plain, "speedup_vs_plain": el_plain / el,
+                "identical_to_plain": identical})
+    return out
+
+
+def bench_plain_8streams(batched, steps=100, count=512):
+    """The plain baseline of the batched workload spread over 8 streams driven by 8
+    host threads, so that solves overlap on the device; updates the `batched` entry.
+    It runs after every other leg: concurrent work from many host threads on many
+    streams left the process's later multi-stream work slower (the LDS-resident
+    batch's size classes, on streams of their own, measured 4.3e9 cell-updates/s
+    after it against 5.7e9 before).  Lone-member plans that would take the
+    cooperative solver run faster here on the streaming kernels (cooperative
+    launches do not overlap one another), so both are timed and the faster is the
+    baseline."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2108_12742_amd import enoao as E
+    from paper_2108_12742_amd import workloads as W
+    insts = W.batch_1d(0, count)
+    probs = [E.problem_from_instance(i) for i in insts]
+    u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
+    cells = sum(int(p.nx) for p in probs)
+    plans = [E.enoao_plan_create(p) for p in probs]
+    plain = [u.clone() for u in u0]
+    for coop in (False, True):  # graph capture and first touch, untimed, for both solvers
+        E.enoao_set_coop(coop)
+        for pl, u, v in zip(plans, plain, u0):
+            E.enoao_solve(pl, u, 1e300, cfl=0.3, max_steps=steps)
+            u.copy_(v)
+    E.enoao_set_coop(True)
     nstreams = 8
     streams = [torch.cuda.Stream() for _ in range(nstreams)]
-    for u, v in zip(plain, u0):
-        u.copy_(v)
-    torch.cuda.synchronize()
 
     def lane(k):
         for i in range(k, len(plans), nstreams):
             E.enoao_solve(plans[i], plain[i], 1e300, cfl=0.3, max_steps=steps, stream=streams[k])
 
-    # over 8 streams the lone-member plans that would take the cooperative solver
-    # run faster on the streaming kernels (cooperative launches do not overlap one
-    # another), so both are timed and the faster is the baseline
-    el8 = {}
+    el8, results = {}, []
     for coop in (True, False):
         E.enoao_set_coop(coop)
         try:
@@ -401,17 +425,15 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
                 list(ex.map(lane, range(nstreams)))
             torch.cuda.synchronize()
             el8["cooperative" if coop else "streaming"] = time.perf_counter() - t0
+            results.append([u.clone() for u in plain])
         finally:
             E.enoao_set_coop(True)
-        identical = identical and all(torch.equal(a, b) for a, b in zip(states, plain))
     best8 = min(el8, key=el8.get)
-    el_plain8 = el8[best8]
-    out.update({"plain_value": cells * steps / el_plain, "speedup_vs_plain": el_plain / el,
-                "plain_8streams_value": cells * steps / el_plain8, "speedup_vs_plain_8streams": el_plain8 / el,
-                "plain_8streams_solver": best8,
-                "plain_8streams_values": {k: cells * steps / v for k, v in el8.items()},
-                "identical_to_plain": identical})
-    return out
+    batched["identical_8streams"] = all(torch.equal(a, b) for a, b in zip(*results))
+    el = batched["ms_per_step"] * 1e-3 * steps
+    batched.update({"plain_8streams_value": cells * steps / el8[best8],
+                    "speedup_vs_plain_8streams": el8[best8] / el, "plain_8streams_solver": best8,
+                    "plain_8streams_values": {k: cells * steps / v for k, v in el8.items()}})
 
 
 def bench_resident(steps=100, count=512, n_hi=1700):
@@ -761,6 +783,8 @@ def main():
         out["discontinuous"] = bench_discontinuous()
         print("[bench] served leg ...", file=sys.stderr, flush=True)
         out["served"] = bench_served(requests=args.served_requests)
+        print("[bench] batched workload's plain solves over 8 streams ...", file=sys.stderr, flush=True)
+        bench_plain_8streams(out["batched"])
     print(json.dumps(out), flush=True)
 
 
