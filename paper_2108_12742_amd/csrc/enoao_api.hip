@@ -149,8 +149,8 @@ struct Runtime {
         size_t lds;        // dynamic LDS bytes per workgroup
     };
     std::vector<ResClass> res_classes;
-    std::vector<hipStream_t> res_streams;  // classes after the first run on these, concurrently
-    std::vector<hipEvent_t> res_events;    // fork + one join per extra class
+    std::vector<hipStream_t> res_streams;  // several classes: one stream each, run concurrently
+    std::vector<hipEvent_t> res_events;    // one join per class, then the fork
     bool use_resident() const { return resident && g_resident != 0; }
     // one 1D member too long for the resident solver but at most one segment per
     // wave of one workgroup per CU: the cooperative solver (coop_groups workgroups)
@@ -397,15 +397,18 @@ struct Runtime {
             res_classes.back().count++;
         }
         resident = !res_classes.empty();
-        for (size_t c = 1; c < res_classes.size(); ++c) {
-            hipStream_t st;
-            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-            res_streams.push_back(st);
-        }
-        for (size_t c = 0; c < res_classes.size(); ++c) {
-            hipEvent_t e;
-            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            res_events.push_back(e);
+        if (res_classes.size() > 1) {
+            for (size_t c = 0; c < res_classes.size(); ++c) {
+                hipStream_t st;
+                HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+                res_streams.push_back(st);
+            }
+            // one event per class, and the fork point last
+            for (size_t c = 0; c <= res_classes.size(); ++c) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                res_events.push_back(e);
+            }
         }
         return ENOAO_OK;
     }
@@ -415,17 +418,22 @@ struct Runtime {
     {
         int slot;
         HIP_TRY(prof_begin(PROF_RESIDENT, s, slot));
-        if (res_classes.size() > 1) HIP_TRY(hipEventRecord(res_events[0], s));
-        for (size_t c = 0; c < res_classes.size(); ++c) {
+        // one class: on the caller's stream; several: every class on a stream of
+        // the object's (made one after another at creation), forked from and joined
+        // into the caller's, so that no class shares the caller's stream
+        const size_t nc = res_classes.size();
+        if (nc > 1) HIP_TRY(hipEventRecord(res_events[nc], s));
+        for (size_t c = 0; c < nc; ++c) {
             const ResClass &rc = res_classes[c];
-            hipStream_t st = c == 0 ? s : res_streams[c - 1];
-            if (c > 0) HIP_TRY(hipStreamWaitEvent(st, res_events[0], 0));
+            hipStream_t st = nc == 1 ? s : res_streams[c];
+            if (nc > 1) HIP_TRY(hipStreamWaitEvent(st, res_events[nc], 0));
             KParams p = params(0, -1, -1);
             p.res_first = rc.first;
             HIP_TRY(launch_resident(eq, order, ch, rc.block, p, rc.count, k, rc.lds, st));
-            if (c > 0) HIP_TRY(hipEventRecord(res_events[c], st));
+            if (nc > 1) HIP_TRY(hipEventRecord(res_events[c], st));
         }
-        for (size_t c = 1; c < res_classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(s, res_events[c], 0));
+        if (nc > 1)
+            for (size_t c = 0; c < nc; ++c) HIP_TRY(hipStreamWaitEvent(s, res_events[c], 0));
         HIP_TRY(prof_end(slot, s));
         return ENOAO_OK;
     }
