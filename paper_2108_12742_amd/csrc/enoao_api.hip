@@ -149,8 +149,8 @@ struct Runtime {
         size_t lds;        // dynamic LDS bytes per workgroup
     };
     std::vector<ResClass> res_classes;
-    std::vector<hipStream_t> res_streams;  // several classes: one stream each, run concurrently
-    std::vector<hipEvent_t> res_events;    // one join per class, then the fork
+    std::vector<hipStream_t> res_streams;  // classes after the first run on these, concurrently
+    std::vector<hipEvent_t> res_events;    // fork + one join per extra class
     bool use_resident() const { return resident && g_resident != 0; }
     // one 1D member too long for the resident solver but at most one segment per
     // wave of one workgroup per CU: the cooperative solver (coop_groups workgroups)
@@ -359,10 +359,13 @@ struct Runtime {
     // LDS size classes of the resident solver.  The dynamic LDS of a launch is the
     // same for all its workgroups, so one launch for all members would give every
     // member the largest one's and hold the CUs at the occupancy of the largest.
-    // Members (largest first) are grouped by how many of their workgroups fit one
-    // CU's LDS (4, 3, 2 or 1); each class is one launch, and the classes run
-    // concurrently on streams of their own (forked from and joined to the
-    // caller's stream).  Workgroups of 4 waves: on the small-member batch 8-wave
+    // Members (largest first) are grouped by how many of their workgroups one CU
+    // holds: as many as fit its LDS (4, 3, 2 or 1), at most as many as the kernel's
+    // registers allow (two for Euler: more LDS classes would not raise occupancy,
+    // only add launches).  Each class is one launch, and the classes run
+    // concurrently on streams of their own (forked from and joined to the caller's
+    // stream): every class needs a hardware queue of its own, since two classes
+    // sharing one run one after the other (HIP spreads streams over few queues).  Workgroups of 4 waves: on the small-member batch 8-wave
     // workgroups (one per CU) for the mid-sized members measured 13% slower.
     enoao_status plan_resident(const enoao_problem *ps, const std::vector<int> &sorted)
     {
@@ -372,10 +375,12 @@ struct Runtime {
         if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) != hipSuccess ||
             per_cu <= 0)
             per_cu = (int)limit;
+        int by_regs = resident_groups_per_cu(eq, order, ch);
+        by_regs = by_regs < 1 ? 4 : by_regs;
         auto cls = [&](long long nx, int &block, size_t &lds) {
             block = RES_BLOCK;
             lds = resident_lds_bytes(nc, nq, g, nx, RES_BLOCK);
-            for (int k = 4; k >= 2; --k)
+            for (int k = by_regs < 4 ? by_regs : 4; k >= 2; --k)
                 if (lds + 1024 <= (size_t)per_cu / k) return k;  // 1 KiB for each workgroup's static LDS
             return lds <= limit ? 1 : 0;
         };
@@ -397,18 +402,15 @@ struct Runtime {
             res_classes.back().count++;
         }
         resident = !res_classes.empty();
-        if (res_classes.size() > 1) {
-            for (size_t c = 0; c < res_classes.size(); ++c) {
-                hipStream_t st;
-                HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-                res_streams.push_back(st);
-            }
-            // one event per class, and the fork point last
-            for (size_t c = 0; c <= res_classes.size(); ++c) {
-                hipEvent_t e;
-                HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-                res_events.push_back(e);
-            }
+        for (size_t c = 1; c < res_classes.size(); ++c) {
+            hipStream_t st;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            res_streams.push_back(st);
+        }
+        for (size_t c = 0; c < res_classes.size(); ++c) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            res_events.push_back(e);
         }
         return ENOAO_OK;
     }
@@ -418,22 +420,17 @@ struct Runtime {
     {
         int slot;
         HIP_TRY(prof_begin(PROF_RESIDENT, s, slot));
-        // one class: on the caller's stream; several: every class on a stream of
-        // the object's (made one after another at creation), forked from and joined
-        // into the caller's, so that no class shares the caller's stream
-        const size_t nc = res_classes.size();
-        if (nc > 1) HIP_TRY(hipEventRecord(res_events[nc], s));
-        for (size_t c = 0; c < nc; ++c) {
+        if (res_classes.size() > 1) HIP_TRY(hipEventRecord(res_events[0], s));
+        for (size_t c = 0; c < res_classes.size(); ++c) {
             const ResClass &rc = res_classes[c];
-            hipStream_t st = nc == 1 ? s : res_streams[c];
-            if (nc > 1) HIP_TRY(hipStreamWaitEvent(st, res_events[nc], 0));
+            hipStream_t st = c == 0 ? s : res_streams[c - 1];
+            if (c > 0) HIP_TRY(hipStreamWaitEvent(st, res_events[0], 0));
             KParams p = params(0, -1, -1);
             p.res_first = rc.first;
             HIP_TRY(launch_resident(eq, order, ch, rc.block, p, rc.count, k, rc.lds, st));
-            if (nc > 1) HIP_TRY(hipEventRecord(res_events[c], st));
+            if (c > 0) HIP_TRY(hipEventRecord(res_events[c], st));
         }
-        if (nc > 1)
-            for (size_t c = 0; c < nc; ++c) HIP_TRY(hipStreamWaitEvent(s, res_events[c], 0));
+        for (size_t c = 1; c < res_classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(s, res_events[c], 0));
         HIP_TRY(prof_end(slot, s));
         return ENOAO_OK;
     }

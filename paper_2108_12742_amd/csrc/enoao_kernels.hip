@@ -1736,6 +1736,16 @@ size_t resident_lds_limit()
     return v > 256 ? (size_t)v - 256 : 0;
 }
 
+int resident_groups_per_cu(int eq, int order, bool ch)
+{
+    int n = 0;
+    if (eq == EULER2D ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)pick_resident(eq, order, ch), RES_BLOCK, 0) !=
+            hipSuccess)
+        return 0;
+    return n;
+}
+
 int occupancy_x(int eq, int order, int mode, bool rec, bool ch) { return occupancy(pick_x(eq, order, mode, rec, ch)); }
 int occupancy_y(int order, int mode, bool rec, bool ch, int yw)
 {

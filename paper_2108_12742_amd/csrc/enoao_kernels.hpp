@@ -64,6 +64,9 @@ hipError_t launch_resident(int eq, int order, bool ch, int block, const KParams 
                            size_t lds, hipStream_t s);
 // largest dynamic LDS a resident workgroup may use on this device (0: none)
 size_t resident_lds_limit();
+// resident workgroups one CU can hold as far as registers and waves allow (LDS
+// aside; 0: unknown)
+int resident_groups_per_cu(int eq, int order, bool ch);
 
 // Cooperative solver of one 1D member (p.inst[0]): nsteps controlled steps in one
 // cooperative launch of `groups` workgroups of RES_BLOCK threads (each wave one
