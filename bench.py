@@ -383,13 +383,11 @@ def bench_batched(steps=100, warmup=2, count=512, tune=True, plain=True, wg=0):
 def bench_plain_8streams(batched, steps=100, count=512):
     """The plain baseline of the batched workload spread over 8 streams driven by 8
     host threads, so that solves overlap on the device; updates the `batched` entry.
-    It runs after every other leg: concurrent work from many host threads on many
-    streams left the process's later multi-stream work slower (the LDS-resident
-    batch's size classes, on streams of their own, measured 4.3e9 cell-updates/s
-    after it against 5.7e9 before).  Lone-member plans that would take the
-    cooperative solver run faster here on the streaming kernels (cooperative
-    launches do not overlap one another), so both are timed and the faster is the
-    baseline."""
+    It runs after every other leg, since its streams (torch's pool) change how the
+    runtime spreads later streams over its hardware queues.  Lone-member plans that
+    would take the cooperative solver run faster here on the streaming kernels
+    (cooperative launches do not overlap one another), so both are timed and the
+    faster is the baseline."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     from paper_2108_12742_amd import enoao as E
