@@ -329,9 +329,10 @@ enoao_status enoao_batch_set_tiles(enoao_batch *batch, int32_t y_strip_columns, 
  * enoao_batch_step) with one 4-wave workgroup per member: the state is read
  * from HBM at the start of a launch, every step and stage runs out of LDS, and
  * the state is written back at its end.  Members are grouped by how many of
- * their workgroups fit one CU's LDS; each group is one launch, and the groups
- * run concurrently on streams the library forks from and joins back into the
- * caller's stream.  The arithmetic is the streaming kernels' (Sections 2 to 4
+ * their workgroups one CU holds (as many as fit its LDS, at most as many as the
+ * kernel's registers allow: two groups at most for Euler 1D); each group is
+ * one launch, and the groups run concurrently on streams the library forks
+ * from and joins back into the caller's stream.  The arithmetic is the streaming kernels' (Sections 2 to 4
  * as above), so results are bitwise the same either way.  enable = 1 (default)
  * allows it for plans and batches used afterwards, 0 forces the streaming
  * kernels; other values return ENOAO_EINVAL.  enoao_step (host-given step) and
@@ -355,7 +356,7 @@ enoao_status enoao_set_resident(int32_t enable);
  * bit 1 (value 2) and enoao_solve returns ENOAO_EDEVICE.  Cooperative
  * launches do not overlap one another: callers that solve many such plans at
  * once on several streams do better on the streaming kernels (512 plans over 8
- * streams measured 2.7 times faster with it off).  enable = 1 (default) allows
+ * streams measured 1.1 to 2.7 times faster with it off).  enable = 1 (default) allows
  * it for plans and batches used afterwards; 0 leaves such problems to the
  * resident solver or the streaming kernels; other values return ENOAO_EINVAL.
  * Devices without cooperative launches never use it. */
