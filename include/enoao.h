@@ -359,7 +359,11 @@ enoao_status enoao_set_resident(int32_t enable);
  * streams measured 1.1 to 2.7 times faster with it off).  enable = 1 (default) allows
  * it for plans and batches used afterwards; 0 leaves such problems to the
  * resident solver or the streaming kernels; other values return ENOAO_EINVAL.
- * Devices without cooperative launches never use it. */
+ * Devices without cooperative launches never use it.  Where the runtime turns
+ * a cooperative launch down (it does in a process started while another
+ * process that has made cooperative launches holds the GPU), the plan or batch
+ * takes the resident solver or the streaming kernels from then on, in the same
+ * call, with the same results. */
 enoao_status enoao_set_coop(int32_t enable);
 
 /* Wave-uniform shortcut of the face kernels (Section 3.2, first principle):

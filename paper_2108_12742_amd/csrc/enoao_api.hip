@@ -194,6 +194,11 @@ struct Runtime {
         if (slot < 0) return hipSuccess;
         return hipEventRecord(ev_pool[slot + 1], s);
     }
+    // drop the pair just begun (its launch did not happen)
+    void prof_cancel(int slot)
+    {
+        if (slot >= 0 && !ev_pairs.empty() && ev_pairs.back().second == slot) ev_pairs.pop_back();
+    }
     // after a synchronisation: fold the recorded pairs into the per-kind totals
     void prof_collect()
     {
@@ -617,14 +622,28 @@ struct Runtime {
 
     enoao_status steps(int k, bool control, hipStream_t s)
     {
-        if (control && use_resident() && !(use_coop() && coop_first)) return resident_steps(k, s);
-        if (control && use_coop()) {
+        if (control && use_coop() && (coop_first || !use_resident())) {
             int slot;
+            bool refused = false;
             HIP_TRY(prof_begin(PROF_COOP, s, slot));
-            HIP_TRY(launch_coop(eq, order, ch, coop_groups, params(0, -1, -1), k, h_inst[0].amax, d_bar, s));
-            HIP_TRY(prof_end(slot, s));
-            return ENOAO_OK;
+            const hipError_t e =
+                launch_coop(eq, order, ch, coop_groups, params(0, -1, -1), k, h_inst[0].amax, d_bar, s, &refused);
+            if (e == hipSuccess) {
+                HIP_TRY(prof_end(slot, s));
+                return ENOAO_OK;
+            }
+            if (!refused) return ENOAO_EDEVICE;
+            // The runtime turned the cooperative launch down (it does while another
+            // process that has made cooperative launches holds the device): clear the
+            // error and leave the object to the other solvers from now on.  The zeroing
+            // already enqueued cleared the maxima ring, so the maxima of the state at
+            // this step boundary are taken again.
+            (void)hipGetLastError();
+            prof_cancel(slot);
+            coop = false;
+            if (enoao_status r = reset_and_maxima(s)) return r;
         }
+        if (control && use_resident()) return resident_steps(k, s);
         for (int i = 0; i < k; ++i) {
             if (control) {
                 int slot;
@@ -1091,23 +1110,27 @@ enoao_status enoao_solve(enoao_plan *plan, double *u, double t_final, double cfl
     if (enoao_status e = rt.reset_and_maxima(s)) return e;
 
     // steps per graph replay: a guess of the total, bounded
-    int k = 16;
-    if (dt_fixed > 0.0) {
-        const double est = std::ceil(t_final / dt_fixed);
-        k = (int)std::min(256.0, std::max(1.0, est));
-    } else {
-        // CFL steps: the end time may come early (the rest of a replay then only
-        // checks its flag), unless the caller bounds the step count
-        k = max_steps > 0 && max_steps <= 256 ? (int)max_steps : 64;
-    }
-    // the resident solver runs a call's steps in one launch (it stops by itself at
-    // t_final): fewer, longer launches
-    if (rt.use_resident() || rt.use_coop()) k = 1024;
-    if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps);
-    k = std::max(k, 1);
+    auto steps_per_launch = [&]() {
+        int k = 16;
+        if (dt_fixed > 0.0) {
+            const double est = std::ceil(t_final / dt_fixed);
+            k = (int)std::min(256.0, std::max(1.0, est));
+        } else {
+            // CFL steps: the end time may come early (the rest of a replay then only
+            // checks its flag), unless the caller bounds the step count
+            k = max_steps > 0 && max_steps <= 256 ? (int)max_steps : 64;
+        }
+        // the resident and cooperative solvers run many steps in one launch (they
+        // stop by themselves at t_final): fewer, longer launches
+        if (rt.use_resident() || rt.use_coop()) k = 1024;
+        if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps);
+        return std::max(k, 1);
+    };
     enoao_status st = ENOAO_OK;
     int64_t taken = 0;  // steps known to be taken (host view)
     while (taken < max_steps) {
+        // (again each time: a refused cooperative launch hands the plan to the others)
+        const int k = steps_per_launch();
         // never enqueue more steps than the budget left: a partial batch runs eagerly
         const int64_t left = max_steps - taken;
         if (left >= k) {

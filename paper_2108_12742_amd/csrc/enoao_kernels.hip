@@ -1715,16 +1715,19 @@ int coop_max_groups(int eq, int order, bool ch)
 }
 
 hipError_t launch_coop(int eq, int order, bool ch, int groups, const KParams &p, int nsteps,
-                       unsigned long long *amax, unsigned *bar, hipStream_t s)
+                       unsigned long long *amax, unsigned *bar, hipStream_t s, bool *refused)
 {
+    *refused = false;
     if (eq == EULER2D || groups < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(coop_reset, dim3(1), dim3(64), 0, s, amax, bar);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     KParams copy = p;
     void *args[] = {&copy, &nsteps, &bar};
-    return hipLaunchCooperativeKernel((const void *)pick_coop(eq, order, ch), dim3(groups), dim3(RES_BLOCK), args, 0,
-                                      s);
+    const hipError_t ce = hipLaunchCooperativeKernel((const void *)pick_coop(eq, order, ch), dim3(groups),
+                                                     dim3(RES_BLOCK), args, 0, s);
+    *refused = ce != hipSuccess;
+    return ce;
 }
 
 size_t resident_lds_limit()

@@ -71,11 +71,13 @@ int resident_groups_per_cu(int eq, int order, bool ch);
 // Cooperative solver of one 1D member (p.inst[0]): nsteps controlled steps in one
 // cooperative launch of `groups` workgroups of RES_BLOCK threads (each wave one
 // or more 63-cell segments per stage), after zeroing the member's maxima slots
-// (amax) and the two barrier words (bar).  coop_max_groups: the most workgroups
-// such a launch can keep resident on this device (0: no cooperative launch).
+// (amax) and the two barrier words (bar).  *refused is set when the runtime
+// turned the cooperative launch itself down (its error is returned; the zeroing
+// has been enqueued).  coop_max_groups: the most workgroups such a launch can
+// keep resident on this device (0: no cooperative launch).
 int coop_max_groups(int eq, int order, bool ch);
 hipError_t launch_coop(int eq, int order, bool ch, int groups, const KParams &p, int nsteps,
-                       unsigned long long *amax, unsigned *bar, hipStream_t s);
+                       unsigned long long *amax, unsigned *bar, hipStream_t s, bool *refused);
 
 // resident workgroups per CU of each kernel (for persistent grid sizes)
 int occupancy_x(int eq, int order, int mode, bool rec, bool ch);

@@ -164,3 +164,50 @@ def test_lone_member_solver_choice(kind, n, solver):
         outs.append((ran, u.cpu()))
     assert [o[0] for o in outs] == [solver, "resident", "stream"]
     assert torch.equal(outs[0][1], outs[2][1]) and torch.equal(outs[1][1], outs[2][1])
+
+
+_CHILD = r'''
+import json, sys
+import numpy as np
+import torch
+from paper_2108_12742_amd import enoao as E
+from paper_2108_12742_amd import workloads as W
+inst = W.riemann_1d(7, 2000)
+out = {}
+for coop in (1, 0):
+    E.enoao_set_coop(coop)
+    plan = E.enoao_plan_create(E.problem_from_instance(inst))
+    E.enoao_profile(plan, True)
+    u = torch.from_numpy(inst.u0).cuda()
+    t, n = E.enoao_solve(plan, u, 1e300, cfl=0.3, max_steps=40)
+    out[coop] = (u.cpu().numpy(), t, n, E.enoao_profile_read(plan)["coop"][1])
+print(json.dumps({"same": bool(np.array_equal(out[1][0], out[0][0])), "t": [out[1][1], out[0][1]],
+                  "n": [out[1][2], out[0][2]], "coop_launches": out[1][3]}), flush=True)
+'''
+
+
+def test_coop_beside_another_process():
+    """A second process on the GPU while this one, which has made cooperative
+    launches, is alive: the runtime may turn the second one's cooperative launch
+    down, and the plan then takes the streaming kernels (no error, the same bits)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    torch = PT.torch_cuda()
+    E = _E()
+    inst = _case("e1", 2000, 3)
+    plan = E.enoao_plan_create(E.problem_from_instance(inst))
+    E.enoao_profile(plan, True)
+    u = PT.to_dev(torch, inst.u0)
+    E.enoao_solve(plan, u, 1e300, cfl=0.3, max_steps=5)
+    assert E.enoao_profile_read(plan)["coop"][1] > 0
+    torch.cuda.synchronize()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    print("cooperative solve in a second process", flush=True)
+    r = subprocess.run([sys.executable, "-c", _CHILD], cwd=root, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    print("second process:", res, flush=True)
+    assert res["same"] and res["n"] == [40, 40] and res["t"][0] == res["t"][1]
+    del plan
