@@ -442,8 +442,8 @@ def run_plain_8streams(steps=100):
     this process touches the GPU.  How HIP spreads torch's pool of streams over its
     few hardware queues depends on the streams a process made before (late in the
     benchmark's process the same solves measured 2.3e8 cell-updates/s against 6.2e8
-    in a process of their own); and a second process beside one that holds the GPU
-    failed its solves with a HIP error."""
+    in a process of their own); and beside a process that has made cooperative
+    launches, the runtime turns a second process's cooperative launches down."""
     import subprocess
     r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--only-leg", "plain8", "--steps", str(steps)],
                        capture_output=True, text=True, timeout=900)
