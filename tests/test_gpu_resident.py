@@ -89,11 +89,19 @@ def test_resident_stops_at_t_final_and_resumes():
     assert torch.equal(ur, us)
 
 
-def test_resident_batch_matches_streaming_batch():
+# member sizes spanning every size class of each kernel (workgroups per CU as the
+# LDS allows, at most as the registers allow: two for Euler, three for advection)
+BATCHES = [("e1", 5, (128, 300, 77, 1000, 5, 640, 1800)), ("e1", 7, (100, 513, 1500, 1000, 20, 900, 1700)),
+           ("e1-comp", 5, (150, 700, 77, 1000, 1700)), ("adv", 5, (200, 1500, 3000, 6000, 64, 900, 4000))]
+
+
+@pytest.mark.parametrize("kind,order,sizes", BATCHES, ids=[f"{k}-ao{o}" for k, o, _ in BATCHES])
+def test_resident_batch_matches_streaming_batch(kind, order, sizes):
     torch = PT.torch_cuda()
     E = _E()
-    insts = [W.riemann_1d(40 + k, n) for k, n in enumerate((128, 300, 77, 1000, 5, 640))]
-    probs = [E.problem_from_instance(i) for i in insts]
+    insts = [_case(kind, n, 40 + k) for k, n in enumerate(sizes)]
+    probs = [E.problem_from_instance(i, order=order, recon_vars=i.meta.get("recon", 0)) for i in insts]
+    print(f"resident batch {kind} order {order} sizes {sizes}", flush=True)
     outs = []
     for resident in (True, False):
         E.enoao_set_resident(resident)
@@ -101,7 +109,7 @@ def test_resident_batch_matches_streaming_batch():
             b = E.enoao_batch_create(probs)
             E.enoao_batch_profile(b, True)
             us = [PT.to_dev(torch, i.u0) for i in insts]
-            tf = [1e300, 0.01, 1e300, 2e-4, 1e300, 1e300]
+            tf = [1e300, 0.01, 1e300, 2e-4] + [1e300] * (len(sizes) - 4)
             E.enoao_batch_step(b, us, 7, 0.3, t_final=tf)
             E.enoao_batch_step(b, us, 5, 0.3, t_final=tf)
             t, steps, status = E.enoao_batch_query(b)
