@@ -181,15 +181,26 @@ for coop in (1, 0):
     u = torch.from_numpy(inst.u0).cuda()
     t, n = E.enoao_solve(plan, u, 1e300, cfl=0.3, max_steps=40)
     out[coop] = (u.cpu().numpy(), t, n, E.enoao_profile_read(plan)["coop"][1])
+    # the same line as a one-member batch (its steps take the same path)
+    b = E.enoao_batch_create([E.problem_from_instance(inst)])
+    ub = [torch.from_numpy(inst.u0).cuda()]
+    E.enoao_batch_step(b, ub, 40, 0.3)
+    tb, nb, sb = E.enoao_batch_query(b)
+    out["batch", coop] = (ub[0].cpu().numpy(), float(tb[0]), int(nb[0]), int(sb[0]))
 print(json.dumps({"same": bool(np.array_equal(out[1][0], out[0][0])), "t": [out[1][1], out[0][1]],
-                  "n": [out[1][2], out[0][2]], "coop_launches": out[1][3]}), flush=True)
+                  "n": [out[1][2], out[0][2]], "coop_launches": out[1][3],
+                  "batch_same": bool(np.array_equal(out["batch", 1][0], out[0][0]) and
+                                     np.array_equal(out["batch", 0][0], out[0][0])),
+                  "batch_n": [out["batch", 1][2], out["batch", 0][2]],
+                  "batch_status": [out["batch", 1][3], out["batch", 0][3]]}), flush=True)
 '''
 
 
 def test_coop_beside_another_process():
     """A second process on the GPU while this one, which has made cooperative
     launches, is alive: the runtime may turn the second one's cooperative launch
-    down, and the plan then takes the streaming kernels (no error, the same bits)."""
+    down, and the plan (or one-member batch) then takes the streaming kernels (no
+    error, the same bits)."""
     import json
     import os
     import subprocess
@@ -210,4 +221,5 @@ def test_coop_beside_another_process():
     res = json.loads(r.stdout.strip().splitlines()[-1])
     print("second process:", res, flush=True)
     assert res["same"] and res["n"] == [40, 40] and res["t"][0] == res["t"][1]
+    assert res["batch_same"] and res["batch_n"] == [40, 40] and res["batch_status"] == [0, 0]
     del plan
