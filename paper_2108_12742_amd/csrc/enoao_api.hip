@@ -370,8 +370,9 @@ struct Runtime {
     // only add launches).  Each class is one launch, and the classes run
     // concurrently on streams of their own (forked from and joined to the caller's
     // stream): every class needs a hardware queue of its own, since two classes
-    // sharing one run one after the other (HIP spreads streams over few queues).  Workgroups of 4 waves: on the small-member batch 8-wave
-    // workgroups (one per CU) for the mid-sized members measured 13% slower.
+    // sharing one run one after the other (HIP spreads streams over few queues).
+    // Workgroups of 4 waves: on the small-member batch 8-wave workgroups (one per
+    // CU) for the mid-sized members measured 13% slower.
     enoao_status plan_resident(const enoao_problem *ps, const std::vector<int> &sorted)
     {
         const int nq = eq == ADVECTION ? 1 : 9, g = order == 5 ? 4 : 5;
