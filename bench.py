@@ -454,12 +454,27 @@ def run_plain_8streams(steps=100):
 
 def add_plain_8streams(batched, res):
     """The `batched` entry against the 8-stream plain baseline (the faster solver)."""
+    if "error" in res or "error" in batched:
+        batched["plain_8streams_error"] = res.get("error", "the batched leg failed")
+        return
     best8 = max(res["values"], key=res["values"].get)
     batched.update({"identical_8streams": res["identical"], "plain_8streams_value": res["values"][best8],
                     "speedup_vs_plain_8streams": batched["value"] / res["values"][best8],
                     "plain_8streams_solver": best8, "plain_8streams_values": res["values"],
                     "plain_8streams_streaming_by_stream_set": res["streaming_by_stream_set"],
                     "plain_8streams_process": "a child process of its own, before the benchmark's"})
+
+
+def run_leg(out, key, fn, *args, **kwargs):
+    """One extra leg into out[key].  An exception is printed and recorded there as
+    {"error": ...}, so that a failing extra leg cannot take the main workload's
+    line with it."""
+    import traceback
+    try:
+        out[key] = fn(*args, **kwargs)
+    except Exception as e:  # every failure of a leg, reported in its entry
+        traceback.print_exc()
+        out[key] = {"error": f"{type(e).__name__}: {e}"}
 
 
 def bench_resident(steps=100, count=512, n_hi=1700):
@@ -719,7 +734,9 @@ def main():
     if not args.no_extras and args.only_leg is None:
         print("[bench] batched workload's plain solves over 8 streams, in a process of their own ...",
               file=sys.stderr, flush=True)
-        plain8 = run_plain_8streams()
+        box = {}
+        run_leg(box, "plain8", run_plain_8streams)
+        plain8 = box["plain8"]
 
     import torch
     from paper_2108_12742_amd import enoao as E
@@ -813,19 +830,19 @@ def main():
     if not args.no_extras:
         print(f"[bench] main workload: {value:.4g} cell-updates/s; smooth advection latency ...", file=sys.stderr,
               flush=True)
-        out["advection_c0"] = bench_c0()
+        run_leg(out, "advection_c0", bench_c0)
         print("[bench] 1D Euler N = 2000 to t = 0.2 ...", file=sys.stderr, flush=True)
-        out["euler1d_c1"] = bench_c1()
+        run_leg(out, "euler1d_c1", bench_c1)
         print("[bench] batched leg ...", file=sys.stderr, flush=True)
-        out["batched"] = bench_batched()
+        run_leg(out, "batched", bench_batched)
         print("[bench] batched leg done; LDS-resident small members ...", file=sys.stderr, flush=True)
-        out["batched_small"] = bench_resident()
+        run_leg(out, "batched_small", bench_resident)
         print("[bench] order 7 ...", file=sys.stderr, flush=True)
-        out["order7"] = bench_order7(n=n)
+        run_leg(out, "order7", bench_order7, n=n)
         print("[bench] discontinuous workloads ...", file=sys.stderr, flush=True)
-        out["discontinuous"] = bench_discontinuous()
+        run_leg(out, "discontinuous", bench_discontinuous)
         print("[bench] served leg ...", file=sys.stderr, flush=True)
-        out["served"] = bench_served(requests=args.served_requests)
+        run_leg(out, "served", bench_served, requests=args.served_requests)
         add_plain_8streams(out["batched"], plain8)
     print(json.dumps(out), flush=True)
 

@@ -36,3 +36,22 @@ def test_algorithmic_bytes():
     assert R.algorithmic_bytes("euler1d", "x", 1) == 48
     e = R.hbm_entry(96 * 4194304, 140.6e-6)
     assert e["bound"] == "hbm" and abs(e["frac"] - 0.358) < 1e-3
+
+
+def test_failing_extra_leg_is_recorded():
+    """An extra leg that raises is reported in its own entry; the others and the main
+    line go on.  A failed 8-stream baseline leaves the batched entry without a speedup."""
+    sys.path.insert(0, ROOT)
+    import bench
+    out = {}
+    bench.run_leg(out, "broken", lambda: 1 / 0)
+    bench.run_leg(out, "fine", lambda k: {"value": k}, k=2)
+    assert out["broken"] == {"error": "ZeroDivisionError: division by zero"} and out["fine"] == {"value": 2}
+    batched = {"value": 1.0e10}
+    bench.add_plain_8streams(batched, {"error": "RuntimeError: child failed"})
+    assert batched["plain_8streams_error"] == "RuntimeError: child failed"
+    assert "speedup_vs_plain_8streams" not in batched
+    ok = {"value": 1.0e10}
+    bench.add_plain_8streams(ok, {"values": {"cooperative": 2.0e8, "streaming": 2.5e8}, "identical": True,
+                                  "streaming_by_stream_set": [2.5e8, 2.2e8]})
+    assert ok["plain_8streams_solver"] == "streaming" and ok["speedup_vs_plain_8streams"] == 40.0
